@@ -1,0 +1,226 @@
+"""Oracle for the symmetry-adapted exact-diagonalization path.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``smoke()`` and by the
+CPU-baseline leg of ``bench.py``, never by the product package.  It shares
+no code with the GPU library; the only module both use is ``workloads``
+(seeded inputs).
+
+Contents:
+  * C core (``oracle.c``): brute-force orbit search, Gosper enumeration,
+    hash-map index, column-by-column product, getRow.
+  * Here: ctypes marshalling, and the Lanczos recurrence in FP64 numpy with
+    the tridiagonal eigenproblem solved by SciPy (a library primitive).
+
+Parity pins of every function live in ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Tuple
+
+import numpy as np
+
+from . import _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+class _Sector(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int32), ("weight", ctypes.c_int32),
+                ("n_elements", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("perm", ctypes.c_void_p), ("flip", ctypes.c_void_p), ("chi", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.library_path()
+        if not os.path.exists(path) or _build.stale():
+            _build.build()
+        L = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        i64, i32, u64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64
+        L.orc_apply.argtypes = [P, ctypes.c_int, u64]
+        L.orc_apply.restype = u64
+        L.orc_state_info.argtypes = [P, i64, P, P, P, P]
+        L.orc_state_info.restype = None
+        L.orc_enumerate.argtypes = [P, P, P, i64]
+        L.orc_enumerate.restype = i64
+        L.orc_index_lookup.argtypes = [P, i64, i64, P, P]
+        L.orc_index_lookup.restype = None
+        L.orc_matvec_columns.argtypes = [P, P, P, i64, P, i32, i32, P, P, i64, i64]
+        L.orc_matvec_columns.restype = i64
+        L.orc_get_row.argtypes = [P, u64, P, i32, P, P, i32]
+        L.orc_get_row.restype = i32
+        _lib = L
+    return _lib
+
+
+class Problem:
+    """A sector (group + characters + weight) and optionally a term table,
+    held in the layouts the C core reads."""
+
+    def __init__(self, sector):
+        g = sector.group
+        self.n_sites = int(sector.n_sites)
+        self.weight = int(sector.weight)
+        self.perm = np.ascontiguousarray(g.perm, dtype=np.uint16)
+        self.flip = np.ascontiguousarray(g.flip, dtype=np.uint8)
+        self.chi = np.ascontiguousarray(g.chi, dtype=np.float64)
+        self.n_elements = int(self.perm.shape[0])
+        self.terms = np.ascontiguousarray(sector.terms) if sector.terms is not None else None
+        self._c = _Sector(self.n_sites, self.weight, self.n_elements, 0,
+                          self.perm.ctypes.data, self.flip.ctypes.data, self.chi.ctypes.data)
+        self.is_real = bool(np.all(self.chi[:, 1] == 0.0) and
+                            (self.terms is None or np.all(self.terms["im"] == 0.0)))
+
+    @property
+    def ptr(self):
+        return ctypes.addressof(self._c)
+
+
+def apply(prob: Problem, g: int, s: int) -> int:
+    return int(lib().orc_apply(prob.ptr, int(g), int(s)))
+
+
+def enumerate_basis(prob: Problem) -> Tuple[np.ndarray, np.ndarray]:
+    """Sorted representatives and their stabilizer sizes."""
+    L = lib()
+    d = int(L.orc_enumerate(prob.ptr, None, None, 0))
+    reps = np.zeros(d, np.uint64)
+    stab = np.zeros(d, np.uint16)
+    d2 = int(L.orc_enumerate(prob.ptr, reps.ctypes.data, stab.ctypes.data, d))
+    assert d2 == d
+    return reps, stab
+
+
+def count_basis(prob: Problem) -> int:
+    return int(lib().orc_enumerate(prob.ptr, None, None, 0))
+
+
+def state_info(prob: Problem, states) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    s = np.ascontiguousarray(states, dtype=np.uint64)
+    n = s.shape[0]
+    reps = np.zeros(n, np.uint64)
+    chi = np.zeros((n, 2), np.float64)
+    norm = np.zeros(n, np.float64)
+    lib().orc_state_info(prob.ptr, n, s.ctypes.data, reps.ctypes.data, chi.ctypes.data,
+                         norm.ctypes.data)
+    return reps, chi[:, 0] + 1j * chi[:, 1], norm
+
+
+def index_lookup(reps: np.ndarray, keys) -> np.ndarray:
+    reps = np.ascontiguousarray(reps, dtype=np.uint64)
+    k = np.ascontiguousarray(keys, dtype=np.uint64)
+    out = np.zeros(k.shape[0], np.int64)
+    lib().orc_index_lookup(reps.ctypes.data, reps.shape[0], k.shape[0], k.ctypes.data,
+                           out.ctypes.data)
+    return out
+
+
+def matvec(prob: Problem, reps, stab, x, columns=None) -> np.ndarray:
+    """y = H x in the symmetry-adapted basis, column by column.
+
+    x: [d] or [d][nrhs], real or complex.  Returns complex unless the problem
+    and x are real.  ``columns`` = (begin, end) restricts the scatter to a
+    column range (for timing samples); the result then holds only those
+    columns' contributions.
+    """
+    reps = np.ascontiguousarray(reps, dtype=np.uint64)
+    stab = np.ascontiguousarray(stab, dtype=np.uint16)
+    d = reps.shape[0]
+    xa = np.asarray(x)
+    squeeze = xa.ndim == 1
+    if d == 0:
+        return np.zeros_like(xa)
+    xc = np.ascontiguousarray(xa.reshape(d, -1), dtype=np.complex128)
+    nrhs = xc.shape[1]
+    y = np.zeros((d, nrhs), np.complex128)
+    b, e = (0, d) if columns is None else columns
+    n = lib().orc_matvec_columns(prob.ptr, reps.ctypes.data, stab.ctypes.data, d,
+                                 prob.terms.ctypes.data, len(prob.terms), nrhs,
+                                 xc.ctypes.data, y.ctypes.data, int(b), int(e))
+    if n < 0:
+        raise RuntimeError("oracle: a neighbour representative in the sector is missing")
+    matvec.last_applied = int(n)
+    if prob.is_real and not np.iscomplexobj(xa):
+        y = y.real.copy()
+    return y[:, 0] if squeeze else y
+
+
+matvec.last_applied = 0
+
+
+def get_row(prob: Problem, r: int, cap: int = 4096):
+    """(representatives, coefficients) of the non-zeros of row r (getRow)."""
+    out_r = np.zeros(cap, np.uint64)
+    out_c = np.zeros((cap, 2), np.float64)
+    n = int(lib().orc_get_row(prob.ptr, int(r), prob.terms.ctypes.data, len(prob.terms),
+                              out_r.ctypes.data, out_c.ctypes.data, cap))
+    if n < 0:
+        raise ValueError("not a representative in the sector")
+    if n > cap:
+        return get_row(prob, r, n)
+    return out_r[:n].copy(), out_c[:n, 0] + 1j * out_c[:n, 1]
+
+
+def dense(prob: Problem, reps, stab) -> np.ndarray:
+    """The sector Hamiltonian as a dense matrix, one column per unit vector."""
+    d = len(reps)
+    return matvec(prob, reps, stab, np.eye(d, dtype=np.complex128))
+
+
+def lanczos(apply_h, v0: np.ndarray, m: int, reorth: bool = True, tol: float = 0.0):
+    """Lanczos three-term recurrence in FP64 with optional full CGS2
+    reorthogonalization; the tridiagonal eigenproblem by SciPy.
+
+    Step k: w = H v_k; alpha_k = Re <v_k, w>; w -= alpha_k v_k + beta_k v_{k-1};
+    (CGS2: twice w -= V (V^H w)); beta_{k+1} = ||w||; v_{k+1} = w / beta_{k+1}.
+    alpha_k is taken before reorthogonalization.  With tol > 0 the loop stops
+    once successive lowest Ritz values differ by less than tol*max(1,|E0|)
+    and beta_{k+1} |s_k| < sqrt(tol)*max(1,|E0|).
+    Returns dict(e0, alpha, beta, resid, iters, converged).
+    """
+    from scipy.linalg import eigh_tridiagonal
+
+    v = np.asarray(v0)
+    v = v / np.sqrt(np.vdot(v, v).real)
+    V = [v]
+    alpha, beta = [], []
+    prev = None
+    e0 = None
+    resid = np.inf
+    converged = False
+    for k in range(m):
+        w = apply_h(V[k])
+        a = float(np.vdot(V[k], w).real)
+        w = w - a * V[k]
+        if k > 0:
+            w = w - beta[k - 1] * V[k - 1]
+        if reorth:
+            Vm = np.stack(V, axis=0)
+            for _ in range(2):
+                h = Vm.conj() @ w
+                w = w - Vm.T @ h
+        b = float(np.sqrt(np.vdot(w, w).real))
+        alpha.append(a)
+        evals, evecs = eigh_tridiagonal(np.array(alpha), np.array(beta),
+                                        select="i", select_range=(0, 0))
+        e0 = float(evals[0])
+        resid = b * abs(evecs[-1, 0])
+        scale = max(1.0, abs(e0))
+        if tol > 0 and prev is not None and abs(e0 - prev) < tol * scale and resid < np.sqrt(tol) * scale:
+            converged = True
+            break
+        prev = e0
+        if k + 1 < m:
+            if b == 0.0:
+                break
+            beta.append(b)
+            V.append(w / b)
+    return dict(e0=e0, alpha=np.array(alpha), beta=np.array(beta), resid=resid,
+                iters=len(alpha), converged=converged)
