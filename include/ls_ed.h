@@ -1,0 +1,211 @@
+/*
+ * ls_ed.h -- symmetry-adapted exact diagonalization on one MI355X (gfx950).
+ *
+ * The problem statement follows Westerhout & Chamberlain, "Implementing
+ * scalable matrix-vector products for the exact diagonalization methods in
+ * quantum many-body physics" (PAW-ATM'23):
+ *   - basis states are N-bit strings; with symmetries a basis index is not
+ *     the bitstring itself (Section 2.1, Fig. 1);
+ *   - U(1) fixes the Hamming weight (Section 2.1);
+ *   - lattice symmetries (translations, reflections, spin inversion) keep one
+ *     representative per orbit (Section 2.1; benchmark symmetries in
+ *     Section 6, "Test Hamiltonians");
+ *   - the product is y_i = sum_j H_ij x_j with matrix elements computed on
+ *     the fly from basis states, and stateToIndex mapping a state to its
+ *     index in the sorted list of representatives (Section 5.3).
+ *
+ * Conventions fixed by this library (the paper leaves them open):
+ *   - bit i of a state is site i; a set bit is an up spin;
+ *   - a group element g = (perm, flip) sends bit i to bit perm[i], then
+ *     inverts all N bits if flip != 0; (g h).s = g.(h.s);
+ *   - the representative of s is the minimum of its orbit {g.s};
+ *   - the sector is the common eigenspace U_g psi = chi(g) psi, i.e. the
+ *     image of P = (1/|G|) sum_g conj(chi(g)) U_g; its basis vectors are
+ *     P|r>/||P|r>|| for representatives r with P|r> != 0.
+ *
+ * Memory: arguments named d_* are device pointers (HBM of the current
+ * device) owned by the caller; work is enqueued on `stream` (a hipStream_t
+ * passed as void*; NULL = the default stream) and is complete when the
+ * stream is.  Descriptors and term tables are host memory, read during the
+ * call only.  Handles are owned by the library, immutable after creation,
+ * and freed with the matching *_destroy.  Calls on different streams may
+ * overlap; a handle may be shared by concurrent calls.
+ *
+ * Errors: every call returns ls_status.  No exception crosses this boundary.
+ * On LS_EINVAL nothing has been enqueued and out-parameters are untouched.
+ * ls_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef LS_ED_H
+#define LS_ED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LS_OK = 0,
+    LS_WNOTCONV = 1,     /* outputs valid, tolerance not reached */
+    LS_EINVAL = -1,      /* invalid argument; nothing enqueued */
+    LS_ENOMEM = -2,      /* device allocation failed */
+    LS_EDEVICE = -3,     /* a HIP runtime call failed */
+    LS_EINTERNAL = -4    /* an internal consistency check failed */
+} ls_status;
+
+typedef struct ls_basis ls_basis;
+typedef struct ls_operator ls_operator;
+
+/* A symmetry sector.
+ *   n_sites         N, 1..64.
+ *   hamming_weight  w in 0..N, or -1 for no U(1) restriction (then N <= 36).
+ *   n_elements      |G|, 1..4096; the elements must form a group (closed
+ *                   under composition, containing the identity, no
+ *                   duplicates).
+ *   perm            host, [n_elements][n_sites] uint16: bijections of sites.
+ *   flip            host, [n_elements] uint8: 1 = also invert all spins;
+ *                   needs 2w = N when w >= 0.
+ *   chi             host, [n_elements][2] double (re, im): a one-dimensional
+ *                   representation, chi(gh) = chi(g) chi(h) within 1e-9.   */
+typedef struct {
+    uint32_t n_sites;
+    int32_t hamming_weight;
+    uint32_t n_elements;
+    const uint16_t *perm;
+    const uint8_t *flip;
+    const double *chi;
+} ls_sector_desc;
+
+/* One elementary term of H (the "sum of bit-flip and diagonal spin terms"):
+ *   c * sum over s with (s & sel_mask) == sel_value of
+ *       (-1)^popcount(s & sign_mask) |s ^ flip><s|,      c = re + i im.
+ * flip == 0 is a diagonal term.  The term list as a whole must be Hermitian
+ * and commute with every group element; with U(1) every off-diagonal term
+ * needs flip subset of sel_mask and must conserve the Hamming weight.      */
+typedef struct {
+    double re, im;
+    uint64_t sel_mask, sel_value;
+    uint64_t flip;
+    uint64_t sign_mask;
+} ls_term;
+
+/* Build the sorted list of representatives of a sector (Section 5.2:
+ * iterate over all candidate bitstrings, keep those that satisfy the
+ * representative condition; here every weight-w bitstring in increasing
+ * order, kept iff it is its orbit's minimum and P does not annihilate it).
+ * The handle owns reps (uint64 [dim], strictly increasing), their
+ * stabilizer sizes and the search layout used by ls_index_lookup.
+ * Blocks until the build on `stream` has finished.
+ * Errors: LS_EINVAL (invalid descriptor: see ls_sector_desc), LS_ENOMEM,
+ * LS_EDEVICE, LS_EINTERNAL (a group-compiler self-check failed).          */
+ls_status ls_basis_build(const ls_sector_desc *desc, void *stream, ls_basis **out);
+
+/* Validates a sector descriptor and compiles its group on the host only (no
+ * device work): the checks of ls_basis_build plus the group compiler's own
+ * self-checks (Benes routing verified on every wire).  Optional outputs
+ * (any may be NULL): the translation layout found, lx * ly = n_sites or
+ * 1 x 1 when the group has no full set of lattice translations; whether
+ * the global spin flip pairs images; the number of coset representatives
+ * walked per orbit search.                                                 */
+ls_status ls_sector_check(const ls_sector_desc *desc, uint32_t *lx, uint32_t *ly, uint32_t *pair_flip,
+                          uint32_t *n_cosets);
+
+/* Dimension, whether vectors are real (all chi real), and the device array
+ * of representatives (borrowed; valid until ls_basis_destroy).  Any output
+ * pointer may be NULL.                                                     */
+ls_status ls_basis_info(const ls_basis *basis, uint64_t *dim, int *is_real,
+                        const uint64_t **d_reps);
+
+/* Copies the representatives (uint64 [dim]) and their stabilizer sizes
+ * (uint16 [dim], the number of group elements fixing each) into caller
+ * buffers on `stream`.  Either destination may be NULL.                   */
+ls_status ls_basis_copy(const ls_basis *basis, uint64_t *d_reps_out, uint16_t *d_stab_out, void *stream);
+
+/* Frees the handle and its device memory (after synchronizing the device). */
+void ls_basis_destroy(ls_basis *basis);
+
+/* Per state: its representative (orbit minimum), the character chi(g*) of
+ * an element g* with g*.s = rep, and norm = sqrt(stab/|G|) with stab the
+ * stabilizer size (the norm of P|rep>).  A state of the wrong Hamming
+ * weight or whose orbit P annihilates gets chi = 0 and norm = 0; a state
+ * with bits at or above N is returned unchanged with chi = norm = 0.
+ *   d_states  device uint64 [n]        (in)
+ *   d_reps    device uint64 [n]        (out)
+ *   d_chi     device double [n][2]     (out, re/im)
+ *   d_norm    device double [n]        (out)
+ * n may be 0.  Errors: LS_EINVAL (NULL handle or NULL pointer with n > 0). */
+ls_status ls_state_info(const ls_basis *basis, uint64_t n, const uint64_t *d_states,
+                        uint64_t *d_reps, double *d_chi, double *d_norm, void *stream);
+
+/* stateToIndex (Section 5.3): position of each representative in the sorted
+ * list, or -1 when the value is not in it (not an error).
+ *   d_keys   device uint64 [n] (in);  d_index  device int64 [n] (out).     */
+ls_status ls_index_lookup(const ls_basis *basis, uint64_t n, const uint64_t *d_keys,
+                          int64_t *d_index, void *stream);
+
+/* Compile a term list into an operator on the basis's sector.  Validates
+ * Hermiticity of the term set, weight conservation (with U(1)) and
+ * invariance of the term set under every group element (after merging
+ * equal terms), else LS_EINVAL.  The operator borrows the basis, which
+ * must outlive it.                                                         */
+ls_status ls_operator_create(const ls_basis *basis, uint32_t n_terms, const ls_term *terms,
+                             ls_operator **out);
+void ls_operator_destroy(ls_operator *op);
+
+/* Whether the operator acts on complex vectors (complex characters or
+ * complex coefficients).                                                   */
+ls_status ls_operator_info(const ls_operator *op, int *is_complex, uint64_t *dim);
+
+/* y = H x (Section 5.3, the first listing's row-by-row ("pull") form: each
+ * row's elements are generated from its representative, looked up, and
+ * accumulated; no atomics, since H is Hermitian).
+ *   nrhs   1..64 right-hand sides.
+ *   d_x    device [dim][nrhs], row-major; double, or complex128 as (re, im)
+ *          pairs when the operator is complex.  (in)
+ *   d_y    same shape, must not overlap d_x.  (out)
+ * Errors: LS_EINVAL (NULL handle or vector, nrhs out of range, x and y
+ * overlapping).  A neighbour whose representative is not in the basis
+ * belongs to an orbit the projector annihilates and contributes zero.     */
+ls_status ls_matvec(const ls_operator *op, uint32_t nrhs, const void *d_x, void *d_y, void *stream);
+
+/* Lanczos ground-state solve on top of ls_matvec.  FP64 throughout, Krylov
+ * vectors resident in HBM, full CGS2 reorthogonalization when reorth = 1,
+ * dot products reduced in a fixed order (deterministic).
+ *   max_iter  Krylov dimension cap (>= 1; clipped to dim).
+ *   tol       0: run exactly max_iter steps.  > 0: stop when successive
+ *             lowest Ritz values differ by < tol*max(1,|E0|) and the residual
+ *             bound beta |s_last| < sqrt(tol)*max(1,|E0|).
+ *   seed      start vector entry i = 2u-1 with u from the counter generator
+ *             of the paper's hash64_01 (value c of stream seed is
+ *             hash64_01(seed + (c+1)*0x9E3779B97F4A7C15), top 53 bits);
+ *             complex entries take counters 2i (re) and 2i+1 (im).
+ *   d_v0      optional device start vector (dim entries, double or complex
+ *             as for ls_matvec); overrides seed when not NULL.
+ * Outputs (host): lowest Ritz value, steps taken, residual bound; alpha and
+ * beta (host arrays of max_iter doubles, may be NULL) receive the
+ * tridiagonal coefficients (beta[k] couples steps k and k+1).
+ * Returns LS_OK, LS_WNOTCONV (tol > 0 not reached), or an error.           */
+typedef struct {
+    uint32_t max_iter;
+    uint32_t reorth;
+    double tol;
+    uint64_t seed;
+    const void *d_v0;
+    double *alpha;
+    double *beta;
+} ls_lanczos_opts;
+
+ls_status ls_lanczos(const ls_operator *op, const ls_lanczos_opts *opts, void *stream,
+                     double *e0, uint32_t *iters, double *resid_bound);
+
+/* Thread-local description of the last non-OK status. */
+const char *ls_last_error(void);
+
+/* Library version string. */
+const char *ls_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LS_ED_H */

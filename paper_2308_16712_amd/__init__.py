@@ -1,0 +1,49 @@
+"""Symmetry-adapted exact diagonalization on one MI355X.
+
+Thin Python face of the C ABI in ``include/ls_ed.h`` (library
+``libls_ed.so``, hand-written HIP for gfx950).  The functions below carry the
+ABI's names and only marshal arguments; device buffers are torch tensors.
+
+    basis = ls_basis_build(sector)            # representatives, search layout
+    reps, chi, norm = ls_state_info(basis, states)
+    idx = ls_index_lookup(basis, keys)
+    op = ls_operator_create(basis, terms)
+    y = ls_matvec(op, x)                      # y = H x, x: [dim] or [dim][nrhs]
+    res = ls_lanczos(op, max_iter=100, tol=1e-10)
+"""
+from __future__ import annotations
+
+from ._lib import (EXPORTS, LIB_PATH, LSError, Basis, Operator, load, sector_check)  # noqa: F401
+
+
+def ls_sector_check(sector) -> dict:
+    """Validate a sector and compile its group on the host only."""
+    g = sector.group
+    return sector_check(sector.n_sites, sector.weight, g.perm, g.flip, g.chi)
+
+
+def ls_basis_build(sector, stream=None) -> Basis:
+    """Build the basis of a sector (an object with n_sites, weight and a
+    group holding perm/flip/chi arrays)."""
+    return Basis.from_sector(sector, stream)
+
+
+def ls_state_info(basis: Basis, states, stream=None):
+    return basis.state_info(states, stream)
+
+
+def ls_index_lookup(basis: Basis, keys, stream=None):
+    return basis.index_lookup(keys, stream)
+
+
+def ls_operator_create(basis: Basis, term_table) -> Operator:
+    return Operator(basis, term_table)
+
+
+def ls_matvec(op: Operator, x, y=None, stream=None):
+    return op.matvec(x, y, stream)
+
+
+def ls_lanczos(op: Operator, max_iter: int, tol: float = 0.0, seed: int = 1, v0=None, reorth: bool = True,
+               stream=None):
+    return op.lanczos(max_iter, tol, seed, v0, reorth, stream)

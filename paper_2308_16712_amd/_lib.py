@@ -1,0 +1,263 @@
+"""ctypes binding of ``libls_ed.so`` (the C ABI declared in include/ls_ed.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Device buffers are torch tensors on the current HIP device; the
+stream is torch's current stream unless one is given.  The binding fails
+loudly when the library has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libls_ed.so")
+
+LS_OK, LS_WNOTCONV, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_EINTERNAL = 0, 1, -1, -2, -3, -4
+_NAMES = {0: "LS_OK", 1: "LS_WNOTCONV", -1: "LS_EINVAL", -2: "LS_ENOMEM", -3: "LS_EDEVICE", -4: "LS_EINTERNAL"}
+
+EXPORTS = ["ls_sector_check", "ls_basis_build", "ls_basis_info", "ls_basis_copy", "ls_basis_destroy", "ls_state_info",
+           "ls_index_lookup", "ls_operator_create", "ls_operator_destroy", "ls_operator_info", "ls_matvec",
+           "ls_lanczos", "ls_last_error", "ls_version"]
+
+
+class LSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SectorDesc(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_uint32), ("hamming_weight", ctypes.c_int32),
+                ("n_elements", ctypes.c_uint32), ("perm", ctypes.c_void_p),
+                ("flip", ctypes.c_void_p), ("chi", ctypes.c_void_p)]
+
+
+class Term(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double), ("sel_mask", ctypes.c_uint64),
+                ("sel_value", ctypes.c_uint64), ("flip", ctypes.c_uint64), ("sign_mask", ctypes.c_uint64)]
+
+
+class LanczosOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_uint32), ("reorth", ctypes.c_uint32), ("tol", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("d_v0", ctypes.c_void_p), ("alpha", ctypes.c_void_p),
+                ("beta", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (no build, no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
+                          " (or python paper_2308_16712_amd/build.py)")
+    L = ctypes.CDLL(path)
+    P, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+    sig = {
+        "ls_sector_check": ([P, P, P, P, P], i32),
+        "ls_basis_build": ([P, P, P], i32),
+        "ls_basis_info": ([P, P, P, P], i32),
+        "ls_basis_copy": ([P, P, P, P], i32),
+        "ls_basis_destroy": ([P], None),
+        "ls_state_info": ([P, u64, P, P, P, P, P], i32),
+        "ls_index_lookup": ([P, u64, P, P, P], i32),
+        "ls_operator_create": ([P, u32, P, P], i32),
+        "ls_operator_destroy": ([P], None),
+        "ls_operator_info": ([P, P, P], i32),
+        "ls_matvec": ([P, u32, P, P, P], i32),
+        "ls_lanczos": ([P, P, P, P, P, P], i32),
+        "ls_last_error": ([], ctypes.c_char_p),
+        "ls_version": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(status: int, ok=(LS_OK,)):
+    if status not in ok:
+        raise LSError(status, load().ls_last_error().decode())
+    return status
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t) -> ctypes.c_void_p:
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("device buffers are torch tensors")
+    if t.device.type != "cuda":
+        raise ValueError("device buffers must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def sector_check(n_sites: int, hamming_weight: int, perm, flip, chi) -> dict:
+    """Validate a sector and compile its group on the host (ls_sector_check)."""
+    L = load()
+    perm = np.ascontiguousarray(perm, dtype=np.uint16)
+    flip = np.ascontiguousarray(flip, dtype=np.uint8)
+    chi = np.ascontiguousarray(chi, dtype=np.float64)
+    desc = SectorDesc(n_sites, hamming_weight, perm.shape[0], perm.ctypes.data, flip.ctypes.data,
+                      chi.ctypes.data)
+    lx, ly, pf, nc = (ctypes.c_uint32() for _ in range(4))
+    _check(L.ls_sector_check(ctypes.byref(desc), ctypes.byref(lx), ctypes.byref(ly), ctypes.byref(pf),
+                             ctypes.byref(nc)))
+    return dict(lx=lx.value, ly=ly.value, pair_flip=pf.value, n_cosets=nc.value)
+
+
+class Basis:
+    """Handle of a built basis (ls_basis_build)."""
+
+    def __init__(self, n_sites: int, hamming_weight: int, perm, flip, chi, stream=None):
+        L = load()
+        self._perm = np.ascontiguousarray(perm, dtype=np.uint16)
+        self._flip = np.ascontiguousarray(flip, dtype=np.uint8)
+        self._chi = np.ascontiguousarray(chi, dtype=np.float64)
+        if self._perm.ndim != 2 or self._perm.shape[1] != n_sites:
+            raise ValueError("perm must be [n_elements][n_sites]")
+        desc = SectorDesc(n_sites, hamming_weight, self._perm.shape[0], self._perm.ctypes.data,
+                          self._flip.ctypes.data, self._chi.ctypes.data)
+        h = ctypes.c_void_p()
+        _check(L.ls_basis_build(ctypes.byref(desc), _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        self.n_sites = n_sites
+        self.weight = hamming_weight
+        dim = ctypes.c_uint64()
+        is_real = ctypes.c_int()
+        _check(L.ls_basis_info(h, ctypes.byref(dim), ctypes.byref(is_real), None))
+        self.dim = int(dim.value)
+        self.is_real = bool(is_real.value)
+
+    @classmethod
+    def from_sector(cls, sector, stream=None) -> "Basis":
+        g = sector.group
+        return cls(sector.n_sites, sector.weight, g.perm, g.flip, g.chi, stream)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def copy(self, stream=None):
+        """(reps int64 view of uint64, stab int16 view of uint16) as new device tensors."""
+        import torch
+        reps = torch.empty(max(self.dim, 1), dtype=torch.int64, device="cuda")
+        stab = torch.empty(max(self.dim, 1), dtype=torch.int16, device="cuda")
+        _check(load().ls_basis_copy(self._h, _dptr(reps), _dptr(stab), _stream_ptr(stream)))
+        return reps[: self.dim], stab[: self.dim]
+
+    def state_info(self, states, stream=None):
+        import torch
+        n = states.numel()
+        reps = torch.empty(n, dtype=torch.int64, device=states.device)
+        chi = torch.empty((n, 2), dtype=torch.float64, device=states.device)
+        norm = torch.empty(n, dtype=torch.float64, device=states.device)
+        if n:
+            _check(load().ls_state_info(self._h, n, _dptr(states), _dptr(reps), _dptr(chi), _dptr(norm),
+                                        _stream_ptr(stream)))
+        return reps, chi, norm
+
+    def index_lookup(self, keys, stream=None):
+        import torch
+        n = keys.numel()
+        out = torch.empty(n, dtype=torch.int64, device=keys.device)
+        if n:
+            _check(load().ls_index_lookup(self._h, n, _dptr(keys), _dptr(out), _stream_ptr(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().ls_basis_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def terms_to_ctypes(term_table) -> ctypes.Array:
+    n = len(term_table)
+    arr = (Term * max(n, 1))()
+    for k in range(n):
+        t = term_table[k]
+        arr[k] = Term(float(t["re"]), float(t["im"]), int(t["sel_mask"]), int(t["sel_value"]),
+                      int(t["flip"]), int(t["sign_mask"]))
+    return arr
+
+
+class Operator:
+    """Handle of a compiled Hamiltonian (ls_operator_create)."""
+
+    def __init__(self, basis: Basis, term_table):
+        L = load()
+        self.basis = basis
+        self._terms = terms_to_ctypes(term_table)
+        h = ctypes.c_void_p()
+        _check(L.ls_operator_create(basis.handle, len(term_table), self._terms, ctypes.byref(h)))
+        self._h = h
+        c = ctypes.c_int()
+        _check(L.ls_operator_info(h, ctypes.byref(c), None))
+        self.is_complex = bool(c.value)
+        self.dim = basis.dim
+
+    @property
+    def handle(self):
+        return self._h
+
+    def matvec(self, x, y=None, stream=None):
+        """y = H x for x of shape [dim] or [dim][nrhs] (float64 / complex128)."""
+        import torch
+        want = torch.complex128 if self.is_complex else torch.float64
+        if x.dtype != want:
+            raise TypeError(f"x must be {want}")
+        nrhs = 1 if x.dim() == 1 else x.shape[1]
+        if x.shape[0] != self.dim:
+            raise ValueError("x has the wrong dimension")
+        if y is None:
+            y = torch.empty_like(x)
+        _check(load().ls_matvec(self._h, nrhs, _dptr(x), _dptr(y), _stream_ptr(stream)))
+        return y
+
+    def lanczos(self, max_iter: int, tol: float = 0.0, seed: int = 1, v0=None, reorth: bool = True,
+                stream=None):
+        m = int(max_iter)
+        alpha = np.zeros(m)
+        beta = np.zeros(m)
+        opts = LanczosOpts(m, 1 if reorth else 0, float(tol), int(seed),
+                           _dptr(v0) if v0 is not None else None, alpha.ctypes.data, beta.ctypes.data)
+        e0 = ctypes.c_double()
+        it = ctypes.c_uint32()
+        res = ctypes.c_double()
+        st = _check(load().ls_lanczos(self._h, ctypes.byref(opts), _stream_ptr(stream), ctypes.byref(e0),
+                                      ctypes.byref(it), ctypes.byref(res)), ok=(LS_OK, LS_WNOTCONV))
+        k = int(it.value)
+        return dict(e0=e0.value, iters=k, resid=res.value, alpha=alpha[:k].copy(),
+                    beta=beta[: max(k - 1, 0)].copy(), converged=(st == LS_OK) and tol > 0)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().ls_operator_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,207 @@
+// The C ABI: argument checks, exception-to-status translation, handles.
+
+#include <cstring>
+#include <new>
+
+#include "ls_internal.hpp"
+
+namespace ls {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+const char *last_error() { return g_last_error.c_str(); }
+
+}  // namespace ls
+
+namespace {
+
+template <typename F>
+ls_status guarded(F &&f) {
+    try {
+        return f();
+    } catch (const ls::Error &e) {
+        ls::set_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        ls::set_error("host allocation failed");
+        return LS_ENOMEM;
+    } catch (const std::exception &e) {
+        ls::set_error(e.what());
+        return LS_EINTERNAL;
+    }
+}
+
+void free_basis(ls_basis *b) {
+    if (!b) return;
+    hipFree(b->d_reps);
+    hipFree(b->d_stab);
+    hipFree(b->d_buckets);
+    hipFree(b->d_binom);
+    hipFree(b->d_cosets);
+    hipFree(b->d_chi);
+    hipFree(b->d_chi_one);
+    delete b;
+}
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+const char *ls_last_error(void) { return ls::last_error(); }
+
+const char *ls_version(void) { return "ls_ed 0.1 (gfx950)"; }
+
+ls_status ls_basis_build(const ls_sector_desc *desc, void *stream, ls_basis **out) {
+    ls_basis *b = nullptr;
+    ls_status st = guarded([&] {
+        LS_REQUIRE(desc != nullptr && out != nullptr, "desc and out must not be NULL");
+        ls::GroupPlan plan = ls::compile_group(*desc);
+        b = new ls_basis();
+        b->plan = std::move(plan);
+        b->weight = desc->hamming_weight;
+        b->perm_copy.assign(desc->perm, desc->perm + static_cast<size_t>(desc->n_elements) * desc->n_sites);
+        b->flip_copy.assign(desc->flip, desc->flip + desc->n_elements);
+        LS_HIP_CHECK(hipGetDevice(&b->device));
+        ls::build_basis(b, as_stream(stream));
+        *out = b;
+        return LS_OK;
+    });
+    if (st != LS_OK) free_basis(b);
+    return st;
+}
+
+ls_status ls_sector_check(const ls_sector_desc *desc, uint32_t *lx, uint32_t *ly, uint32_t *pair_flip,
+                          uint32_t *n_cosets) {
+    return guarded([&] {
+        LS_REQUIRE(desc != nullptr, "desc must not be NULL");
+        const ls::GroupPlan plan = ls::compile_group(*desc);
+        if (lx) *lx = plan.lx;
+        if (ly) *ly = plan.ly;
+        if (pair_flip) *pair_flip = plan.pair_flip;
+        if (n_cosets) *n_cosets = static_cast<uint32_t>(plan.cosets.size());
+        return LS_OK;
+    });
+}
+
+ls_status ls_basis_info(const ls_basis *b, uint64_t *dim, int *is_real, const uint64_t **d_reps) {
+    return guarded([&] {
+        LS_REQUIRE(b != nullptr, "basis must not be NULL");
+        if (dim) *dim = b->dim;
+        if (is_real) *is_real = b->plan.chi_mode != ls::kChiComplex;
+        if (d_reps) *d_reps = b->d_reps;
+        return LS_OK;
+    });
+}
+
+ls_status ls_basis_copy(const ls_basis *b, uint64_t *d_reps_out, uint16_t *d_stab_out, void *stream) {
+    return guarded([&] {
+        LS_REQUIRE(b != nullptr, "basis must not be NULL");
+        if (b->dim == 0) return LS_OK;
+        if (d_reps_out)
+            LS_HIP_CHECK(hipMemcpyAsync(d_reps_out, b->d_reps, b->dim * sizeof(uint64_t), hipMemcpyDeviceToDevice,
+                                        as_stream(stream)));
+        if (d_stab_out)
+            LS_HIP_CHECK(hipMemcpyAsync(d_stab_out, b->d_stab, b->dim * sizeof(uint16_t), hipMemcpyDeviceToDevice,
+                                        as_stream(stream)));
+        return LS_OK;
+    });
+}
+
+void ls_basis_destroy(ls_basis *b) {
+    if (!b) return;
+    hipDeviceSynchronize();
+    free_basis(b);
+}
+
+ls_status ls_state_info(const ls_basis *b, uint64_t n, const uint64_t *d_states, uint64_t *d_reps, double *d_chi,
+                        double *d_norm, void *stream) {
+    return guarded([&] {
+        LS_REQUIRE(b != nullptr, "basis must not be NULL");
+        if (n == 0) return LS_OK;
+        LS_REQUIRE(d_states && d_reps && d_chi && d_norm, "device pointers must not be NULL");
+        ls::launch_state_info(b, n, d_states, d_reps, d_chi, d_norm, as_stream(stream));
+        return LS_OK;
+    });
+}
+
+ls_status ls_index_lookup(const ls_basis *b, uint64_t n, const uint64_t *d_keys, int64_t *d_index, void *stream) {
+    return guarded([&] {
+        LS_REQUIRE(b != nullptr, "basis must not be NULL");
+        if (n == 0) return LS_OK;
+        LS_REQUIRE(d_keys && d_index, "device pointers must not be NULL");
+        ls::launch_index_lookup(b, n, d_keys, d_index, as_stream(stream));
+        return LS_OK;
+    });
+}
+
+ls_status ls_operator_create(const ls_basis *b, uint32_t n_terms, const ls_term *terms, ls_operator **out) {
+    ls_operator *op = nullptr;
+    ls_status st = guarded([&] {
+        LS_REQUIRE(b != nullptr && out != nullptr, "basis and out must not be NULL");
+        op = new ls_operator();
+        op->basis = b;
+        ls::compile_terms(b, n_terms, terms, op);
+        const size_t bytes = std::max<size_t>(op->host_terms.size(), 1) * sizeof(ls_term_dev);
+        LS_HIP_CHECK(hipMalloc(&op->d_terms, bytes));
+        if (!op->host_terms.empty())
+            LS_HIP_CHECK(hipMemcpy(op->d_terms, op->host_terms.data(), op->host_terms.size() * sizeof(ls_term_dev),
+                                   hipMemcpyHostToDevice));
+        *out = op;
+        return LS_OK;
+    });
+    if (st != LS_OK && op) {
+        hipFree(op->d_terms);
+        delete op;
+    }
+    return st;
+}
+
+void ls_operator_destroy(ls_operator *op) {
+    if (!op) return;
+    hipDeviceSynchronize();
+    hipFree(op->d_terms);
+    delete op;
+}
+
+ls_status ls_operator_info(const ls_operator *op, int *is_complex, uint64_t *dim) {
+    return guarded([&] {
+        LS_REQUIRE(op != nullptr, "operator must not be NULL");
+        if (is_complex) *is_complex = op->is_complex ? 1 : 0;
+        if (dim) *dim = op->basis->dim;
+        return LS_OK;
+    });
+}
+
+ls_status ls_matvec(const ls_operator *op, uint32_t nrhs, const void *d_x, void *d_y, void *stream) {
+    return guarded([&] {
+        LS_REQUIRE(op != nullptr, "operator must not be NULL");
+        LS_REQUIRE(nrhs >= 1 && nrhs <= 64, "nrhs must be in 1..64");
+        if (op->basis->dim == 0) return LS_OK;
+        LS_REQUIRE(d_x != nullptr && d_y != nullptr, "x and y must not be NULL");
+        const size_t bytes = op->basis->dim * nrhs * (op->is_complex ? 16u : 8u);
+        const char *xb = static_cast<const char *>(d_x);
+        const char *yb = static_cast<const char *>(d_y);
+        LS_REQUIRE(xb + bytes <= yb || yb + bytes <= xb, "x and y must not overlap");
+        ls::launch_matvec(op, nrhs, d_x, d_y, as_stream(stream));
+        return LS_OK;
+    });
+}
+
+ls_status ls_lanczos(const ls_operator *op, const ls_lanczos_opts *opts, void *stream, double *e0, uint32_t *iters,
+                     double *resid_bound) {
+    return guarded([&] {
+        LS_REQUIRE(op != nullptr && opts != nullptr, "operator and opts must not be NULL");
+        LS_REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
+        LS_REQUIRE(opts->reorth <= 1, "reorth must be 0 or 1");
+        LS_REQUIRE(std::isfinite(opts->tol) && opts->tol >= 0, "tol must be >= 0");
+        LS_REQUIRE(op->basis->dim > 0, "the basis is empty");
+        return ls::run_lanczos(op, opts, as_stream(stream), e0, iters, resid_bound);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,439 @@
+// Basis construction (Section 5.2), state_info and stateToIndex kernels.
+//
+// Enumeration: the candidates are all weight-w bitstrings in increasing
+// order (colex rank 0 .. C(N,w)-1), or 0 .. 2^N-1 without U(1).  The paper
+// splits this range into chunks, filters each chunk and then places the
+// survivors with a histogram -> cumulative sum -> offsets scheme (Section
+// 5.1 "Block to hashed", Section 5.2).  On one GPU the same scheme becomes
+// an order-preserving stream compaction:
+//   pass 1  every lane filters 64 consecutive candidates (Gosper's
+//           next-combination step between them) and keeps a 64-bit mark
+//           word; a workgroup reduction gives per-chunk counts;
+//   scan    an exclusive scan of the chunk counts gives chunk offsets;
+//   pass 2  a workgroup scan of the lanes' mark popcounts gives each lane's
+//           offset; the lane regenerates its candidates and writes the
+//           marked ones.  No atomics; the output is sorted by construction.
+// The "condition" kept by the filter: s is the minimum of its orbit, and P
+// does not annihilate it (every stabilizer element has character 1).
+
+#include <algorithm>
+#include <cmath>
+
+#include "orbit.hpp"
+
+namespace ls {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kCandPerLane = 64;
+
+__device__ uint64_t unrank_colex(uint64_t rank, uint32_t n, int32_t w, const uint64_t *tab) {
+    uint64_t s = 0;
+    uint32_t k = static_cast<uint32_t>(w);
+    for (int p = static_cast<int>(n) - 1; p >= 0 && k > 0; --p) {
+        const uint64_t c = binom(tab, static_cast<uint32_t>(p), k);
+        if (c <= rank) {
+            s |= 1ULL << p;
+            rank -= c;
+            --k;
+        }
+    }
+    return s;
+}
+
+template <typename W>
+__device__ __forceinline__ W next_combination(W x) {
+    const W c = x & (~x + 1);
+    const W r = x + c;
+    const int z = sizeof(W) == 4 ? __builtin_ctz(static_cast<uint32_t>(x))
+                                 : __builtin_ctzll(static_cast<uint64_t>(x));
+    return (((r ^ x) >> 2) >> z) | r;
+}
+
+// s kept iff no image is smaller and every image equal to s has chi == 1.
+template <typename W, int KIND>
+__device__ __forceinline__ bool is_member(const PlanDev &P, W s) {
+    bool keep = true;
+    for_each_image<W, KIND>(P, s, [&](W v, uint32_t code) {
+        if (v < s || (v == s && !chi_is_one(P, code))) {
+            keep = false;
+            return false;
+        }
+        return true;
+    });
+    return keep;
+}
+
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    const uint32_t r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// exclusive scan over the block
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const uint32_t add = t >= off ? sh[t - off] : 0u;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    const uint32_t incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+struct EnumArgs {
+    PlanDev plan;
+    const uint64_t *binom;
+    uint64_t total;        // candidates
+    uint32_t n_sites;
+    int32_t weight;
+    uint64_t *marks;       // [lanes]
+    uint32_t *counts;      // [blocks]
+    const uint64_t *offsets;  // [blocks], pass 2
+    uint64_t *reps;        // pass 2
+};
+
+template <typename W>
+__device__ __forceinline__ W first_candidate(const EnumArgs &a, uint64_t start) {
+    return a.weight >= 0 ? static_cast<W>(unrank_colex(start, a.n_sites, a.weight, a.binom))
+                         : static_cast<W>(start);
+}
+
+template <typename W>
+__device__ __forceinline__ W next_candidate(const EnumArgs &a, W s) {
+    return a.weight >= 0 ? next_combination<W>(s) : static_cast<W>(s + 1);
+}
+
+template <typename W, int KIND>
+__global__ void __launch_bounds__(kBlock) k_enum_mark(EnumArgs a) {
+    __shared__ uint32_t sh[kBlock];
+    const uint64_t lane = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const uint64_t start = lane * kCandPerLane;
+    uint64_t mask = 0;
+    if (start < a.total) {
+        const uint32_t cnt = static_cast<uint32_t>(min<uint64_t>(kCandPerLane, a.total - start));
+        W s = first_candidate<W>(a, start);
+        for (uint32_t q = 0; q < cnt; ++q) {
+            if (is_member<W, KIND>(a.plan, s)) mask |= 1ULL << q;
+            if (q + 1 < cnt) s = next_candidate<W>(a, s);
+        }
+        a.marks[lane] = mask;
+    }
+    const uint32_t c = block_sum(static_cast<uint32_t>(__builtin_popcountll(mask)), sh);
+    if (threadIdx.x == 0) a.counts[blockIdx.x] = c;
+}
+
+template <typename W>
+__global__ void __launch_bounds__(kBlock) k_enum_write(EnumArgs a) {
+    __shared__ uint32_t sh[kBlock];
+    const uint64_t lane = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const uint64_t start = lane * kCandPerLane;
+    uint64_t mask = start < a.total ? a.marks[lane] : 0ULL;
+    const uint32_t local = block_exclusive_scan(static_cast<uint32_t>(__builtin_popcountll(mask)), sh);
+    if (mask == 0) return;
+    uint64_t pos = a.offsets[blockIdx.x] + local;
+    const uint32_t cnt = static_cast<uint32_t>(min<uint64_t>(kCandPerLane, a.total - start));
+    W s = first_candidate<W>(a, start);
+    for (uint32_t q = 0; q < cnt; ++q) {
+        if ((mask >> q) & 1ULL) a.reps[pos++] = static_cast<uint64_t>(s);
+        if (q + 1 < cnt) s = next_candidate<W>(a, s);
+    }
+}
+
+// Single-workgroup exclusive scan of n counts (n up to a few million).
+__global__ void __launch_bounds__(1024) k_scan_counts(const uint32_t *counts, uint64_t n, uint64_t *offsets,
+                                                      uint64_t *total) {
+    __shared__ uint64_t sh[1024];
+    const int t = threadIdx.x;
+    const uint64_t per = (n + 1023) / 1024;
+    const uint64_t b = min<uint64_t>(n, per * t), e = min<uint64_t>(n, b + per);
+    uint64_t s = 0;
+    for (uint64_t i = b; i < e; ++i) s += counts[i];
+    sh[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint64_t add = t >= off ? sh[t - off] : 0ull;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    uint64_t run = sh[t] - s;
+    for (uint64_t i = b; i < e; ++i) {
+        offsets[i] = run;
+        run += counts[i];
+    }
+    if (t == 1023) *total = sh[1023];
+}
+
+template <typename W, int KIND>
+__global__ void __launch_bounds__(kBlock) k_stab(PlanDev P, const uint64_t *reps, uint64_t d, uint16_t *stab) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= d) return;
+    const W r = static_cast<W>(reps[i]);
+    uint32_t cnt = 0;
+    for_each_image<W, KIND>(P, r, [&](W v, uint32_t) {
+        cnt += v == r ? 1u : 0u;
+        return true;
+    });
+    stab[i] = static_cast<uint16_t>(cnt);
+}
+
+__global__ void __launch_bounds__(kBlock) k_buckets(const uint64_t *reps, uint64_t d, uint64_t kmin, uint32_t shift,
+                                                    uint64_t nb, uint32_t *buckets) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= d) return;
+    const uint64_t bi = (reps[i] - kmin) >> shift;
+    const int64_t prev = i == 0 ? -1 : static_cast<int64_t>((reps[i - 1] - kmin) >> shift);
+    for (int64_t k = prev + 1; k <= static_cast<int64_t>(bi); ++k) buckets[k] = static_cast<uint32_t>(i);
+    if (i == d - 1)
+        for (uint64_t k = bi + 1; k <= nb; ++k) buckets[k] = static_cast<uint32_t>(d);
+}
+
+template <typename W, int KIND>
+__global__ void __launch_bounds__(kBlock) k_state_info(PlanDev P, int32_t weight, uint64_t n, const uint64_t *states,
+                                                       uint64_t *reps, double *chi, double *norm) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t s64 = states[i];
+    if (P.n_sites < 64 && (s64 >> P.n_sites) != 0) {
+        reps[i] = s64;
+        chi[2 * i] = 0.0;
+        chi[2 * i + 1] = 0.0;
+        norm[i] = 0.0;
+        return;
+    }
+    const W s = static_cast<W>(s64);
+    W best = s;
+    uint32_t arg = 0, stab = 0;
+    bool bad = false;
+    for_each_image<W, KIND>(P, s, [&](W v, uint32_t code) {
+        if (v < best) { best = v; arg = code; }
+        if (v == s) {
+            ++stab;
+            bad = bad || !chi_is_one(P, code);
+        }
+        return true;
+    });
+    const bool in = !bad && (weight < 0 || __builtin_popcountll(s64) == weight);
+    reps[i] = static_cast<uint64_t>(best);
+    if (in) {
+        const double2 c = P.chi[arg];
+        chi[2 * i] = c.x;
+        chi[2 * i + 1] = c.y;
+        norm[i] = __dsqrt_rn(__ddiv_rn(static_cast<double>(stab), static_cast<double>(P.n_elements)));
+    } else {
+        chi[2 * i] = 0.0;
+        chi[2 * i + 1] = 0.0;
+        norm[i] = 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_index_lookup(SearchDev S, uint64_t n, const uint64_t *keys, int64_t *out) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    out[i] = lookup_index(S, keys[i]);
+}
+
+template <typename W>
+int orbit_kind(const GroupPlan &p) {
+    return (sizeof(W) == 4 && p.ly == 1 && p.lx == p.n_sites && p.n_sites <= 32) ? kOrbitRing32 : kOrbitGeneric;
+}
+
+uint64_t grid_for(uint64_t n) { return (n + kBlock - 1) / kBlock; }
+
+template <typename W>
+void enumerate_impl(ls_basis *b, hipStream_t st, uint64_t total, uint64_t **out_reps, uint64_t *out_dim) {
+    const GroupPlan &gp = b->plan;
+    const uint64_t lanes = (total + kCandPerLane - 1) / kCandPerLane;
+    const uint64_t blocks = grid_for(lanes);
+    uint64_t *marks = nullptr, *offsets = nullptr, *d_total = nullptr;
+    uint32_t *counts = nullptr;
+    LS_HIP_CHECK(hipMalloc(&marks, std::max<uint64_t>(lanes, 1) * sizeof(uint64_t)));
+    LS_HIP_CHECK(hipMalloc(&counts, std::max<uint64_t>(blocks, 1) * sizeof(uint32_t)));
+    LS_HIP_CHECK(hipMalloc(&offsets, std::max<uint64_t>(blocks, 1) * sizeof(uint64_t)));
+    LS_HIP_CHECK(hipMalloc(&d_total, sizeof(uint64_t)));
+    EnumArgs a{};
+    a.plan = b->plan_dev;
+    a.binom = b->d_binom;
+    a.total = total;
+    a.n_sites = gp.n_sites;
+    a.weight = b->weight;
+    a.marks = marks;
+    a.counts = counts;
+    a.offsets = offsets;
+    const int kind = orbit_kind<W>(gp);
+    if (blocks > 0) {
+        if (kind == kOrbitRing32)
+            hipLaunchKernelGGL((k_enum_mark<W, kOrbitRing32>), dim3(blocks), dim3(kBlock), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_enum_mark<W, kOrbitGeneric>), dim3(blocks), dim3(kBlock), 0, st, a);
+        LS_HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, counts, blocks, offsets, d_total);
+        LS_HIP_CHECK(hipGetLastError());
+    }
+    uint64_t dim = 0;
+    if (blocks > 0) {
+        LS_HIP_CHECK(hipMemcpyAsync(&dim, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        LS_HIP_CHECK(hipStreamSynchronize(st));
+    }
+    uint64_t *reps = nullptr;
+    LS_HIP_CHECK(hipMalloc(&reps, std::max<uint64_t>(dim, 1) * sizeof(uint64_t)));
+    a.reps = reps;
+    if (dim > 0) {
+        hipLaunchKernelGGL((k_enum_write<W>), dim3(blocks), dim3(kBlock), 0, st, a);
+        LS_HIP_CHECK(hipGetLastError());
+    }
+    LS_HIP_CHECK(hipStreamSynchronize(st));
+    hipFree(marks);
+    hipFree(counts);
+    hipFree(offsets);
+    hipFree(d_total);
+    *out_reps = reps;
+    *out_dim = dim;
+}
+
+template <typename W>
+void stab_impl(ls_basis *b, hipStream_t st) {
+    if (b->dim == 0) return;
+    if (orbit_kind<W>(b->plan) == kOrbitRing32)
+        hipLaunchKernelGGL((k_stab<W, kOrbitRing32>), dim3(grid_for(b->dim)), dim3(kBlock), 0, st, b->plan_dev,
+                           b->d_reps, b->dim, b->d_stab);
+    else
+        hipLaunchKernelGGL((k_stab<W, kOrbitGeneric>), dim3(grid_for(b->dim)), dim3(kBlock), 0, st, b->plan_dev,
+                           b->d_reps, b->dim, b->d_stab);
+    LS_HIP_CHECK(hipGetLastError());
+}
+
+uint64_t host_binom(uint32_t n, uint32_t k) {
+    if (k > n) return 0;
+    uint64_t r = 1;
+    for (uint32_t i = 1; i <= k; ++i) r = r * (n - k + i) / i;   // exact: r*(n-k+i) divisible by i
+    return r;
+}
+
+}  // namespace
+
+void build_basis(ls_basis *b, hipStream_t st) {
+    const GroupPlan &gp = b->plan;
+    const uint32_t n = gp.n_sites;
+    // binomial table
+    std::vector<uint64_t> tab(65 * 65, 0);
+    for (uint32_t i = 0; i <= 64; ++i)
+        for (uint32_t k = 0; k <= i; ++k) tab[i * 65 + k] = host_binom(i, k);
+    LS_HIP_CHECK(hipMalloc(&b->d_binom, tab.size() * sizeof(uint64_t)));
+    LS_HIP_CHECK(hipMemcpy(b->d_binom, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    // plan
+    const size_t ncos = gp.cosets.size();
+    LS_HIP_CHECK(hipMalloc(&b->d_cosets, ncos * sizeof(CosetRep)));
+    LS_HIP_CHECK(hipMemcpy(b->d_cosets, gp.cosets.data(), ncos * sizeof(CosetRep), hipMemcpyHostToDevice));
+    LS_HIP_CHECK(hipMalloc(&b->d_chi, gp.n_elements * sizeof(double2)));
+    LS_HIP_CHECK(hipMemcpy(b->d_chi, gp.chi.data(), gp.n_elements * sizeof(double2), hipMemcpyHostToDevice));
+    LS_HIP_CHECK(hipMalloc(&b->d_chi_one, gp.chi_one.size() * sizeof(uint32_t)));
+    LS_HIP_CHECK(hipMemcpy(b->d_chi_one, gp.chi_one.data(), gp.chi_one.size() * sizeof(uint32_t),
+                           hipMemcpyHostToDevice));
+    PlanDev &pd = b->plan_dev;
+    pd.n_sites = n;
+    pd.lx = gp.lx;
+    pd.ly = gp.ly;
+    pd.n_trans = gp.lx * gp.ly;
+    pd.n_cosets = static_cast<uint32_t>(ncos);
+    pd.pair_flip = gp.pair_flip;
+    pd.n_stages = gp.n_stages;
+    pd.n_elements = gp.n_elements;
+    pd.full = gp.full;
+    pd.col0 = gp.col0;
+    pd.cosets = b->d_cosets;
+    pd.chi = b->d_chi;
+    pd.chi_one = b->d_chi_one;
+
+    // candidates
+    uint64_t total;
+    if (b->weight >= 0) total = host_binom(n, static_cast<uint32_t>(b->weight));
+    else total = 1ULL << n;
+    if (n <= 32) enumerate_impl<uint32_t>(b, st, total, &b->d_reps, &b->dim);
+    else enumerate_impl<uint64_t>(b, st, total, &b->d_reps, &b->dim);
+    if (b->dim >= 0xFFFFFFFFull) throw Error{LS_EINVAL, "basis dimension must be below 2^32 - 1"};
+
+    LS_HIP_CHECK(hipMalloc(&b->d_stab, std::max<uint64_t>(b->dim, 1) * sizeof(uint16_t)));
+    if (n <= 32) stab_impl<uint32_t>(b, st);
+    else stab_impl<uint64_t>(b, st);
+
+    // search layout
+    SearchDev &S = b->search_dev;
+    S.n_sites = n;
+    S.weight = b->weight;
+    S.dim = b->dim;
+    S.reps = b->d_reps;
+    S.binom = b->d_binom;
+    if (gp.n_elements == 1 && b->weight < 0) {
+        S.mode = kLookupIdentity;
+    } else if (gp.n_elements == 1) {
+        S.mode = kLookupRank;
+    } else {
+        S.mode = kLookupSearch;
+        uint64_t kmin = 0, kmax = 0;
+        if (b->dim > 0) {
+            LS_HIP_CHECK(hipMemcpy(&kmin, b->d_reps, sizeof(uint64_t), hipMemcpyDeviceToHost));
+            LS_HIP_CHECK(hipMemcpy(&kmax, b->d_reps + (b->dim - 1), sizeof(uint64_t), hipMemcpyDeviceToHost));
+        }
+        S.kmin = kmin;
+        S.kmax = kmax;
+        // about 4 keys per bucket, 2^8 .. 2^22 buckets
+        uint32_t bits = 8;
+        while (bits < 22 && (1ULL << bits) * 4 < b->dim) ++bits;
+        const uint64_t range = kmax - kmin;
+        uint32_t len = 0;
+        while (len < 64 && (range >> len) != 0) ++len;
+        S.bits = bits;
+        S.shift = len > bits ? len - bits : 0;
+        const uint64_t nb = (range >> S.shift) + 1;   // buckets 0 .. nb-1
+        LS_HIP_CHECK(hipMalloc(&b->d_buckets, (nb + 1) * sizeof(uint32_t)));
+        if (b->dim > 0)
+            hipLaunchKernelGGL(k_buckets, dim3(grid_for(b->dim)), dim3(kBlock), 0, st, b->d_reps, b->dim, kmin,
+                               S.shift, nb, b->d_buckets);
+        else
+            LS_HIP_CHECK(hipMemsetAsync(b->d_buckets, 0, (nb + 1) * sizeof(uint32_t), st));
+        LS_HIP_CHECK(hipGetLastError());
+        S.buckets = b->d_buckets;
+    }
+    LS_HIP_CHECK(hipStreamSynchronize(st));
+}
+
+void launch_state_info(const ls_basis *b, uint64_t n, const uint64_t *states, uint64_t *reps, double *chi,
+                       double *norm, hipStream_t st) {
+    if (n == 0) return;
+    const GroupPlan &gp = b->plan;
+    if (gp.n_sites <= 32) {
+        if (orbit_kind<uint32_t>(gp) == kOrbitRing32)
+            hipLaunchKernelGGL((k_state_info<uint32_t, kOrbitRing32>), dim3(grid_for(n)), dim3(kBlock), 0, st,
+                               b->plan_dev, b->weight, n, states, reps, chi, norm);
+        else
+            hipLaunchKernelGGL((k_state_info<uint32_t, kOrbitGeneric>), dim3(grid_for(n)), dim3(kBlock), 0, st,
+                               b->plan_dev, b->weight, n, states, reps, chi, norm);
+    } else {
+        hipLaunchKernelGGL((k_state_info<uint64_t, kOrbitGeneric>), dim3(grid_for(n)), dim3(kBlock), 0, st,
+                           b->plan_dev, b->weight, n, states, reps, chi, norm);
+    }
+    LS_HIP_CHECK(hipGetLastError());
+}
+
+void launch_index_lookup(const ls_basis *b, uint64_t n, const uint64_t *keys, int64_t *index, hipStream_t st) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_index_lookup, dim3(grid_for(n)), dim3(kBlock), 0, st, b->search_dev, n, keys, index);
+    LS_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace ls

@@ -1,0 +1,363 @@
+// Lanczos ground-state solve on top of the on-the-fly product.
+//
+// The paper's product is consumed by Krylov eigensolvers that call it
+// hundreds to thousands of times (Section 2.1, Section 6.3).  This driver
+// keeps every Krylov vector resident in HBM and runs the three-term
+// recurrence in FP64:
+//   w = H v_k;  alpha_k = Re<v_k, w>;  w -= alpha_k v_k + beta_k v_{k-1};
+//   CGS2 (twice: h = V^H w; w -= V h);  beta_{k+1} = ||w||;
+//   v_{k+1} = w / beta_{k+1}.
+// Dot products use a fixed grid and a fixed reduction tree, so results do
+// not depend on scheduling.  The m x m tridiagonal eigenproblem is solved on
+// the host (Sturm-sequence bisection for the lowest eigenvalue, inverse
+// iteration for the last component of its eigenvector).
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "ls_internal.hpp"
+
+namespace ls {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kDotBlocks = 1024;
+constexpr int kTile = 8;    // Krylov vectors per pass of the multi-dot
+
+template <bool CPLX>
+struct V;
+template <>
+struct V<false> {
+    using T = double;
+};
+template <>
+struct V<true> {
+    using T = double2;
+};
+
+__device__ __forceinline__ double block_reduce(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// partial[b] (re, im) = sum over the block's fixed index set of conj(a) b
+template <bool CPLX>
+__global__ void __launch_bounds__(kBlock) k_dot_partial(const void *pa, const void *pb, uint64_t n, double2 *partial) {
+    __shared__ double sh[kBlock];
+    double re = 0.0, im = 0.0;
+    const uint64_t stride = static_cast<uint64_t>(kDotBlocks) * kBlock;
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+        if constexpr (CPLX) {
+            const double2 a = static_cast<const double2 *>(pa)[i];
+            const double2 b = static_cast<const double2 *>(pb)[i];
+            re = fma(a.x, b.x, fma(a.y, b.y, re));
+            im = fma(a.x, b.y, fma(-a.y, b.x, im));
+        } else {
+            re = fma(static_cast<const double *>(pa)[i], static_cast<const double *>(pb)[i], re);
+        }
+    }
+    re = block_reduce(re, sh);
+    if constexpr (CPLX) im = block_reduce(im, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(re, im);
+}
+
+// out[j] = sum_b partial[b * stride + j], b = 0..nb-1 in a fixed tree
+__global__ void __launch_bounds__(kBlock) k_reduce_partials(const double2 *partial, int nb, int stride, double2 *out) {
+    __shared__ double sh[kBlock];
+    const int j = blockIdx.x;
+    double re = 0.0, im = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+        re += partial[static_cast<size_t>(b) * stride + j].x;
+        im += partial[static_cast<size_t>(b) * stride + j].y;
+    }
+    re = block_reduce(re, sh);
+    im = block_reduce(im, sh);
+    if (threadIdx.x == 0) out[j] = make_double2(re, im);
+}
+
+// partial[b][j0 + q] = sum over the block's rows of conj(V_{j0+q}) w, q < tile
+template <bool CPLX>
+__global__ void __launch_bounds__(kBlock) k_multidot_partial(const void *pV, uint64_t n, int j0, int tile,
+                                                             const void *pw, double2 *partial, int stride) {
+    __shared__ double sh[kBlock];
+    double re[kTile], im[kTile];
+#pragma unroll
+    for (int q = 0; q < kTile; ++q) re[q] = im[q] = 0.0;
+    const uint64_t gstride = static_cast<uint64_t>(kDotBlocks) * kBlock;
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += gstride) {
+        if constexpr (CPLX) {
+            const double2 w = static_cast<const double2 *>(pw)[i];
+            const double2 *Vb = static_cast<const double2 *>(pV);
+#pragma unroll
+            for (int q = 0; q < kTile; ++q) {
+                if (q < tile) {
+                    const double2 v = Vb[static_cast<uint64_t>(j0 + q) * n + i];
+                    re[q] = fma(v.x, w.x, fma(v.y, w.y, re[q]));
+                    im[q] = fma(v.x, w.y, fma(-v.y, w.x, im[q]));
+                }
+            }
+        } else {
+            const double w = static_cast<const double *>(pw)[i];
+            const double *Vb = static_cast<const double *>(pV);
+#pragma unroll
+            for (int q = 0; q < kTile; ++q)
+                if (q < tile) re[q] = fma(Vb[static_cast<uint64_t>(j0 + q) * n + i], w, re[q]);
+        }
+    }
+    for (int q = 0; q < tile; ++q) {
+        const double r = block_reduce(re[q], sh);
+        double m = 0.0;
+        if constexpr (CPLX) m = block_reduce(im[q], sh);
+        if (threadIdx.x == 0) partial[static_cast<size_t>(blockIdx.x) * stride + j0 + q] = make_double2(r, m);
+    }
+}
+
+// w -= sum_j V_j h_j
+template <bool CPLX>
+__global__ void __launch_bounds__(kBlock) k_gemv_sub(const void *pV, uint64_t n, int nv, const double2 *h, void *pw) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    if constexpr (CPLX) {
+        const double2 *Vb = static_cast<const double2 *>(pV);
+        double2 w = static_cast<double2 *>(pw)[i];
+        double sre = 0.0, sim = 0.0;
+        for (int j = 0; j < nv; ++j) {
+            const double2 v = Vb[static_cast<uint64_t>(j) * n + i];
+            const double2 c = h[j];
+            sre = fma(v.x, c.x, fma(-v.y, c.y, sre));
+            sim = fma(v.x, c.y, fma(v.y, c.x, sim));
+        }
+        w.x -= sre;
+        w.y -= sim;
+        static_cast<double2 *>(pw)[i] = w;
+    } else {
+        const double *Vb = static_cast<const double *>(pV);
+        double s = 0.0;
+        for (int j = 0; j < nv; ++j) s = fma(Vb[static_cast<uint64_t>(j) * n + i], h[j].x, s);
+        static_cast<double *>(pw)[i] -= s;
+    }
+}
+
+// w -= alpha v + beta vp   (vp may be null)
+template <bool CPLX>
+__global__ void __launch_bounds__(kBlock) k_three_term(void *pw, const void *pv, const void *pvp, uint64_t n,
+                                                       double alpha, double beta) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    if constexpr (CPLX) {
+        double2 w = static_cast<double2 *>(pw)[i];
+        const double2 v = static_cast<const double2 *>(pv)[i];
+        w.x -= alpha * v.x;
+        w.y -= alpha * v.y;
+        if (pvp) {
+            const double2 u = static_cast<const double2 *>(pvp)[i];
+            w.x -= beta * u.x;
+            w.y -= beta * u.y;
+        }
+        static_cast<double2 *>(pw)[i] = w;
+    } else {
+        double w = static_cast<double *>(pw)[i];
+        w -= alpha * static_cast<const double *>(pv)[i];
+        if (pvp) w -= beta * static_cast<const double *>(pvp)[i];
+        static_cast<double *>(pw)[i] = w;
+    }
+}
+
+// dst = src / s (element-wise over doubles)
+__global__ void __launch_bounds__(kBlock) k_div(double *dst, const double *src, uint64_t n, double s) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < n) dst[i] = src[i] / s;
+}
+
+// Start vector from the counter generator built on the paper's hash64_01.
+__device__ __forceinline__ uint64_t mix(uint64_t x) {
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebULL;
+    return x ^ (x >> 31);
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_uniform(double *out, uint64_t count, uint64_t seed) {
+    const uint64_t c = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (c >= count) return;
+    const uint64_t u = mix(seed + (c + 1) * 0x9E3779B97F4A7C15ULL);
+    out[c] = 2.0 * (static_cast<double>(u >> 11) * 0x1.0p-53) - 1.0;
+}
+
+uint32_t grid(uint64_t n) { return static_cast<uint32_t>((n + kBlock - 1) / kBlock); }
+
+// Lowest eigenvalue of the symmetric tridiagonal (a, b) by Sturm bisection.
+double tridiag_lowest(const std::vector<double> &a, const std::vector<double> &b) {
+    const size_t m = a.size();
+    double lo = a[0], hi = a[0];
+    for (size_t i = 0; i < m; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    const double scale = std::max(std::fabs(lo), std::fabs(hi));
+    const double tiny = std::max(scale, 1.0) * 1e-300;
+    auto count_below = [&](double x) {
+        int cnt = 0;
+        double q = a[0] - x;
+        if (q < 0) ++cnt;
+        for (size_t i = 1; i < m; ++i) {
+            if (std::fabs(q) < tiny) q = -tiny;
+            q = a[i] - x - b[i - 1] * b[i - 1] / q;
+            if (q < 0) ++cnt;
+        }
+        return cnt;
+    };
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (count_below(mid) >= 1) hi = mid; else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// |last component| of the unit eigenvector of T for eigenvalue theta
+double tridiag_last_component(const std::vector<double> &a, const std::vector<double> &b, double theta) {
+    const size_t m = a.size();
+    if (m == 1) return 1.0;
+    double norm_t = 0.0;
+    for (size_t i = 0; i < m; ++i) norm_t = std::max(norm_t, std::fabs(a[i]) + (i ? std::fabs(b[i - 1]) : 0.0));
+    const double eps = std::max(norm_t, 1.0) * 1e-15;
+    std::vector<double> z(m, 1.0), c(m), d(m), rhs(m);
+    for (int pass = 0; pass < 3; ++pass) {
+        // Thomas solve of (T - theta) y = z with pivot guard
+        for (size_t i = 0; i < m; ++i) rhs[i] = z[i];
+        d[0] = a[0] - theta;
+        if (std::fabs(d[0]) < eps) d[0] = eps;
+        for (size_t i = 1; i < m; ++i) {
+            const double l = b[i - 1] / d[i - 1];
+            d[i] = a[i] - theta - l * b[i - 1];
+            if (std::fabs(d[i]) < eps) d[i] = eps;
+            rhs[i] -= l * rhs[i - 1];
+        }
+        z[m - 1] = rhs[m - 1] / d[m - 1];
+        for (size_t i = m - 1; i-- > 0;) z[i] = (rhs[i] - b[i] * z[i + 1]) / d[i];
+        double nz = 0.0;
+        for (double v : z) nz += v * v;
+        nz = std::sqrt(nz);
+        for (double &v : z) v /= nz;
+    }
+    return std::fabs(z[m - 1]);
+}
+
+struct DevMem {
+    void *p = nullptr;
+    ~DevMem() { if (p) hipFree(p); }
+};
+
+template <bool CPLX>
+ls_status lanczos_impl(const ls_operator *op, const ls_lanczos_opts *o, hipStream_t st, double *e0_out,
+                       uint32_t *iters_out, double *resid_out) {
+    using T = typename V<CPLX>::T;
+    const uint64_t n = op->basis->dim;
+    const uint32_t m = static_cast<uint32_t>(std::min<uint64_t>(o->max_iter, n));
+    const size_t es = sizeof(T);
+    DevMem Vm, wm, part, scal;
+    hipError_t err = hipMalloc(&Vm.p, static_cast<size_t>(m) * n * es);
+    if (err != hipSuccess) throw Error{LS_ENOMEM, "cannot allocate the Krylov vectors"};
+    LS_HIP_CHECK(hipMalloc(&wm.p, n * es));
+    LS_HIP_CHECK(hipMalloc(&part.p, static_cast<size_t>(kDotBlocks) * std::max<uint32_t>(m, 1) * sizeof(double2)));
+    LS_HIP_CHECK(hipMalloc(&scal.p, std::max<uint32_t>(m, 1) * sizeof(double2)));
+    T *Vb = static_cast<T *>(Vm.p);
+    T *w = static_cast<T *>(wm.p);
+    double2 *partial = static_cast<double2 *>(part.p);
+    double2 *hs = static_cast<double2 *>(scal.p);
+    const uint64_t nd = n * (CPLX ? 2 : 1);    // doubles per vector
+
+    auto dot = [&](const T *x, const T *y) {
+        hipLaunchKernelGGL(k_dot_partial<CPLX>, dim3(kDotBlocks), dim3(kBlock), 0, st, x, y, n, partial);
+        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, partial, kDotBlocks, 1, hs);
+        double2 r;
+        LS_HIP_CHECK(hipMemcpyAsync(&r, hs, sizeof(double2), hipMemcpyDeviceToHost, st));
+        LS_HIP_CHECK(hipStreamSynchronize(st));
+        return r;
+    };
+
+    // start vector
+    if (o->d_v0) {
+        LS_HIP_CHECK(hipMemcpyAsync(w, o->d_v0, n * es, hipMemcpyDeviceToDevice, st));
+    } else {
+        hipLaunchKernelGGL(k_fill_uniform, dim3(grid(nd)), dim3(kBlock), 0, st, reinterpret_cast<double *>(w), nd,
+                           o->seed);
+    }
+    LS_HIP_CHECK(hipGetLastError());
+    const double nrm0 = std::sqrt(dot(w, w).x);
+    if (!(nrm0 > 0.0)) throw Error{LS_EINVAL, "the start vector is zero"};
+    hipLaunchKernelGGL(k_div, dim3(grid(nd)), dim3(kBlock), 0, st, reinterpret_cast<double *>(Vb),
+                       reinterpret_cast<const double *>(w), nd, nrm0);
+
+    std::vector<double> alpha, beta;
+    double e0 = 0.0, resid = INFINITY, prev = 0.0;
+    bool have_prev = false, converged = false;
+    for (uint32_t k = 0; k < m; ++k) {
+        T *vk = Vb + static_cast<uint64_t>(k) * n;
+        launch_matvec(op, 1, vk, w, st);
+        const double a = dot(vk, w).x;
+        hipLaunchKernelGGL(k_three_term<CPLX>, dim3(grid(n)), dim3(kBlock), 0, st, w, vk,
+                           k > 0 ? Vb + static_cast<uint64_t>(k - 1) * n : nullptr, n, a,
+                           k > 0 ? beta[k - 1] : 0.0);
+        if (o->reorth) {
+            const int nv = static_cast<int>(k) + 1;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int j0 = 0; j0 < nv; j0 += kTile)
+                    hipLaunchKernelGGL(k_multidot_partial<CPLX>, dim3(kDotBlocks), dim3(kBlock), 0, st, Vb, n, j0,
+                                       std::min(kTile, nv - j0), w, partial, static_cast<int>(m));
+                hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(kBlock), 0, st, partial, kDotBlocks,
+                                   static_cast<int>(m), hs);
+                hipLaunchKernelGGL(k_gemv_sub<CPLX>, dim3(grid(n)), dim3(kBlock), 0, st, Vb, n, nv, hs, w);
+            }
+        }
+        LS_HIP_CHECK(hipGetLastError());
+        const double bnext = std::sqrt(dot(w, w).x);
+        alpha.push_back(a);
+        e0 = tridiag_lowest(alpha, beta);
+        resid = bnext * tridiag_last_component(alpha, beta, e0);
+        const double scale = std::max(1.0, std::fabs(e0));
+        if (o->tol > 0 && have_prev && std::fabs(e0 - prev) < o->tol * scale && resid < std::sqrt(o->tol) * scale) {
+            converged = true;
+            break;
+        }
+        prev = e0;
+        have_prev = true;
+        if (k + 1 < m) {
+            if (bnext == 0.0) break;
+            beta.push_back(bnext);
+            hipLaunchKernelGGL(k_div, dim3(grid(nd)), dim3(kBlock), 0, st,
+                               reinterpret_cast<double *>(Vb + static_cast<uint64_t>(k + 1) * n),
+                               reinterpret_cast<const double *>(w), nd, bnext);
+        }
+    }
+    LS_HIP_CHECK(hipStreamSynchronize(st));
+    if (o->alpha)
+        for (size_t k = 0; k < alpha.size(); ++k) o->alpha[k] = alpha[k];
+    if (o->beta)
+        for (size_t k = 0; k < beta.size(); ++k) o->beta[k] = beta[k];
+    if (e0_out) *e0_out = e0;
+    if (iters_out) *iters_out = static_cast<uint32_t>(alpha.size());
+    if (resid_out) *resid_out = resid;
+    return (o->tol > 0 && !converged) ? LS_WNOTCONV : LS_OK;
+}
+
+}  // namespace
+
+ls_status run_lanczos(const ls_operator *op, const ls_lanczos_opts *o, hipStream_t st, double *e0, uint32_t *iters,
+                      double *resid) {
+    if (op->is_complex) return lanczos_impl<true>(op, o, st, e0, iters, resid);
+    return lanczos_impl<false>(op, o, st, e0, iters, resid);
+}
+
+}  // namespace ls

@@ -1,0 +1,169 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ls_ed.h"
+
+namespace ls {
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const std::string &msg);
+const char *last_error();
+
+struct Error {
+    ls_status status;
+    std::string msg;
+};
+
+#define LS_HIP_CHECK(expr)                                                            \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            throw ::ls::Error{LS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define LS_REQUIRE(cond, msg)                                                         \
+    do {                                                                              \
+        if (!(cond)) throw ::ls::Error{LS_EINVAL, (msg)};                             \
+    } while (0)
+
+// ---------------------------------------------------------------- group plan
+//
+// The group is split as G = union over p in P of (Z x T) o p, where
+//   T = all translations of an lx-by-ly block layout of the sites
+//       (site = x + lx*y; a ring is lx = N, ly = 1; no structure: 1 x 1),
+//   Z = {identity, global spin flip F} when F is in G, else {identity},
+//   P = one representative per right coset.
+// An element is addressed by the code ((p * |T|) + t) * |Z| + f, with
+// t = a + lx*b for the translation (x, y) -> (x+a, y+b).  On the device a
+// coset representative is applied once (identity, full bit reversal, or a
+// Benes network), the translations are then walked with shifts, and the
+// flip partner of every image is v ^ full.
+
+constexpr int kMaxStages = 11;
+
+enum CosetKind : uint32_t { kCosetIdentity = 0, kCosetReverse = 1, kCosetBenes = 2 };
+
+struct CosetRep {
+    uint32_t kind;      // CosetKind
+    uint32_t flip;      // 1: invert all spins after the permutation
+    uint64_t masks[kMaxStages];
+};
+
+enum ChiMode : int { kChiTrivial = 0, kChiReal = 1, kChiComplex = 2 };
+
+struct GroupPlan {
+    uint32_t n_sites = 0;
+    uint32_t n_elements = 0;
+    uint32_t lx = 1, ly = 1;        // translation layout (1 x 1 = none)
+    uint32_t pair_flip = 0;         // Z contains F
+    uint32_t n_stages = 0;          // 9 for N <= 32, else 11
+    uint64_t full = 0;              // low N bits set
+    uint64_t col0 = 0;              // bits of column x = 0 of every row
+    int chi_mode = kChiTrivial;
+    std::vector<CosetRep> cosets;   // P
+    std::vector<double> chi;        // [n_elements][2] by code
+    std::vector<uint32_t> chi_one;  // bitset by code: chi == 1
+    std::vector<int32_t> code_to_index;  // code -> index in the user's list
+};
+
+// Validates the descriptor and compiles the plan.  Throws Error.
+GroupPlan compile_group(const ls_sector_desc &d);
+
+// Route a bit permutation (bit i -> bit dest[i]) on n = 32 or 64 wires into
+// Benes delta-swap masks; returns the number of stages (2 log2 n - 1).
+int benes_route(const std::vector<int> &dest, int n, uint64_t *masks);
+
+// Host reference application of a routed network (used for self-checks).
+uint64_t benes_apply_host(uint64_t x, const uint64_t *masks, int n_stages, int n);
+
+// ---------------------------------------------------------------- device views
+
+struct PlanDev {
+    uint32_t n_sites, lx, ly, n_trans;
+    uint32_t n_cosets, pair_flip, n_stages, n_elements;
+    uint64_t full, col0;
+    const CosetRep *cosets;     // device
+    const double2 *chi;         // device, by code
+    const uint32_t *chi_one;    // device bitset, by code
+};
+
+enum LookupMode : uint32_t { kLookupSearch = 0, kLookupRank = 1, kLookupIdentity = 2 };
+
+struct SearchDev {
+    uint32_t mode;      // LookupMode
+    uint32_t bits;      // bucket bits
+    uint32_t shift;     // bucket = (key - kmin) >> shift
+    int32_t weight;     // for rank / identity validation
+    uint32_t n_sites;
+    uint32_t pad_;
+    uint64_t dim;
+    uint64_t kmin, kmax;
+    const uint64_t *reps;       // device [dim]
+    const uint32_t *buckets;    // device [2^bits + 1]
+    const uint64_t *binom;      // device [65][65]
+};
+
+}  // namespace ls
+
+// ---------------------------------------------------------------- handles
+
+struct ls_basis {
+    ls::GroupPlan plan;
+    std::vector<uint16_t> perm_copy;   // the descriptor's group, [nG][N]
+    std::vector<uint8_t> flip_copy;    // [nG]
+    int32_t weight = -1;
+    uint64_t dim = 0;
+    int device = 0;
+    // device memory
+    uint64_t *d_reps = nullptr;
+    uint16_t *d_stab = nullptr;
+    uint32_t *d_buckets = nullptr;
+    uint64_t *d_binom = nullptr;
+    ls::CosetRep *d_cosets = nullptr;
+    double2 *d_chi = nullptr;
+    uint32_t *d_chi_one = nullptr;
+    ls::PlanDev plan_dev{};
+    ls::SearchDev search_dev{};
+};
+
+struct ls_term_dev {
+    double re, im;          // coefficient, already conjugated for the pull form
+    uint64_t sel, val, flip, sign;
+};
+
+struct ls_operator {
+    const ls_basis *basis = nullptr;
+    bool is_complex = false;
+    uint32_t n_diag = 0, n_off = 0;
+    ls_term_dev *d_terms = nullptr;     // diagonal terms first, then off-diagonal
+    int *d_error = nullptr;             // device error flag
+    std::vector<ls_term_dev> host_terms;
+};
+
+namespace ls {
+
+// basis.hip
+void build_basis(ls_basis *b, hipStream_t stream);
+void launch_state_info(const ls_basis *b, uint64_t n, const uint64_t *states, uint64_t *reps,
+                       double *chi, double *norm, hipStream_t stream);
+void launch_index_lookup(const ls_basis *b, uint64_t n, const uint64_t *keys, int64_t *index,
+                         hipStream_t stream);
+
+// terms.cpp
+void compile_terms(const ls_basis *b, uint32_t n_terms, const ls_term *terms, ls_operator *op);
+
+// matvec.hip
+void launch_matvec(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t stream);
+
+// lanczos.hip
+ls_status run_lanczos(const ls_operator *op, const ls_lanczos_opts *o, hipStream_t stream,
+                      double *e0, uint32_t *iters, double *resid);
+
+}  // namespace ls

@@ -1,0 +1,193 @@
+// Device helpers: group action, orbit search and stateToIndex.
+//
+// Every lane owns one basis state and walks the whole group in registers:
+// for each coset representative p (identity, full bit reversal or a Benes
+// network of delta swaps), the translated images tau_t(p(s)) are produced
+// by shifts (x-rotation of every row, rotation of the word by one row), and
+// with spin inversion in the group each image v is paired with v ^ full.
+// The representative is the minimum image (the orbit minimum).
+#pragma once
+
+#include "ls_internal.hpp"
+
+namespace ls {
+
+// Structure kinds the kernels are specialised for.
+enum OrbitKind : int {
+    kOrbitGeneric = 0,   // runtime lx, ly (ring, torus, or no translations)
+    kOrbitRing32 = 1,    // N <= 32 ring: all rotations from one funnel shift each
+};
+
+template <typename W>
+__device__ __forceinline__ W benes_apply(W x, const uint64_t *m) {
+    if constexpr (sizeof(W) == 4) {
+        constexpr int dl[9] = {16, 8, 4, 2, 1, 2, 4, 8, 16};
+#pragma unroll
+        for (int s = 0; s < 9; ++s) {
+            const W t = ((x >> dl[s]) ^ x) & static_cast<W>(m[s]);
+            x ^= t ^ (t << dl[s]);
+        }
+    } else {
+        constexpr int dl[11] = {32, 16, 8, 4, 2, 1, 2, 4, 8, 16, 32};
+#pragma unroll
+        for (int s = 0; s < 11; ++s) {
+            const W t = ((x >> dl[s]) ^ x) & static_cast<W>(m[s]);
+            x ^= t ^ (t << dl[s]);
+        }
+    }
+    return x;
+}
+
+template <typename W>
+__device__ __forceinline__ W bit_reverse(W x, uint32_t n) {
+    if constexpr (sizeof(W) == 4)
+        return static_cast<W>(__builtin_bitreverse32(static_cast<uint32_t>(x)) >> (32u - n));
+    else
+        return static_cast<W>(__builtin_bitreverse64(static_cast<uint64_t>(x)) >> (64u - n));
+}
+
+template <typename W>
+__device__ __forceinline__ W apply_coset(const CosetRep &c, W s, const PlanDev &P) {
+    W u;
+    if (c.kind == kCosetIdentity)
+        u = s;
+    else if (c.kind == kCosetReverse)
+        u = bit_reverse<W>(s, P.n_sites);
+    else
+        u = benes_apply<W>(s, c.masks);
+    if (c.flip) u ^= static_cast<W>(P.full);
+    return u;
+}
+
+// (x, y) -> (x + 1, y) for every row of an lx-wide layout
+template <typename W>
+__device__ __forceinline__ W xrot(W v, const PlanDev &P) {
+    const W c0 = static_cast<W>(P.col0), full = static_cast<W>(P.full);
+    return ((v << 1) & ~c0 & full) | ((v >> (P.lx - 1)) & c0);
+}
+
+// (x, y) -> (x, y + 1): rotate the N-bit word by one row
+template <typename W>
+__device__ __forceinline__ W yrot(W v, const PlanDev &P) {
+    return ((v << P.lx) | (v >> (P.n_sites - P.lx))) & static_cast<W>(P.full);
+}
+
+__device__ __forceinline__ bool chi_is_one(const PlanDev &P, uint32_t code) {
+    return (P.chi_one[code >> 5] >> (code & 31)) & 1u;
+}
+
+// Visit every group image of s: f(v, code).  Returning false from f stops.
+template <typename W, int KIND, typename F>
+__device__ __forceinline__ void for_each_image(const PlanDev &P, W s, F &&f) {
+    const uint32_t nz = P.pair_flip ? 2u : 1u;
+    const W full = static_cast<W>(P.full);
+    for (uint32_t p = 0; p < P.n_cosets; ++p) {
+        const CosetRep c = P.cosets[p];
+        W u = apply_coset<W>(c, s, P);
+        if constexpr (KIND == kOrbitRing32) {
+            // u doubled into 64 bits: rotating right by t is one funnel shift
+            const uint32_t n = P.n_sites;
+            const uint64_t uu = static_cast<uint64_t>(u) | (static_cast<uint64_t>(u) << n);
+            const uint32_t lo = static_cast<uint32_t>(uu), hi = static_cast<uint32_t>(uu >> 32);
+            for (uint32_t t = 0; t < n; ++t) {
+                const W v = static_cast<W>(__builtin_amdgcn_alignbit(hi, lo, t)) & full;
+                // right rotation by t is the translation a = (n - t) mod n
+                const uint32_t a = t == 0 ? 0u : n - t;
+                const uint32_t base = (p * n + a) * nz;
+                if (!f(v, base)) return;
+                if (P.pair_flip && !f(static_cast<W>(v ^ full), base + 1)) return;
+            }
+        } else {
+            for (uint32_t b = 0; b < P.ly; ++b) {
+                W v = u;
+                for (uint32_t a = 0; a < P.lx; ++a) {
+                    const uint32_t base = (p * P.n_trans + a + P.lx * b) * nz;
+                    if (!f(v, base)) return;
+                    if (P.pair_flip && !f(static_cast<W>(v ^ full), base + 1)) return;
+                    if (a + 1 < P.lx) v = xrot<W>(v, P);
+                }
+                if (b + 1 < P.ly) u = yrot<W>(u, P);
+            }
+        }
+    }
+}
+
+// Orbit minimum; with TRACK also the code of the first element reaching it.
+template <typename W, int KIND, bool TRACK>
+__device__ __forceinline__ W orbit_min(const PlanDev &P, W s, uint32_t &code) {
+    W best = s;
+    uint32_t arg = 0;
+    if constexpr (!TRACK && KIND == kOrbitRing32) {
+        // plain min, two images per rotation with spin inversion
+        const W full = static_cast<W>(P.full);
+        const uint32_t n = P.n_sites;
+        for (uint32_t p = 0; p < P.n_cosets; ++p) {
+            const CosetRep c = P.cosets[p];
+            const W u = apply_coset<W>(c, s, P);
+            const uint64_t uu = static_cast<uint64_t>(u) | (static_cast<uint64_t>(u) << n);
+            const uint32_t lo = static_cast<uint32_t>(uu), hi = static_cast<uint32_t>(uu >> 32);
+            if (P.pair_flip) {
+                for (uint32_t t = 0; t < n; ++t) {
+                    const W v = static_cast<W>(__builtin_amdgcn_alignbit(hi, lo, t)) & full;
+                    best = min(best, min(v, static_cast<W>(v ^ full)));
+                }
+            } else {
+                for (uint32_t t = 0; t < n; ++t) {
+                    const W v = static_cast<W>(__builtin_amdgcn_alignbit(hi, lo, t)) & full;
+                    best = min(best, v);
+                }
+            }
+        }
+    } else {
+        for_each_image<W, KIND>(P, s, [&](W v, uint32_t c) {
+            if constexpr (TRACK) {
+                if (v < best) { best = v; arg = c; }
+            } else {
+                best = v < best ? v : best;
+            }
+            return true;
+        });
+    }
+    code = arg;
+    return best;
+}
+
+// Binomial coefficient table [65][65] in device memory.
+__device__ __forceinline__ uint64_t binom(const uint64_t *t, uint32_t n, uint32_t k) {
+    return t[n * 65u + k];
+}
+
+// Position of s among the weight-w bitstrings in increasing order.
+__device__ __forceinline__ uint64_t colex_rank(uint64_t s, const uint64_t *tab) {
+    uint64_t r = 0;
+    uint32_t k = 1;
+    while (s) {
+        const uint32_t p = static_cast<uint32_t>(__builtin_ctzll(s));
+        r += binom(tab, p, k);
+        ++k;
+        s &= s - 1;
+    }
+    return r;
+}
+
+// stateToIndex: bucket of the key's high bits, then binary search.
+__device__ __forceinline__ int64_t lookup_index(const SearchDev &S, uint64_t key) {
+    if (S.mode == kLookupIdentity)
+        return (S.n_sites == 64 || (key >> S.n_sites) == 0) ? static_cast<int64_t>(key) : -1;
+    if (S.mode == kLookupRank) {
+        if ((S.n_sites < 64 && (key >> S.n_sites) != 0) || __builtin_popcountll(key) != S.weight) return -1;
+        return static_cast<int64_t>(colex_rank(key, S.binom));
+    }
+    if (key < S.kmin || key > S.kmax) return -1;
+    const uint64_t b = (key - S.kmin) >> S.shift;
+    uint32_t lo = S.buckets[b];
+    const uint32_t end = S.buckets[b + 1];
+    uint32_t hi = end;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (S.reps[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return (lo < end && S.reps[lo] == key) ? static_cast<int64_t>(lo) : -1;
+}
+
+}  // namespace ls

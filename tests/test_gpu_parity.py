@@ -1,0 +1,267 @@
+"""GPU path (through the C ABI) against the oracle.
+
+Bit-exact: representatives, stabilizers, state_info representatives and
+norms, stateToIndex.  FP64: matvec within 1e-12 (relative L2 and max-abs
+relative to ||y||_inf), Lanczos energies within 1e-10.  Full-size sectors
+are checked on sampled rows that the oracle computes one by one and through
+properties that hold at any size.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import physics_ref as ref
+from workloads import configs, lattice, rng, terms
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2308_16712_amd as ls  # noqa: E402
+
+MATVEC_TOL = 1e-12
+LANCZOS_TOL = 1e-10
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _u64(t):
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+def _dev_u64(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).cuda()
+
+
+def _sector(name, n, w, g, bonds):
+    return configs.sector_from_arrays(name, n, w, g.perm, g.flip, g.chi, terms.heisenberg_terms(bonds))
+
+
+def _small_sectors():
+    out = [configs.ring16_u1()]
+    for n in (16, 18, 20):
+        out.append(_sector(f"ringD{n}_0pp", n, n // 2, lattice.ring_group(n, 0, 1, 1), lattice.ring_bonds(n, 1.0, 0.3)))
+    out.append(_sector("ringD18_pimm", 18, 9, lattice.ring_group(18, 9, -1, -1), lattice.ring_bonds(18, 1.0, 0.2)))
+    out.append(_sector("ringD24_0pp", 24, 12, lattice.ring_group(24, 0, 1, 1), lattice.ring_bonds(24, 1.0, 0.0)))
+    out.append(_sector("ringT20_k3", 20, 10, lattice.ring_group(20, 3), lattice.ring_bonds(20, 1.0, 0.45)))
+    out.append(_sector("ringTZ18_k5", 18, 9, lattice.ring_group(18, 5, 0, -1), lattice.ring_bonds(18, 1.0, 0.1)))
+    out.append(_sector("ringT15_w6_k4", 15, 6, lattice.ring_group(15, 4), lattice.ring_bonds(15, 1.0, 0.3)))
+    out.append(_sector("ring32_w4_D", 32, 4, lattice.ring_group(32, 0, 1), lattice.ring_bonds(32, 1.0, 0.2)))
+    out.append(_sector("torus4x4_full", 16, 8, lattice.torus_group(4, 4, 0, 0, "full", None, 1),
+                       lattice.torus_bonds(4, 4, 1.0, 0.5)))
+    out.append(_sector("torus4x4_k12", 16, 8, lattice.torus_group(4, 4, 1, 2, "none"),
+                       lattice.torus_bonds(4, 4, 1.0, 0.5)))
+    out.append(_sector("torus4x6_full", 24, 12, lattice.torus_group(6, 4, 0, 0, "full", None, 1),
+                       lattice.torus_bonds(6, 4, 1.0, 0.35)))
+    out.append(_sector("torus3x4_mx-", 12, 6, lattice.torus_group(4, 3, 0, 0, "c2v", {"mx": -1}, 1),
+                       lattice.torus_bonds(4, 3, 1.0, 0.5)))
+    perm = [5, 2, 9, 0, 11, 7, 1, 10, 3, 8, 6, 4]
+    out.append(_sector("scrambled12_k2", 12, 6, lattice.relabel_group(lattice.ring_group(12, 2), perm),
+                       lattice.relabel_bonds(lattice.ring_bonds(12, 1.0, 0.3), perm)))
+    perm16 = [(7 * i + 3) % 16 for i in range(16)]
+    out.append(_sector("scrambled4x4_full", 16, 8,
+                       lattice.relabel_group(lattice.torus_group(4, 4, 0, 0, "full", None, 1), perm16),
+                       lattice.relabel_bonds(lattice.torus_bonds(4, 4, 1.0, 0.5), perm16)))
+    out.append(_sector("ringT10_noU1_k1", 10, -1, lattice.ring_group(10, 1), lattice.ring_bonds(10, 1.0, 0.0)))
+    out.append(_sector("trivial11_noU1", 11, -1, lattice.trivial_group(11), lattice.ring_bonds(11, 1.0, 0.2)))
+    # 64-bit words
+    out.append(_sector("ring40_w3_D", 40, 3, lattice.ring_group(40, 0, 1), lattice.ring_bonds(40, 1.0, 0.25)))
+    out.append(_sector("ring33_w4_k5", 33, 4, lattice.ring_group(33, 5), lattice.ring_bonds(33, 1.0, 0.0)))
+    out.append(_sector("torus6x6_w3_full", 36, 3, lattice.torus_group(6, 6), lattice.torus_bonds(6, 6, 1.0, 0.5)))
+    out.append(_sector("torus6x6_w4_k10", 36, 4, lattice.torus_group(6, 6, 1, 0, "none"),
+                       lattice.torus_bonds(6, 6, 1.0, 0.5)))
+    return out
+
+
+SMALL = _small_sectors()
+_CACHE = {}
+
+
+def _built(sec):
+    if sec.name not in _CACHE:
+        _say(f"[gpu] build basis {sec.name}")
+        P = oracle.Problem(sec)
+        reps, stab = oracle.enumerate_basis(P)
+        b = ls.ls_basis_build(sec)
+        op = ls.ls_operator_create(b, sec.terms)
+        _CACHE[sec.name] = (P, reps, stab, b, op)
+    return _CACHE[sec.name]
+
+
+@pytest.mark.parametrize("sec", SMALL, ids=lambda s: s.name)
+def test_basis_bit_exact(sec):
+    P, reps, stab, b, op = _built(sec)
+    assert b.dim == len(reps)
+    g_reps, g_stab = b.copy()
+    assert np.array_equal(_u64(g_reps), reps)
+    assert np.array_equal(g_stab.cpu().numpy().view(np.uint16), stab)
+    assert b.is_real == bool(np.all(sec.group.chi[:, 1] == 0))
+
+
+@pytest.mark.parametrize("sec", SMALL, ids=lambda s: s.name)
+def test_state_info_bit_exact(sec):
+    P, reps, stab, b, op = _built(sec)
+    n = sec.n_sites
+    st = rng.counter_u64(99, np.arange(3000, dtype=np.uint64))
+    mask = np.uint64((1 << n) - 1) if n < 64 else np.uint64(~0 & ((1 << 64) - 1))
+    states = np.concatenate([
+        st & mask,                                     # any weight
+        reps[: 500],                                   # representatives
+        np.array([0, int(mask), 1 << (n - 1)], dtype=np.uint64),
+        (st[:50] | np.uint64(1 << n)) if n < 64 else st[:0],   # bits at or above N
+    ]).astype(np.uint64)
+    o_rep, o_chi, o_norm = oracle.state_info(P, states)
+    g_rep, g_chi, g_norm = b.state_info(_dev_u64(states))
+    assert np.array_equal(_u64(g_rep), o_rep)
+    assert np.array_equal(g_norm.cpu().numpy(), o_norm)          # bit-exact
+    gc = g_chi.cpu().numpy()
+    assert np.allclose(gc[:, 0] + 1j * gc[:, 1], o_chi, atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("sec", SMALL, ids=lambda s: s.name)
+def test_index_lookup_bit_exact(sec):
+    P, reps, stab, b, op = _built(sec)
+    n = sec.n_sites
+    mask = (1 << n) - 1
+    extra = rng.counter_u64(7, np.arange(2000, dtype=np.uint64)) & np.uint64(mask)
+    keys = np.concatenate([reps, extra, np.array([0, mask], dtype=np.uint64)]).astype(np.uint64)
+    if n < 63:
+        keys = np.concatenate([keys, np.array([1 << (n + 1), (1 << 63) + 5], dtype=np.uint64)])
+    want = oracle.index_lookup(reps, keys)
+    got = b.index_lookup(_dev_u64(keys)).cpu().numpy()
+    assert np.array_equal(got, want)
+
+
+def _compare(y_gpu, y_ref):
+    scale = max(np.max(np.abs(y_ref)), 1e-300)
+    rel_l2 = np.linalg.norm(y_gpu - y_ref) / max(np.linalg.norm(y_ref), 1e-300)
+    assert rel_l2 <= MATVEC_TOL, rel_l2
+    assert np.max(np.abs(y_gpu - y_ref)) <= MATVEC_TOL * scale
+
+
+@pytest.mark.parametrize("nrhs", [1, 3, 4, 11])
+@pytest.mark.parametrize("sec", SMALL, ids=lambda s: s.name)
+def test_matvec_parity(sec, nrhs):
+    P, reps, stab, b, op = _built(sec)
+    d = len(reps)
+    if d == 0:
+        return
+    if nrhs > 1 and d > 20000:
+        pytest.skip("multi-RHS checked on the smaller sectors")
+    x = rng.vector(sec.seed + 17 + nrhs, d, nrhs, complex_=op.is_complex)
+    y_ref = oracle.matvec(P, reps, stab, x)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    y = op.matvec(xt).cpu().numpy()
+    _compare(y, y_ref)
+
+
+def test_matvec_empty_and_errors():
+    sec = SMALL[0]
+    P, reps, stab, b, op = _built(sec)
+    x = torch.zeros(b.dim, dtype=torch.float64, device="cuda")
+    with pytest.raises(ls.LSError):
+        op.matvec(x, x)                       # overlapping
+    with pytest.raises(TypeError):
+        op.matvec(x.to(torch.complex128))
+    # empty sector: k != 0 with reflection -1 at tiny N may be empty; use a w=0 ring with k=1
+    g = lattice.ring_group(6, 1)
+    e = ls.ls_basis_build(configs.sector_from_arrays("empty", 6, 0, g.perm, g.flip, g.chi,
+                                                     terms.heisenberg_terms(lattice.ring_bonds(6))))
+    assert e.dim == 0
+
+
+def test_operator_validation():
+    sec = SMALL[1]
+    P, reps, stab, b, op = _built(sec)
+    good = sec.terms.copy()
+    bad = good.copy()
+    bad[len(bad) - 1]["re"] *= 2.0            # breaks Hermiticity
+    with pytest.raises(ls.LSError):
+        ls.ls_operator_create(b, bad)
+    one_bond = terms.heisenberg_terms([(0, 1, 1.0)])   # not translation invariant
+    with pytest.raises(ls.LSError):
+        ls.ls_operator_create(b, one_bond)
+    nonconserving = terms.make_terms([(1.0, 1, 1, 1, 0)])  # sigma^- alone changes the weight
+    with pytest.raises(ls.LSError):
+        ls.ls_operator_create(b, nonconserving)
+
+
+@pytest.mark.parametrize("sec", [SMALL[0], SMALL[6], SMALL[3]], ids=lambda s: s.name)
+def test_lanczos_parity(sec):
+    P, reps, stab, b, op = _built(sec)
+    d = len(reps)
+    m = 30
+    v0 = rng.vector(1, d, complex_=op.is_complex)
+    want = oracle.lanczos(lambda v: oracle.matvec(P, reps, stab, v), v0, m)
+    got = op.lanczos(m, seed=1)               # seeded start on the device
+    assert got["iters"] == want["iters"]
+    assert abs(got["e0"] - want["e0"]) <= LANCZOS_TOL * max(1.0, abs(want["e0"]))
+    assert np.allclose(got["alpha"], want["alpha"], atol=1e-10)
+    assert np.allclose(got["beta"], want["beta"], atol=1e-10)
+    got2 = op.lanczos(m, v0=torch.from_numpy(v0).cuda())
+    assert abs(got2["e0"] - want["e0"]) <= LANCZOS_TOL * max(1.0, abs(want["e0"]))
+
+
+def test_lanczos_converges_cfg1():
+    sec = SMALL[0]
+    P, reps, stab, b, op = _built(sec)
+    res = op.lanczos(200, tol=1e-12, seed=3)
+    assert res["converged"]
+    assert abs(res["e0"] - (-7.142296360616781)) < 1e-10
+
+
+# ----------------------------------------------------------------- full sizes
+
+def _full_size_checks(sec, dim_expected, n_sample=300, n_rows=150):
+    _say(f"[gpu] full-size {sec.name}")
+    b = ls.ls_basis_build(sec)
+    assert b.dim == dim_expected
+    reps_t, stab_t = b.copy()
+    reps = _u64(reps_t)
+    assert np.all(np.diff(reps.astype(np.uint64)) > 0)
+    P = oracle.Problem(sec)
+    pick = (rng.counter_u64(5, np.arange(n_sample, dtype=np.uint64)) % np.uint64(b.dim)).astype(np.int64)
+    pick = np.unique(np.concatenate([pick, [0, b.dim - 1]]))
+    o_rep, o_chi, o_norm = oracle.state_info(P, reps[pick])
+    assert np.array_equal(o_rep, reps[pick])                   # each is its own orbit minimum
+    assert np.all(o_norm > 0)                                  # and in the sector
+    stab = stab_t.cpu().numpy().view(np.uint16)[pick].astype(np.float64)
+    assert np.array_equal(np.sqrt(stab / sec.group.size), o_norm)
+    # index of sampled representatives
+    idx = b.index_lookup(_dev_u64(reps[pick])).cpu().numpy()
+    assert np.array_equal(idx, pick)
+    # matvec on rows sampled by the oracle, x keyed by basis state
+    op = ls.ls_operator_create(b, sec.terms)
+    x = rng.state_values(11, reps, complex_=op.is_complex)
+    y = op.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
+    rows = pick[:n_rows]
+    for i in rows:
+        nb, coef = oracle.get_row(P, int(reps[i]))
+        yi = np.sum(coef * rng.state_values(11, nb, complex_=op.is_complex))
+        assert abs(y[i] - yi) <= MATVEC_TOL * max(1.0, np.max(np.abs(y[rows]))), (i, y[i], yi)
+    # Hermiticity at full size
+    u = rng.vector(21, b.dim, complex_=op.is_complex)
+    v = rng.vector(22, b.dim, complex_=op.is_complex)
+    hu = op.matvec(torch.from_numpy(u).cuda()).cpu().numpy()
+    hv = op.matvec(torch.from_numpy(v).cuda()).cpu().numpy()
+    lhs, rhs = np.vdot(u, hv), np.vdot(hu, v)
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(hv)
+    return b, op
+
+
+def test_full_ring32_symmetric():
+    sec = configs.ring32_symmetric()
+    dim = ref.character_dimension(sec.group, 16)
+    assert dim == 4707969
+    _full_size_checks(sec, dim)
+
+
+def test_full_square6x6_j1j2():
+    sec = configs.square_j1j2()
+    dim = ref.character_dimension(sec.group, 18)
+    assert dim == 15804956
+    _full_size_checks(sec, dim, n_sample=200, n_rows=60)

@@ -74,8 +74,10 @@ def close_group(n: int, generators: Sequence[Tuple[Sequence[int], int, complex]]
     perm = np.array([e[0] for e in elems], dtype=np.uint16)
     flip = np.array([e[1] for e in elems], dtype=np.uint8)
     chi = np.array([[c.real, c.imag] for c in chis], dtype=np.float64)
-    # Snap characters that are exactly +-1 / +-i up to rounding of products.
-    chi[np.abs(chi) < 1e-15] = 0.0
+    # Components within rounding of 0 or +-1 are set exactly, so characters
+    # that are fourth roots of unity (k = 0, N/4, N/2, ...) are exact.
+    for target in (-1.0, 0.0, 1.0):
+        chi[np.abs(chi - target) < 1e-12] = target
     return Group(n, perm, flip, chi)
 
 
