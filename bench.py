@@ -1,0 +1,200 @@
+"""Benchmark: H matrix elements applied per second on one MI355X.
+
+Workload (default): square-lattice J1-J2 Heisenberg model on a 6x6 torus,
+J1 = 1, J2 = 0.5, Sz = 0, k = (0,0), full C4v x translations x spin
+inversion (576 elements), 15,804,956 representatives, FP64 vectors.
+
+A step is one on-the-fly product y = H x over the whole sector (getRow,
+orbit minimum, stateToIndex and accumulation for every row); the basis is
+built once before timing (its build time is reported beside the metric).
+Element applications per step = (off-diagonal terms acting on each row,
+summed over rows) + one diagonal element per row.
+
+Prints one JSON line.  ``--gpus`` > 1 is not supported (one GPU only).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12            # B/s, MI355X HBM3E
+# Integer/logic VALU lane-operations per second: 256 CUs x 4 SIMDs x 16
+# lanes per clock x 2.4 GHz (one 32-bit op per lane per clock).
+PEAK_VALU = 256 * 64 * 2.4e9
+
+
+def workload(name: str):
+    from workloads import configs
+    if name == "square6x6":
+        return configs.square_j1j2(), "square-lattice J1-J2 6x6 torus (J2=0.5), Sz=0, k=0, C4v x T x Z2 (576)"
+    if name == "ring32":
+        return configs.ring32_symmetric(), "Heisenberg ring N=32, Sz=0, k=0, R=+1, Z=+1 (128)"
+    if name == "ring16":
+        return configs.ring16_u1(), "Heisenberg ring N=16, Sz=0, no lattice symmetry"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def count_elements(reps, term_table):
+    """(off-diagonal element applications, rows) of one product."""
+    import numpy as np
+    off = term_table[term_table["flip"] != 0]
+    n_off = 0
+    for lo in range(0, len(reps), 1 << 22):
+        r = reps[lo: lo + (1 << 22)]
+        for t in off:
+            n_off += int(np.count_nonzero((r & np.uint64(t["sel_mask"])) == np.uint64(t["sel_value"])))
+    return n_off, len(reps)
+
+
+def cpu_baseline(sector, budget_s: float):
+    """The oracle's getRow timed on the host: rows drawn by the oracle itself
+    (seeded random states of the sector's weight -> their representatives
+    in the sector), processed until the time budget is spent."""
+    import numpy as np
+    import oracle
+    from workloads import rng
+    P = oracle.Problem(sector)
+    n = sector.n_sites
+    w = sector.weight
+    # seeded random weight-w states
+    states = []
+    st = rng.Stream(2024)
+    while len(states) < 4096:
+        bits = list(range(n))
+        for i in range(n - 1, 0, -1):
+            j = st.randint(0, i + 1)
+            bits[i], bits[j] = bits[j], bits[i]
+        states.append(sum(1 << b for b in bits[:w]))
+    reps, chi, norm = oracle.state_info(P, np.array(states, dtype=np.uint64))
+    rows = np.unique(reps[norm > 0])
+    off = sector.terms[sector.terms["flip"] != 0]
+    t0 = time.perf_counter()
+    elems = 0
+    done = 0
+    for r in rows:
+        oracle.get_row(P, int(r))
+        acting = int(np.count_nonzero((np.uint64(r) & off["sel_mask"]) == off["sel_value"]))
+        elems += acting + 1
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": elems / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"getRow of {done} representatives (drawn by the oracle from seeded random "
+                      f"weight-{w} states), {elems} element applications in {dt:.1f} s, single thread"}
+
+
+def traffic_record(name: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_matvec_{name}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ("matvec.hip", "orbit.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2308_16712_amd", "csrc", f), "rb").read())
+    if rec.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="square6x6")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="run only a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; --gpus must be 1 (the multi-GPU design is described "
+              "but not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2308_16712_amd as ls
+    from workloads import rng
+
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8, "launches": 3}))
+        return
+
+    sector, desc = workload(args.workload)
+    print(f"[bench] building basis {args.workload}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    basis = ls.ls_basis_build(sector)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    op = ls.ls_operator_create(basis, sector.terms)
+    reps_t, _ = basis.copy()
+    reps = reps_t.cpu().numpy().view(np.uint64)
+    n_off, rows = count_elements(reps, sector.terms)
+    elements = n_off + rows
+    x = torch.from_numpy(rng.vector(sector.seed, basis.dim, complex_=op.is_complex)).cuda()
+    y = torch.empty_like(x)
+    print(f"[bench] dim={basis.dim} elements/step={elements} build={build_s:.3f}s", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        ls.ls_matvec(op, x, y)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        ls.ls_matvec(op, x, y)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    ms_per_step = wall * 1e3 / args.steps
+    value = elements * args.steps / wall
+
+    words = (sector.n_sites + 31) // 32
+    ops_per_launch = float(n_off) * sector.group.size * words
+    achieved_ops = ops_per_launch / (kernel_ms * 1e-3)
+    roof = {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TOP/s",
+            "frac": achieved_ops / PEAK_VALU, "traffic": traffic_record(args.workload),
+            "kernel": "k_matvec", "kernel_ms": kernel_ms,
+            "ops_model": f"{sector.group.size} group images x {words} word-min per off-diagonal element"}
+    alg_bytes = rows * (8 + 8 + 8 + 2) + n_off * (8 + 8 + 2)
+    out = {
+        "metric": "H matrix elements/s", "value": value, "unit": "elements/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": desc, "dim": basis.dim, "elements_per_step": elements,
+                   "group_order": sector.group.size, "nrhs": 1},
+        "roofline": roof,
+        "hbm_algorithmic_gbps": alg_bytes / (kernel_ms * 1e-3) / 1e9,
+        "basis_build_s": build_s,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(sector, args.cpu_budget)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
