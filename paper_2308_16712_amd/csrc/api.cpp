@@ -43,6 +43,7 @@ void free_basis(ls_basis *b) {
     hipFree(b->d_cosets);
     hipFree(b->d_chi);
     hipFree(b->d_chi_one);
+    hipFree(b->d_pair_lut);
     delete b;
 }
 

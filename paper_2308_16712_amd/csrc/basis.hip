@@ -358,6 +358,14 @@ void build_basis(ls_basis *b, hipStream_t st) {
     pd.cosets = b->d_cosets;
     pd.chi = b->d_chi;
     pd.chi_one = b->d_chi_one;
+    pd.pair_lut = nullptr;
+    for (int a = 0; a < 8; ++a) pd.col_ge[a] = gp.col_ge[a];
+    if (gp.torus) {
+        LS_HIP_CHECK(hipMalloc(&b->d_pair_lut, gp.pair_lut.size() * sizeof(uint16_t)));
+        LS_HIP_CHECK(hipMemcpy(b->d_pair_lut, gp.pair_lut.data(), gp.pair_lut.size() * sizeof(uint16_t),
+                               hipMemcpyHostToDevice));
+        pd.pair_lut = b->d_pair_lut;
+    }
 
     // candidates
     uint64_t total;

@@ -312,6 +312,32 @@ GroupPlan compile_group(const ls_sector_desc &d) {
         }
     }
     P.chi_mode = trivial ? kChiTrivial : (real ? kChiReal : kChiComplex);
+
+    // Pruning table for tori: the top two rows of an image decide the order
+    // unless they tie, and for each pair of rows the x-rotation that makes
+    // the pair smallest is fixed by the pair alone.
+    if (P.lx >= 2 && P.lx <= 6 && P.ly >= 2 && P.cosets.size() <= 8 && P.cosets.size() * P.ly * nz <= 128) {
+        P.torus = true;
+        const uint32_t L = P.lx, rm = (1u << L) - 1u;
+        auto rot = [&](uint32_t v, uint32_t a) { return a == 0 ? v : (((v << a) | (v >> (L - a))) & rm); };
+        P.pair_lut.resize(1u << (2 * L));
+        for (uint32_t q = 0; q < (1u << (2 * L)); ++q) {
+            const uint32_t top = q >> L, second = q & rm;
+            uint32_t best = ~0u, arg = 0, ties = 0;
+            for (uint32_t a = 0; a < L; ++a) {
+                const uint32_t v = (rot(top, a) << L) | rot(second, a);
+                if (v < best) { best = v; arg = a; ties = 1; }
+                else if (v == best) ++ties;
+            }
+            P.pair_lut[q] = static_cast<uint16_t>((best << 4) | ((ties > 1 ? 1u : 0u) << 3) | arg);
+        }
+        for (uint32_t a = 0; a < L; ++a) {
+            const uint64_t rowpat = static_cast<uint64_t>(rm & ~((1u << a) - 1u));
+            uint64_t m = 0;
+            for (uint32_t y = 0; y < P.ly; ++y) m |= rowpat << (L * y);
+            P.col_ge[a] = m;
+        }
+    }
     if (P.chi_mode != kChiComplex) {
         // characters within 1e-9 of +-1 are used as exactly +-1
         for (uint32_t c = 0; c < ng; ++c) {

@@ -71,6 +71,12 @@ struct GroupPlan {
     std::vector<double> chi;        // [n_elements][2] by code
     std::vector<uint32_t> chi_one;  // bitset by code: chi == 1
     std::vector<int32_t> code_to_index;  // code -> index in the user's list
+    // Pruned torus search (lx <= 6, ly >= 2): for every pair of rows
+    // (top << lx | second) the smallest x-rotation of the pair, packed as
+    // key << 4 | ambiguous << 3 | argmin_a.
+    bool torus = false;
+    std::vector<uint16_t> pair_lut;
+    uint64_t col_ge[8] = {};        // bits with x >= a in every row
 };
 
 // Validates the descriptor and compiles the plan.  Throws Error.
@@ -92,6 +98,8 @@ struct PlanDev {
     const CosetRep *cosets;     // device
     const double2 *chi;         // device, by code
     const uint32_t *chi_one;    // device bitset, by code
+    const uint16_t *pair_lut;   // device, torus pruning table (or null)
+    uint64_t col_ge[8];
 };
 
 enum LookupMode : uint32_t { kLookupSearch = 0, kLookupRank = 1, kLookupIdentity = 2 };
@@ -129,6 +137,7 @@ struct ls_basis {
     ls::CosetRep *d_cosets = nullptr;
     double2 *d_chi = nullptr;
     uint32_t *d_chi_one = nullptr;
+    uint16_t *d_pair_lut = nullptr;
     ls::PlanDev plan_dev{};
     ls::SearchDev search_dev{};
 };
@@ -160,6 +169,7 @@ void launch_index_lookup(const ls_basis *b, uint64_t n, const uint64_t *keys, in
 void compile_terms(const ls_basis *b, uint32_t n_terms, const ls_term *terms, ls_operator *op);
 
 // matvec.hip
+uint32_t matvec_max_terms();   // the term table is staged in LDS
 void launch_matvec(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t stream);
 
 // lanczos.hip

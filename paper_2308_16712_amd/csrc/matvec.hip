@@ -1,7 +1,7 @@
 // y = H x on the fly, row by row (Section 5.3, first listing, "pull" form).
 //
-// One lane owns one row i of the sector Hamiltonian:
-//   r = reps[i];  acc = (sum of diagonal terms acting on r) * x_i
+// Row i of the sector Hamiltonian is generated from its representative r:
+//   acc = (sum of diagonal terms acting on r) * x_i
 //   for each off-diagonal term t acting on r (r & sel == val):
 //       s    = r ^ flip_t,  a = conj(c_t) (-1)^popcount(r & sign_t)
 //       rep  = orbit minimum of s, g* an element reaching it   (getRow)
@@ -12,8 +12,20 @@
 // Hermiticity of H; a neighbour whose orbit the projector annihilates is
 // absent from the basis and contributes nothing.
 //
+// Work layout.  Each off-diagonal term acts on only part of the rows (a
+// Heisenberg exchange term on about a quarter of them), so a loop over the
+// terms that is uniform across a wavefront would run the orbit search for
+// every term with most lanes idle.  Instead every lane walks its own list:
+// one loop iteration = one element (the lane's next acting term of its
+// current row); when a lane's row is exhausted it stores y_i and moves to
+// its next row.  A lane owns `rows_per_lane` rows strided by the total lane
+// count, so per-row differences in the number of acting terms average out.
+// The term table is staged in LDS once per workgroup.
+//
 // Right-hand sides: x and y are [dim][ld] row-major; a launch handles NR
 // consecutive columns, so the orbit search is shared by NR vectors.
+
+#include <algorithm>
 
 #include "orbit.hpp"
 
@@ -22,6 +34,7 @@ namespace ls {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kMaxLdsTerms = 1024;
 
 struct MatvecArgs {
     PlanDev plan;
@@ -30,6 +43,8 @@ struct MatvecArgs {
     const ls_term_dev *terms;
     uint32_t n_diag, n_terms;
     uint64_t dim;
+    uint64_t n_lanes;      // total lanes of the launch
+    uint32_t rows_per_lane;
     uint32_t ld;           // row stride of x and y in elements
     uint32_t col;          // first column handled by this launch
     const void *x;
@@ -40,63 +55,99 @@ __device__ __forceinline__ double sign_of(uint64_t v) {
     return (__builtin_popcountll(v) & 1) ? -1.0 : 1.0;
 }
 
+template <bool CPLX>
+struct Val;
+template <>
+struct Val<false> {
+    using T = double;
+};
+template <>
+struct Val<true> {
+    using T = double2;
+};
+
 // CHI: character mode; CPLX: complex vectors and coefficients.
 template <typename W, int KIND, int CHI, bool CPLX, int NR>
 __global__ void __launch_bounds__(kBlock) k_matvec(MatvecArgs a) {
-    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= a.dim) return;
-    const uint64_t r64 = a.search.reps[i];
-    const double st_i = static_cast<double>(a.stab[i]);
-
-    double dre = 0.0, dim_ = 0.0;
-    for (uint32_t t = 0; t < a.n_diag; ++t) {
-        const ls_term_dev T = a.terms[t];
-        if ((r64 & T.sel) != T.val) continue;
-        const double sg = sign_of(r64 & T.sign);
-        dre += sg * T.re;
-        if constexpr (CPLX) dim_ += sg * T.im;
+    using T = typename Val<CPLX>::T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    ls_term_dev *sterm = reinterpret_cast<ls_term_dev *>(smem);
+    for (uint32_t t = threadIdx.x; t < a.n_terms; t += kBlock) sterm[t] = a.terms[t];
+    // torus pruning tables follow the terms: pair table, col_ge masks
+    const size_t terms_bytes = (static_cast<size_t>(a.n_terms) * sizeof(ls_term_dev) + 15) & ~size_t(15);
+    uint16_t *slut = reinterpret_cast<uint16_t *>(smem + terms_bytes);
+    const uint32_t lut_n = KIND == kOrbitTorus ? (1u << (2 * a.plan.lx)) : 0u;
+    uint64_t *scol = reinterpret_cast<uint64_t *>(smem + terms_bytes + ((lut_n * 2u + 15u) & ~15u));
+    if constexpr (KIND == kOrbitTorus) {
+        for (uint32_t q = threadIdx.x; q < lut_n; q += kBlock) slut[q] = a.plan.pair_lut[q];
+        if (threadIdx.x < 8) scol[threadIdx.x] = a.plan.col_ge[threadIdx.x];
     }
+    __syncthreads();
 
-    if constexpr (!CPLX) {
-        const double *x = static_cast<const double *>(a.x);
-        double acc[NR];
+    const T *x = static_cast<const T *>(a.x);
+    T *y = static_cast<T *>(a.y);
+    const uint64_t lane = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+
+    uint64_t row = lane;
+    uint32_t k = 0;
+    if (row >= a.dim) return;
+
+    uint64_t r = 0;
+    double st_i = 1.0;
+    T acc[NR];
+    uint32_t t = a.n_diag;
+
+    auto begin_row = [&]() {
+        r = a.search.reps[row];
+        st_i = static_cast<double>(a.stab[row]);
+        double dre = 0.0, dim_ = 0.0;
+        for (uint32_t q = 0; q < a.n_diag; ++q) {
+            const ls_term_dev &D = sterm[q];
+            if ((r & D.sel) != D.val) continue;
+            const double sg = sign_of(r & D.sign);
+            dre += sg * D.re;
+            if constexpr (CPLX) dim_ += sg * D.im;
+        }
 #pragma unroll
-        for (int q = 0; q < NR; ++q) acc[q] = dre * x[i * a.ld + a.col + q];
-        for (uint32_t t = a.n_diag; t < a.n_terms; ++t) {
-            const ls_term_dev T = a.terms[t];
-            if ((r64 & T.sel) != T.val) continue;
-            const W s = static_cast<W>(r64 ^ T.flip);
-            uint32_t code;
-            const W rep = orbit_min<W, KIND, (CHI != kChiTrivial)>(a.plan, s, code);
-            const int64_t j = lookup_index(a.search, static_cast<uint64_t>(rep));
-            if (j < 0) continue;
-            double coef = sign_of(r64 & T.sign) * T.re *
-                          __dsqrt_rn(__ddiv_rn(static_cast<double>(a.stab[j]), st_i));
+        for (int q = 0; q < NR; ++q) {
+            const T v = x[row * a.ld + a.col + q];
+            if constexpr (CPLX) acc[q] = make_double2(dre * v.x - dim_ * v.y, dre * v.y + dim_ * v.x);
+            else acc[q] = dre * v;
+        }
+        t = a.n_diag;
+    };
+    begin_row();
+
+    for (;;) {
+        while (t < a.n_terms && (r & sterm[t].sel) != sterm[t].val) ++t;
+        if (t >= a.n_terms) {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) y[row * a.ld + a.col + q] = acc[q];
+            ++k;
+            row += a.n_lanes;
+            if (k >= a.rows_per_lane || row >= a.dim) break;
+            begin_row();
+            continue;
+        }
+        const ls_term_dev &Tm = sterm[t];
+        ++t;
+        const W s = static_cast<W>(r ^ Tm.flip);
+        uint32_t code;
+        W rep;
+        if constexpr (KIND == kOrbitTorus)
+            rep = torus_orbit_min<W, (CHI != kChiTrivial)>(a.plan, s, slut, scol, code);
+        else
+            rep = orbit_min<W, KIND, (CHI != kChiTrivial)>(a.plan, s, code);
+        const int64_t j = lookup_index(a.search, static_cast<uint64_t>(rep));
+        if (j < 0) continue;
+        const double f = sign_of(r & Tm.sign) * __dsqrt_rn(__ddiv_rn(static_cast<double>(a.stab[j]), st_i));
+        if constexpr (!CPLX) {
+            double coef = f * Tm.re;
             if constexpr (CHI == kChiReal) coef *= a.plan.chi[code].x;
 #pragma unroll
             for (int q = 0; q < NR; ++q) acc[q] = fma(coef, x[j * a.ld + a.col + q], acc[q]);
-        }
-        double *y = static_cast<double *>(a.y);
-#pragma unroll
-        for (int q = 0; q < NR; ++q) y[i * a.ld + a.col + q] = acc[q];
-    } else {
-        const double2 *x = static_cast<const double2 *>(a.x);
-        double2 acc[NR];
-#pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            const double2 v = x[i * a.ld + a.col + q];
-            acc[q] = make_double2(dre * v.x - dim_ * v.y, dre * v.y + dim_ * v.x);
-        }
-        for (uint32_t t = a.n_diag; t < a.n_terms; ++t) {
-            const ls_term_dev T = a.terms[t];
-            if ((r64 & T.sel) != T.val) continue;
-            const W s = static_cast<W>(r64 ^ T.flip);
-            uint32_t code;
-            const W rep = orbit_min<W, KIND, (CHI != kChiTrivial)>(a.plan, s, code);
-            const int64_t j = lookup_index(a.search, static_cast<uint64_t>(rep));
-            if (j < 0) continue;
-            const double sg = sign_of(r64 & T.sign) * __dsqrt_rn(__ddiv_rn(static_cast<double>(a.stab[j]), st_i));
-            double cre = sg * T.re, cim = sg * T.im;
+        } else {
+            double cre = f * Tm.re, cim = f * Tm.im;
             if constexpr (CHI != kChiTrivial) {
                 const double2 c = a.plan.chi[code];
                 const double tre = cre * c.x - cim * c.y;
@@ -110,20 +161,20 @@ __global__ void __launch_bounds__(kBlock) k_matvec(MatvecArgs a) {
                 acc[q].y = fma(cre, v.y, fma(cim, v.x, acc[q].y));
             }
         }
-        double2 *y = static_cast<double2 *>(a.y);
-#pragma unroll
-        for (int q = 0; q < NR; ++q) y[i * a.ld + a.col + q] = acc[q];
     }
 }
 
 template <typename W, int KIND, int CHI, bool CPLX>
 void launch_nr(const MatvecArgs &a, int nr, hipStream_t st) {
-    const dim3 grid(static_cast<uint32_t>((a.dim + kBlock - 1) / kBlock));
+    const dim3 grid(static_cast<uint32_t>(a.n_lanes / kBlock));
+    size_t lds = ((std::max<size_t>(a.n_terms, 1) * sizeof(ls_term_dev)) + 15) & ~size_t(15);
+    if (KIND == kOrbitTorus)
+        lds += (((size_t(1) << (2 * a.plan.lx)) * 2 + 15) & ~size_t(15)) + 64;
     switch (nr) {
-        case 8: hipLaunchKernelGGL((k_matvec<W, KIND, CHI, CPLX, 8>), grid, dim3(kBlock), 0, st, a); break;
-        case 4: hipLaunchKernelGGL((k_matvec<W, KIND, CHI, CPLX, 4>), grid, dim3(kBlock), 0, st, a); break;
-        case 2: hipLaunchKernelGGL((k_matvec<W, KIND, CHI, CPLX, 2>), grid, dim3(kBlock), 0, st, a); break;
-        default: hipLaunchKernelGGL((k_matvec<W, KIND, CHI, CPLX, 1>), grid, dim3(kBlock), 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_matvec<W, KIND, CHI, CPLX, 8>), grid, dim3(kBlock), lds, st, a); break;
+        case 4: hipLaunchKernelGGL((k_matvec<W, KIND, CHI, CPLX, 4>), grid, dim3(kBlock), lds, st, a); break;
+        case 2: hipLaunchKernelGGL((k_matvec<W, KIND, CHI, CPLX, 2>), grid, dim3(kBlock), lds, st, a); break;
+        default: hipLaunchKernelGGL((k_matvec<W, KIND, CHI, CPLX, 1>), grid, dim3(kBlock), lds, st, a); break;
     }
 }
 
@@ -136,6 +187,8 @@ void launch_chi(const MatvecArgs &a, int chi, bool cplx, int nr, hipStream_t st)
 
 }  // namespace
 
+uint32_t matvec_max_terms() { return kMaxLdsTerms; }
+
 void launch_matvec(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t st) {
     const ls_basis *b = op->basis;
     if (b->dim == 0) return;
@@ -147,6 +200,14 @@ void launch_matvec(const ls_operator *op, uint32_t nrhs, const void *x, void *y,
     a.n_diag = op->n_diag;
     a.n_terms = op->n_diag + op->n_off;
     a.dim = b->dim;
+    // Rows per lane: enough lanes to fill 256 CUs x 4 SIMDs x 8 waves, and
+    // no more than 16 rows per lane.
+    const uint64_t fill = 256ull * 4 * 8 * 64;
+    uint32_t rpl = static_cast<uint32_t>(std::min<uint64_t>(16, std::max<uint64_t>(1, b->dim / fill)));
+    uint64_t lanes = (b->dim + rpl - 1) / rpl;
+    lanes = (lanes + kBlock - 1) / kBlock * kBlock;
+    a.n_lanes = lanes;
+    a.rows_per_lane = rpl;
     a.ld = nrhs;
     a.x = x;
     a.y = y;
@@ -160,9 +221,11 @@ void launch_matvec(const ls_operator *op, uint32_t nrhs, const void *x, void *y,
         a.col = col;
         if (gp.n_sites <= 32) {
             if (gp.ly == 1 && gp.lx == gp.n_sites) launch_chi<uint32_t, kOrbitRing32>(a, chi, cplx, nr, st);
+            else if (gp.torus) launch_chi<uint32_t, kOrbitTorus>(a, chi, cplx, nr, st);
             else launch_chi<uint32_t, kOrbitGeneric>(a, chi, cplx, nr, st);
         } else {
-            launch_chi<uint64_t, kOrbitGeneric>(a, chi, cplx, nr, st);
+            if (gp.torus) launch_chi<uint64_t, kOrbitTorus>(a, chi, cplx, nr, st);
+            else launch_chi<uint64_t, kOrbitGeneric>(a, chi, cplx, nr, st);
         }
         LS_HIP_CHECK(hipGetLastError());
         col += static_cast<uint32_t>(nr);

@@ -16,6 +16,7 @@ namespace ls {
 enum OrbitKind : int {
     kOrbitGeneric = 0,   // runtime lx, ly (ring, torus, or no translations)
     kOrbitRing32 = 1,    // N <= 32 ring: all rotations from one funnel shift each
+    kOrbitTorus = 2,     // lx <= 6, ly >= 2 torus: pruned by the pair table
 };
 
 template <typename W>
@@ -150,6 +151,97 @@ __device__ __forceinline__ W orbit_min(const PlanDev &P, W s, uint32_t &code) {
     }
     code = arg;
     return best;
+}
+
+// Pruned orbit minimum on an lx-by-ly torus (lx <= 6, ly >= 2).
+//
+// Pass 1 walks every coset representative p, y-shift b and flip f once:
+// the top two rows of tau_{0,b}(F^f p(s)) index the pair table, whose key is
+// the smallest value those two rows take over all x-shifts.  The minimum
+// image has the smallest key, so only (p, b, f) reaching the minimum key
+// can hold it; they are kept in a 128-bit mask.  Pass 2 evaluates those
+// candidates in full at the x-shift the table names (at every x-shift when
+// several shifts tie on the two rows); the images p(s) of pass 1 stay in
+// registers (at most kTorusMaxCosets coset representatives).
+//   lut   pair table, staged in LDS;  lcol  col_ge masks in LDS.
+constexpr uint32_t kTorusMaxCosets = 8;
+
+template <typename W, bool TRACK>
+__device__ __forceinline__ W torus_orbit_min(const PlanDev &P, W s, const uint16_t *lut, const uint64_t *lcol,
+                                             uint32_t &code) {
+    const uint32_t L = P.lx, Ly = P.ly;
+    const uint32_t nz = P.pair_flip ? 2u : 1u;
+    const uint32_t rm = (1u << L) - 1u, m2 = (1u << (2 * L)) - 1u;
+    const W full = static_cast<W>(P.full);
+    uint32_t best = 0xFFFFu;
+    uint64_t M0 = 0, M1 = 0;
+    W us[kTorusMaxCosets];   // p(s) of every coset, reused by pass 2
+#pragma unroll
+    for (uint32_t p = 0; p < kTorusMaxCosets; ++p) {
+        if (p >= P.n_cosets) break;
+        const W u = apply_coset<W>(P.cosets[p], s, P);
+        us[p] = u;
+        for (uint32_t b = 0; b < Ly; ++b) {
+            const uint32_t ty = Ly - 1 - b;
+            uint32_t q;
+            if (ty >= 1)
+                q = static_cast<uint32_t>(u >> (L * (ty - 1))) & m2;
+            else
+                q = ((static_cast<uint32_t>(u) & rm) << L) | (static_cast<uint32_t>(u >> (L * (Ly - 1))) & rm);
+            for (uint32_t f = 0; f < nz; ++f) {
+                const uint32_t k = static_cast<uint32_t>(lut[f ? (q ^ m2) : q]) >> 4;
+                const uint32_t idx = (p * Ly + b) * nz + f;
+                const uint64_t bit0 = idx < 64 ? (1ull << idx) : 0ull;
+                const uint64_t bit1 = idx >= 64 ? (1ull << (idx - 64)) : 0ull;
+                if (k < best) {
+                    best = k;
+                    M0 = bit0;
+                    M1 = bit1;
+                } else if (k == best) {
+                    M0 |= bit0;
+                    M1 |= bit1;
+                }
+            }
+        }
+    }
+    W rmin = static_cast<W>(~static_cast<W>(0));
+    uint32_t arg = 0;
+    while (M0 | M1) {
+        uint32_t idx;
+        if (M0) {
+            idx = static_cast<uint32_t>(__builtin_ctzll(M0));
+            M0 &= M0 - 1;
+        } else {
+            idx = 64u + static_cast<uint32_t>(__builtin_ctzll(M1));
+            M1 &= M1 - 1;
+        }
+        const uint32_t f = idx % nz, pb = idx / nz;
+        const uint32_t b = pb % Ly, p = pb / Ly;
+        W v = us[0];
+#pragma unroll
+        for (uint32_t q = 1; q < kTorusMaxCosets; ++q) v = p == q ? us[q] : v;
+        if (b) v = ((v << (L * b)) | (v >> (P.n_sites - L * b))) & full;
+        if (f) v ^= full;
+        const uint32_t e = lut[static_cast<uint32_t>(v >> (L * (Ly - 2))) & m2];
+        const uint32_t base = (p * P.n_trans + L * b) * nz + f;
+        if (e & 8u) {
+            for (uint32_t a = 0; a < L; ++a) {
+                if (v < rmin) { rmin = v; arg = base + a * nz; }
+                if (a + 1 < L) v = xrot<W>(v, P);
+            }
+        } else {
+            const uint32_t a = e & 7u;
+            W c = v;
+            if (a) {
+                const W ma = static_cast<W>(lcol[a]);
+                c = ((v << a) & ma) | ((v >> (L - a)) & ~ma & full);
+            }
+            if (c < rmin) { rmin = c; arg = base + a * nz; }
+        }
+    }
+    if constexpr (TRACK) code = arg;
+    else code = 0;
+    return rmin;
 }
 
 // Binomial coefficient table [65][65] in device memory.

@@ -77,7 +77,7 @@ uint64_t permute_mask(uint64_t m, const uint16_t *perm, uint32_t n) {
 
 void compile_terms(const ls_basis *b, uint32_t n_terms, const ls_term *terms, ls_operator *op) {
     LS_REQUIRE(n_terms == 0 || terms != nullptr, "terms must not be NULL");
-    LS_REQUIRE(n_terms <= 1u << 20, "too many terms");
+    LS_REQUIRE(n_terms <= matvec_max_terms(), "too many terms (the product stages at most 1024 in LDS)");
     const GroupPlan &gp = b->plan;
     const uint32_t n = gp.n_sites;
     const uint64_t full = gp.full;
