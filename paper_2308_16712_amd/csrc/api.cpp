@@ -152,11 +152,17 @@ ls_status ls_operator_create(const ls_basis *b, uint32_t n_terms, const ls_term 
         if (!op->host_terms.empty())
             LS_HIP_CHECK(hipMemcpy(op->d_terms, op->host_terms.data(), op->host_terms.size() * sizeof(ls_term_dev),
                                    hipMemcpyHostToDevice));
+        if (!op->host_cflip.empty()) {
+            LS_HIP_CHECK(hipMalloc(&op->d_cflip, op->host_cflip.size() * sizeof(uint64_t)));
+            LS_HIP_CHECK(hipMemcpy(op->d_cflip, op->host_cflip.data(), op->host_cflip.size() * sizeof(uint64_t),
+                                   hipMemcpyHostToDevice));
+        }
         *out = op;
         return LS_OK;
     });
     if (st != LS_OK && op) {
         hipFree(op->d_terms);
+        hipFree(op->d_cflip);
         delete op;
     }
     return st;
@@ -166,6 +172,7 @@ void ls_operator_destroy(ls_operator *op) {
     if (!op) return;
     hipDeviceSynchronize();
     hipFree(op->d_terms);
+    hipFree(op->d_cflip);
     delete op;
 }
 

@@ -361,8 +361,8 @@ void build_basis(ls_basis *b, hipStream_t st) {
     pd.pair_lut = nullptr;
     for (int a = 0; a < 8; ++a) pd.col_ge[a] = gp.col_ge[a];
     if (gp.torus) {
-        LS_HIP_CHECK(hipMalloc(&b->d_pair_lut, gp.pair_lut.size() * sizeof(uint16_t)));
-        LS_HIP_CHECK(hipMemcpy(b->d_pair_lut, gp.pair_lut.data(), gp.pair_lut.size() * sizeof(uint16_t),
+        LS_HIP_CHECK(hipMalloc(&b->d_pair_lut, gp.pair_lut.size() * sizeof(uint32_t)));
+        LS_HIP_CHECK(hipMemcpy(b->d_pair_lut, gp.pair_lut.data(), gp.pair_lut.size() * sizeof(uint32_t),
                                hipMemcpyHostToDevice));
         pd.pair_lut = b->d_pair_lut;
     }

@@ -320,8 +320,9 @@ GroupPlan compile_group(const ls_sector_desc &d) {
         P.torus = true;
         const uint32_t L = P.lx, rm = (1u << L) - 1u;
         auto rot = [&](uint32_t v, uint32_t a) { return a == 0 ? v : (((v << a) | (v >> (L - a))) & rm); };
-        P.pair_lut.resize(1u << (2 * L));
-        for (uint32_t q = 0; q < (1u << (2 * L)); ++q) {
+        const uint32_t nq = 1u << (2 * L);
+        std::vector<uint32_t> single(nq);
+        for (uint32_t q = 0; q < nq; ++q) {
             const uint32_t top = q >> L, second = q & rm;
             uint32_t best = ~0u, arg = 0, ties = 0;
             for (uint32_t a = 0; a < L; ++a) {
@@ -329,8 +330,11 @@ GroupPlan compile_group(const ls_sector_desc &d) {
                 if (v < best) { best = v; arg = a; ties = 1; }
                 else if (v == best) ++ties;
             }
-            P.pair_lut[q] = static_cast<uint16_t>((best << 4) | ((ties > 1 ? 1u : 0u) << 3) | arg);
+            single[q] = (best << 4) | ((ties > 1 ? 1u : 0u) << 3) | arg;
         }
+        // each entry also carries the entry of the spin-flipped pair
+        P.pair_lut.resize(nq);
+        for (uint32_t q = 0; q < nq; ++q) P.pair_lut[q] = single[q] | (single[q ^ (nq - 1)] << 16);
         for (uint32_t a = 0; a < L; ++a) {
             const uint64_t rowpat = static_cast<uint64_t>(rm & ~((1u << a) - 1u));
             uint64_t m = 0;

@@ -58,6 +58,8 @@ struct CosetRep {
 
 enum ChiMode : int { kChiTrivial = 0, kChiReal = 1, kChiComplex = 2 };
 
+constexpr uint32_t kTorusCosetSlots = 8;   // coset representatives kept per lane
+
 struct GroupPlan {
     uint32_t n_sites = 0;
     uint32_t n_elements = 0;
@@ -72,10 +74,11 @@ struct GroupPlan {
     std::vector<uint32_t> chi_one;  // bitset by code: chi == 1
     std::vector<int32_t> code_to_index;  // code -> index in the user's list
     // Pruned torus search (lx <= 6, ly >= 2): for every pair of rows
-    // (top << lx | second) the smallest x-rotation of the pair, packed as
-    // key << 4 | ambiguous << 3 | argmin_a.
+    // q = (top << lx | second) the smallest x-rotation of the pair, as
+    // entry = key << 4 | ambiguous << 3 | argmin_a, stored as
+    // entry(q) | entry(q with all bits flipped) << 16.
     bool torus = false;
-    std::vector<uint16_t> pair_lut;
+    std::vector<uint32_t> pair_lut;
     uint64_t col_ge[8] = {};        // bits with x >= a in every row
 };
 
@@ -98,7 +101,7 @@ struct PlanDev {
     const CosetRep *cosets;     // device
     const double2 *chi;         // device, by code
     const uint32_t *chi_one;    // device bitset, by code
-    const uint16_t *pair_lut;   // device, torus pruning table (or null)
+    const uint32_t *pair_lut;   // device, torus pruning table (or null)
     uint64_t col_ge[8];
 };
 
@@ -137,7 +140,7 @@ struct ls_basis {
     ls::CosetRep *d_cosets = nullptr;
     double2 *d_chi = nullptr;
     uint32_t *d_chi_one = nullptr;
-    uint16_t *d_pair_lut = nullptr;
+    uint32_t *d_pair_lut = nullptr;
     ls::PlanDev plan_dev{};
     ls::SearchDev search_dev{};
 };
@@ -152,8 +155,11 @@ struct ls_operator {
     bool is_complex = false;
     uint32_t n_diag = 0, n_off = 0;
     ls_term_dev *d_terms = nullptr;     // diagonal terms first, then off-diagonal
-    int *d_error = nullptr;             // device error flag
     std::vector<ls_term_dev> host_terms;
+    // torus search: the permutation part of every coset representative
+    // applied to every off-diagonal flip mask, [n_off][kTorusCosetSlots]
+    std::vector<uint64_t> host_cflip;
+    uint64_t *d_cflip = nullptr;
 };
 
 namespace ls {

@@ -19,6 +19,13 @@ enum OrbitKind : int {
     kOrbitTorus = 2,     // lx <= 6, ly >= 2 torus: pruned by the pair table
 };
 
+// A value that is the same in every active lane, moved to a scalar register.
+// Loop counters of the group walk are uniform, but the walk runs inside
+// each lane's own element loop, where the compiler cannot prove it; scalar
+// counters keep coset masks in scalar loads and index arithmetic off the
+// vector ALU.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 template <typename W>
 __device__ __forceinline__ W benes_apply(W x, const uint64_t *m) {
     if constexpr (sizeof(W) == 4) {
@@ -82,7 +89,8 @@ template <typename W, int KIND, typename F>
 __device__ __forceinline__ void for_each_image(const PlanDev &P, W s, F &&f) {
     const uint32_t nz = P.pair_flip ? 2u : 1u;
     const W full = static_cast<W>(P.full);
-    for (uint32_t p = 0; p < P.n_cosets; ++p) {
+    for (uint32_t p0 = 0; p0 < P.n_cosets; ++p0) {
+        const uint32_t p = uni(p0);
         const CosetRep c = P.cosets[p];
         W u = apply_coset<W>(c, s, P);
         if constexpr (KIND == kOrbitRing32) {
@@ -90,11 +98,12 @@ __device__ __forceinline__ void for_each_image(const PlanDev &P, W s, F &&f) {
             const uint32_t n = P.n_sites;
             const uint64_t uu = static_cast<uint64_t>(u) | (static_cast<uint64_t>(u) << n);
             const uint32_t lo = static_cast<uint32_t>(uu), hi = static_cast<uint32_t>(uu >> 32);
-            for (uint32_t t = 0; t < n; ++t) {
+            for (uint32_t t0 = 0; t0 < n; ++t0) {
+                const uint32_t t = uni(t0);
                 const W v = static_cast<W>(__builtin_amdgcn_alignbit(hi, lo, t)) & full;
                 // right rotation by t is the translation a = (n - t) mod n
                 const uint32_t a = t == 0 ? 0u : n - t;
-                const uint32_t base = (p * n + a) * nz;
+                const uint32_t base = uni((p * n + a) * nz);
                 if (!f(v, base)) return;
                 if (P.pair_flip && !f(static_cast<W>(v ^ full), base + 1)) return;
             }
@@ -102,7 +111,7 @@ __device__ __forceinline__ void for_each_image(const PlanDev &P, W s, F &&f) {
             for (uint32_t b = 0; b < P.ly; ++b) {
                 W v = u;
                 for (uint32_t a = 0; a < P.lx; ++a) {
-                    const uint32_t base = (p * P.n_trans + a + P.lx * b) * nz;
+                    const uint32_t base = uni((p * P.n_trans + a + P.lx * b) * nz);
                     if (!f(v, base)) return;
                     if (P.pair_flip && !f(static_cast<W>(v ^ full), base + 1)) return;
                     if (a + 1 < P.lx) v = xrot<W>(v, P);
@@ -122,8 +131,8 @@ __device__ __forceinline__ W orbit_min(const PlanDev &P, W s, uint32_t &code) {
         // plain min, two images per rotation with spin inversion
         const W full = static_cast<W>(P.full);
         const uint32_t n = P.n_sites;
-        for (uint32_t p = 0; p < P.n_cosets; ++p) {
-            const CosetRep c = P.cosets[p];
+        for (uint32_t p0 = 0; p0 < P.n_cosets; ++p0) {
+            const CosetRep c = P.cosets[uni(p0)];
             const W u = apply_coset<W>(c, s, P);
             const uint64_t uu = static_cast<uint64_t>(u) | (static_cast<uint64_t>(u) << n);
             const uint32_t lo = static_cast<uint32_t>(uu), hi = static_cast<uint32_t>(uu >> 32);
@@ -155,52 +164,67 @@ __device__ __forceinline__ W orbit_min(const PlanDev &P, W s, uint32_t &code) {
 
 // Pruned orbit minimum on an lx-by-ly torus (lx <= 6, ly >= 2).
 //
-// Pass 1 walks every coset representative p, y-shift b and flip f once:
-// the top two rows of tau_{0,b}(F^f p(s)) index the pair table, whose key is
-// the smallest value those two rows take over all x-shifts.  The minimum
-// image has the smallest key, so only (p, b, f) reaching the minimum key
-// can hold it; they are kept in a 128-bit mask.  Pass 2 evaluates those
-// candidates in full at the x-shift the table names (at every x-shift when
-// several shifts tie on the two rows); the images p(s) of pass 1 stay in
-// registers (at most kTorusMaxCosets coset representatives).
-//   lut   pair table, staged in LDS;  lcol  col_ge masks in LDS.
-constexpr uint32_t kTorusMaxCosets = 8;
+// The images p(s) of the coset representatives come in precomputed (us[]).
+// Pass 1a walks every coset p and y-shift b: the top two rows of
+// tau_{0,b}(p(s)) index the pair table, whose entry holds, for the pair and
+// for its spin-flipped partner, the smallest value the two rows take over
+// all x-shifts (the key) and the x-shift reaching it.  The minimum image has
+// the smallest key, so pass 1b marks the (p, b, f) that reach the smallest
+// key in a 128-bit mask, and pass 2 evaluates only those candidates in full
+// at the x-shift the table names (at every x-shift when several shifts tie
+// on the two rows).  LX, LY, NZ are the layout and |Z| when known at compile
+// time (0: read from the plan).
+//   lut   packed pair table in LDS: entry(q) | entry(q ^ all-ones) << 16,
+//         entry = key << 4 | ambiguous << 3 | argmin_a;
+//   lcol  col_ge masks in LDS.
+constexpr uint32_t kTorusMaxCosets = kTorusCosetSlots;
 
-template <typename W, bool TRACK>
-__device__ __forceinline__ W torus_orbit_min(const PlanDev &P, W s, const uint16_t *lut, const uint64_t *lcol,
-                                             uint32_t &code) {
-    const uint32_t L = P.lx, Ly = P.ly;
-    const uint32_t nz = P.pair_flip ? 2u : 1u;
+template <typename W, bool TRACK, uint32_t LX, uint32_t LY, uint32_t NZ>
+__device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, const uint32_t *lut,
+                                             const uint64_t *lcol, uint32_t &code) {
+    const uint32_t L = LX ? LX : P.lx, Ly = LY ? LY : P.ly;
+    const uint32_t nz = NZ ? NZ : (P.pair_flip ? 2u : 1u);
     const uint32_t rm = (1u << L) - 1u, m2 = (1u << (2 * L)) - 1u;
+    const uint32_t ncos = P.n_cosets;
     const W full = static_cast<W>(P.full);
+    // top two rows of tau_{0,b}(u): rows ly-1-b and ly-2-b (mod ly)
+    auto pair_of = [&](W u, uint32_t b) -> uint32_t {
+        const uint32_t ty = Ly - 1 - b;
+        if (ty >= 1) return static_cast<uint32_t>(u >> (L * (ty - 1))) & m2;
+        return ((static_cast<uint32_t>(u) & rm) << L) | (static_cast<uint32_t>(u >> (L * (Ly - 1))) & rm);
+    };
+    // pass 1a: the smallest key (entries compare by key first)
     uint32_t best = 0xFFFFu;
-    uint64_t M0 = 0, M1 = 0;
-    W us[kTorusMaxCosets];   // p(s) of every coset, reused by pass 2
 #pragma unroll
     for (uint32_t p = 0; p < kTorusMaxCosets; ++p) {
-        if (p >= P.n_cosets) break;
-        const W u = apply_coset<W>(P.cosets[p], s, P);
-        us[p] = u;
-        for (uint32_t b = 0; b < Ly; ++b) {
-            const uint32_t ty = Ly - 1 - b;
-            uint32_t q;
-            if (ty >= 1)
-                q = static_cast<uint32_t>(u >> (L * (ty - 1))) & m2;
-            else
-                q = ((static_cast<uint32_t>(u) & rm) << L) | (static_cast<uint32_t>(u >> (L * (Ly - 1))) & rm);
-            for (uint32_t f = 0; f < nz; ++f) {
-                const uint32_t k = static_cast<uint32_t>(lut[f ? (q ^ m2) : q]) >> 4;
-                const uint32_t idx = (p * Ly + b) * nz + f;
-                const uint64_t bit0 = idx < 64 ? (1ull << idx) : 0ull;
-                const uint64_t bit1 = idx >= 64 ? (1ull << (idx - 64)) : 0ull;
-                if (k < best) {
-                    best = k;
-                    M0 = bit0;
-                    M1 = bit1;
-                } else if (k == best) {
-                    M0 |= bit0;
-                    M1 |= bit1;
-                }
+        if (p >= ncos) break;
+#pragma unroll
+        for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
+            for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
+                const uint32_t b = LY ? b0 : uni(b1);
+                const uint32_t e = lut[pair_of(us[p], b)];
+                best = min(best, e & 0xFFFFu);
+                if (nz == 2) best = min(best, e >> 16);
+            }
+        }
+    }
+    best >>= 4;
+    // pass 1b: which (p, b, f) reach it (bit (p*ly + b)*nz + f)
+    uint64_t M0 = 0, M1 = 0;
+#pragma unroll
+    for (uint32_t p = 0; p < kTorusMaxCosets; ++p) {
+        if (p >= ncos) break;
+#pragma unroll
+        for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
+            for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
+                const uint32_t b = LY ? b0 : uni(b1);
+                const uint32_t e = lut[pair_of(us[p], b)];
+                const uint32_t idx = LY ? (p * Ly + b) * nz : uni((p * Ly + b) * nz);
+                const uint64_t hit = (((e >> 4) & 0xFFFu) == best ? 1ull : 0ull) |
+                                     ((nz == 2 && (e >> 20) == best) ? 2ull : 0ull);
+                if (idx < 63) M0 |= hit << idx;
+                else if (idx == 63) { M0 |= hit << 63; M1 |= hit >> 1; }
+                else M1 |= hit << (idx - 64);
             }
         }
     }
@@ -219,10 +243,10 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, W s, const uint16
         const uint32_t b = pb % Ly, p = pb / Ly;
         W v = us[0];
 #pragma unroll
-        for (uint32_t q = 1; q < kTorusMaxCosets; ++q) v = p == q ? us[q] : v;
+        for (uint32_t q = 1; q < kTorusMaxCosets; ++q) v = (q < ncos && p == q) ? us[q] : v;
         if (b) v = ((v << (L * b)) | (v >> (P.n_sites - L * b))) & full;
         if (f) v ^= full;
-        const uint32_t e = lut[static_cast<uint32_t>(v >> (L * (Ly - 2))) & m2];
+        const uint32_t e = lut[static_cast<uint32_t>(v >> (L * (Ly - 2))) & m2] & 0xFFFFu;
         const uint32_t base = (p * P.n_trans + L * b) * nz + f;
         if (e & 8u) {
             for (uint32_t a = 0; a < L; ++a) {

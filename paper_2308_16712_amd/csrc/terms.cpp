@@ -161,6 +161,29 @@ void compile_terms(const ls_basis *b, uint32_t n_terms, const ls_term *terms, ls
     op->n_diag = 0;
     for (const Term &t : ts) op->n_diag += t.flip == 0 ? 1u : 0u;
     op->n_off = static_cast<uint32_t>(ts.size()) - op->n_diag;
+
+    // p(r ^ f) = p(r) ^ pi_p(f) for a coset representative p = (pi_p, flip):
+    // the images of each flip mask let the kernel reuse p(r) for a whole row
+    op->host_cflip.clear();
+    if (gp.torus) {
+        const int wires = n <= 32 ? 32 : 64;
+        op->host_cflip.assign(static_cast<size_t>(op->n_off) * kTorusCosetSlots, 0);
+        for (uint32_t k = 0; k < op->n_off; ++k) {
+            const uint64_t f = op->host_terms[op->n_diag + k].flip;
+            for (uint32_t p = 0; p < gp.cosets.size(); ++p) {
+                const CosetRep &c = gp.cosets[p];
+                uint64_t g = f;
+                if (c.kind == kCosetReverse) {
+                    g = 0;
+                    for (uint32_t i = 0; i < n; ++i)
+                        if ((f >> i) & 1ULL) g |= 1ULL << (n - 1 - i);
+                } else if (c.kind == kCosetBenes) {
+                    g = benes_apply_host(f, c.masks, static_cast<int>(gp.n_stages), wires);
+                }
+                op->host_cflip[static_cast<size_t>(k) * kTorusCosetSlots + p] = g;
+            }
+        }
+    }
 }
 
 }  // namespace ls
