@@ -169,6 +169,42 @@ ls_status ls_operator_info(const ls_operator *op, int *is_complex, uint64_t *dim
  * belongs to an orbit the projector annihilates and contributes zero.     */
 ls_status ls_matvec(const ls_operator *op, uint32_t nrhs, const void *d_x, void *d_y, void *stream);
 
+/* ---- batched products ------------------------------------------------------
+ * Many products y_k = H_k x_k (k = 0..n-1) over operators of different
+ * sectors, couplings and dimensions, each with its own number of right-hand
+ * sides, executed as one persistent launch per kernel variant (operators on
+ * the same kind of lattice share a launch).  The paper computes many rows at
+ * once to amortise per-call costs (getManyRows, Section 5.3); here many
+ * products share one launch, a tile queue balances uneven dimensions, and
+ * the launch sequence is captured in a HIP graph and replayed.
+ * On the first ls_batch_matvec the library tunes, per variant, the tile size
+ * and grid size (timing candidates on the caller's buffers; y is written
+ * during tuning) and, per basis, the bucket bits of a batch-owned search
+ * layout; the choices are cached per process.  The batch borrows the
+ * operators, which must outlive it.                                         */
+typedef struct ls_batch ls_batch;
+
+/*   ops   host array of n operator handles (may repeat);
+ *   nrhs  host array of n right-hand-side counts, each 1..64.              */
+ls_status ls_batch_create(uint32_t n, const ls_operator *const *ops, const uint32_t *nrhs, ls_batch **out);
+
+/* y_k = H_k x_k for every k, enqueued on `stream`.
+ *   d_x, d_y  host arrays of n device pointers, laid out as for ls_matvec
+ *             ([dim_k][nrhs_k], double or complex128); y_k must not overlap
+ *             x_k.  Pointers may change between calls (the job tables the
+ *             graph reads are rewritten, stream-ordered).                  */
+ls_status ls_batch_matvec(ls_batch *batch, const void *const *d_x, void *const *d_y, void *stream);
+
+/* Launches per call (one per variant and column width), tiles, and whether
+ * a captured graph is in use.  Any output may be NULL.                     */
+ls_status ls_batch_info(const ls_batch *batch, uint32_t *n_launches, uint32_t *n_tiles, uint32_t *graph);
+
+/* Turns graph capture on (default) or off (direct launches) before the
+ * first ls_batch_matvec.                                                   */
+ls_status ls_batch_set_graph(ls_batch *batch, int enabled);
+
+void ls_batch_destroy(ls_batch *batch);
+
 /* Lanczos ground-state solve on top of ls_matvec.  FP64 throughout, Krylov
  * vectors resident in HBM, full CGS2 reorthogonalization when reorth = 1,
  * dot products reduced in a fixed order (deterministic).

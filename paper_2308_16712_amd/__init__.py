@@ -13,7 +13,16 @@ ABI's names and only marshal arguments; device buffers are torch tensors.
 """
 from __future__ import annotations
 
-from ._lib import (EXPORTS, LIB_PATH, LSError, Basis, Operator, load, sector_check)  # noqa: F401
+from ._lib import (EXPORTS, LIB_PATH, LSError, Basis, Batch, Operator, load, sector_check)  # noqa: F401
+
+
+def ls_batch_create(ops, nrhs, graph: bool = True) -> Batch:
+    """Many products in one persistent launch per kernel variant."""
+    return Batch(ops, nrhs, graph)
+
+
+def ls_batch_matvec(batch: Batch, xs, ys, stream=None):
+    return batch.matvec(xs, ys, stream)
 
 
 def ls_sector_check(sector) -> dict:

@@ -21,6 +21,7 @@ _NAMES = {0: "LS_OK", 1: "LS_WNOTCONV", -1: "LS_EINVAL", -2: "LS_ENOMEM", -3: "L
 
 EXPORTS = ["ls_sector_check", "ls_basis_build", "ls_basis_info", "ls_basis_copy", "ls_basis_destroy", "ls_state_info",
            "ls_index_lookup", "ls_operator_create", "ls_operator_destroy", "ls_operator_info", "ls_matvec",
+           "ls_batch_create", "ls_batch_matvec", "ls_batch_info", "ls_batch_set_graph", "ls_batch_destroy",
            "ls_lanczos", "ls_last_error", "ls_version"]
 
 
@@ -72,6 +73,11 @@ def load(path: str = LIB_PATH):
         "ls_operator_destroy": ([P], None),
         "ls_operator_info": ([P, P, P], i32),
         "ls_matvec": ([P, u32, P, P, P], i32),
+        "ls_batch_create": ([u32, P, P, P], i32),
+        "ls_batch_matvec": ([P, P, P, P], i32),
+        "ls_batch_info": ([P, P, P, P], i32),
+        "ls_batch_set_graph": ([P, ctypes.c_int], i32),
+        "ls_batch_destroy": ([P], None),
         "ls_lanczos": ([P, P, P, P, P, P], i32),
         "ls_last_error": ([], ctypes.c_char_p),
         "ls_version": ([], ctypes.c_char_p),
@@ -254,6 +260,57 @@ class Operator:
     def close(self):
         if getattr(self, "_h", None):
             load().ls_operator_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Handle of a batched product (ls_batch_create): many operators, each
+    with its own number of right-hand sides, in one persistent launch per
+    kernel variant, replayed from a HIP graph."""
+
+    def __init__(self, ops, nrhs, graph: bool = True):
+        L = load()
+        self.ops = list(ops)
+        self.nrhs = [int(v) for v in nrhs]
+        if len(self.ops) != len(self.nrhs) or not self.ops:
+            raise ValueError("ops and nrhs must be non-empty and of equal length")
+        n = len(self.ops)
+        self._handles = (ctypes.c_void_p * n)(*[op.handle.value for op in self.ops])
+        self._nrhs = (ctypes.c_uint32 * n)(*self.nrhs)
+        h = ctypes.c_void_p()
+        _check(L.ls_batch_create(n, self._handles, self._nrhs, ctypes.byref(h)))
+        self._h = h
+        if not graph:
+            _check(L.ls_batch_set_graph(h, 0))
+
+    def matvec(self, xs, ys, stream=None):
+        """ys[k] = H_k xs[k] for every k (torch tensors [dim_k][nrhs_k])."""
+        n = len(self.ops)
+        if len(xs) != n or len(ys) != n:
+            raise ValueError("one x and one y per operator")
+        for op, x, y, r in zip(self.ops, xs, ys, self.nrhs):
+            want = (op.dim, r) if r > 1 else (op.dim,)
+            if tuple(x.shape) not in (want, (op.dim, r)) or tuple(y.shape) != tuple(x.shape):
+                raise ValueError("x/y shape does not match the operator and nrhs")
+        px = (ctypes.c_void_p * n)(*[_dptr(x).value for x in xs])
+        py = (ctypes.c_void_p * n)(*[_dptr(y).value for y in ys])
+        _check(load().ls_batch_matvec(self._h, px, py, _stream_ptr(stream)))
+        return ys
+
+    def info(self) -> dict:
+        a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(load().ls_batch_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return dict(launches=a.value, tiles=b.value, graph=bool(c.value))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().ls_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -17,8 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libls_ed.so")
-SOURCES = ["api.cpp", "group.cpp", "terms.cpp", "basis.hip", "matvec.hip", "lanczos.hip"]
-HEADERS = ["ls_internal.hpp", "orbit.hpp"]
+SOURCES = ["api.cpp", "group.cpp", "terms.cpp", "basis.hip", "matvec.hip", "batch.hip", "lanczos.hip"]
+HEADERS = ["ls_internal.hpp", "orbit.hpp", "matvec_impl.hpp", "dispatch.hpp"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,

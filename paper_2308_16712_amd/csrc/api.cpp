@@ -200,6 +200,41 @@ ls_status ls_matvec(const ls_operator *op, uint32_t nrhs, const void *d_x, void 
     });
 }
 
+ls_status ls_batch_create(uint32_t n, const ls_operator *const *ops, const uint32_t *nrhs, ls_batch **out) {
+    return guarded([&] {
+        ls::batch_create(n, ops, nrhs, out);
+        return LS_OK;
+    });
+}
+
+ls_status ls_batch_matvec(ls_batch *batch, const void *const *d_x, void *const *d_y, void *stream) {
+    return guarded([&] {
+        LS_REQUIRE(batch != nullptr, "batch must not be NULL");
+        ls::batch_matvec(batch, d_x, d_y, as_stream(stream));
+        return LS_OK;
+    });
+}
+
+ls_status ls_batch_info(const ls_batch *batch, uint32_t *n_launches, uint32_t *n_tiles, uint32_t *graph) {
+    return guarded([&] {
+        LS_REQUIRE(batch != nullptr, "batch must not be NULL");
+        ls::batch_info(batch, n_launches, n_tiles, graph);
+        return LS_OK;
+    });
+}
+
+ls_status ls_batch_set_graph(ls_batch *batch, int enabled) {
+    return guarded([&] {
+        LS_REQUIRE(batch != nullptr, "batch must not be NULL");
+        ls::batch_set_graph(batch, enabled != 0);
+        return LS_OK;
+    });
+}
+
+void ls_batch_destroy(ls_batch *batch) {
+    if (batch) ls::batch_destroy(batch);
+}
+
 ls_status ls_lanczos(const ls_operator *op, const ls_lanczos_opts *opts, void *stream, double *e0, uint32_t *iters,
                      double *resid_bound) {
     return guarded([&] {

@@ -1,0 +1,463 @@
+// Batched products: many operators (sectors, couplings, dimensions) and
+// right-hand sides in one persistent launch per kernel variant.
+//
+// Work is cut into tiles of (job, first row); a job is one operator and a
+// slice of its right-hand-side columns.  A fixed grid of workgroups pulls
+// tiles from a counter in device memory (reset by a one-thread kernel, so
+// the sequence can be captured in a HIP graph and replayed); when the job
+// changes, the workgroup restages the job's LDS tables.  Tiles are ordered
+// by decreasing job cost, so the tail of the queue is made of small tiles.
+//
+// An autotuner picks, per variant group, the rows per lane of a tile and the
+// number of resident workgroups by timing the candidates on first use, and,
+// per basis, the number of bucket bits of the search layout by timing a
+// lookup sweep (the batch owns these tables; the basis is not modified).
+// Results are cached per process.
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "dispatch.hpp"
+
+namespace ls {
+
+namespace {
+
+struct Tile {
+    uint32_t job;
+    uint32_t pad_;
+    uint64_t row0;
+};
+
+template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
+__global__ void __launch_bounds__(block_of(KIND))
+    k_matvec_batch(const MatvecJob *jobs, const Tile *tiles, uint32_t n_tiles, uint32_t *counter, uint32_t rpl) {
+    constexpr int BLOCK = block_of(KIND);
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t s_tile;
+    uint32_t cur = 0xFFFFFFFFu;
+    LdsTables L{};
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t tile = __builtin_amdgcn_readfirstlane(s_tile);
+        __syncthreads();
+        if (tile >= n_tiles) break;
+        const Tile T = tiles[tile];
+        const uint32_t jid = __builtin_amdgcn_readfirstlane(T.job);
+        const MatvecJob &a = jobs[jid];
+        if (jid != cur) {
+            L = lds_tables<KIND, LX, BLOCK>(a, smem);
+            stage_tables<KIND, LX, BLOCK>(a, L);
+            __syncthreads();
+            cur = jid;
+        }
+        run_rows<W, KIND, CHI, CPLX, NR, LX, LY, NZ>(a, L, T.row0 + threadIdx.x, BLOCK, rpl);
+    }
+}
+
+__global__ void k_reset_counter(uint32_t *c) { *c = 0u; }
+
+// Bucket table for a candidate number of bits (same rule as the basis build).
+__global__ void k_buckets_tuned(const uint64_t *reps, uint64_t d, uint64_t kmin, uint32_t shift, uint64_t nb,
+                                uint32_t *buckets) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= d) return;
+    const uint64_t bi = (reps[i] - kmin) >> shift;
+    const int64_t prev = i == 0 ? -1 : static_cast<int64_t>((reps[i - 1] - kmin) >> shift);
+    for (int64_t k = prev + 1; k <= static_cast<int64_t>(bi); ++k) buckets[k] = static_cast<uint32_t>(i);
+    if (i == d - 1)
+        for (uint64_t k = bi + 1; k <= nb; ++k) buckets[k] = static_cast<uint32_t>(d);
+}
+
+// Lookup sweep used to time a search layout: keys are representatives taken
+// in a scattered order; the sum of indices defeats dead-code elimination.
+__global__ void k_lookup_sweep(SearchDev S, uint64_t n, uint64_t magic, uint64_t *sink) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t j = (i * 0x9E3779B97F4A7C15ULL) % S.dim;
+    const int64_t idx = lookup_index(S, S.reps[j]);
+    // magic is a value no index takes; the store keeps the lookup live
+    if (static_cast<uint64_t>(idx) == magic) *sink = j;
+}
+
+struct Group {
+    Variant v;
+    int nr = 1;
+    std::vector<MatvecJob> jobs;
+    std::vector<std::pair<uint32_t, uint32_t>> item_col;   // (item, first column) per job
+    std::vector<double> cost;
+    MatvecJob *d_jobs = nullptr;
+    Tile *d_tiles = nullptr;
+    uint32_t *d_counter = nullptr;
+    uint32_t n_tiles = 0;
+    uint32_t rpl = 4;
+    uint32_t grid = 0;
+    size_t lds = 0;
+    bool tuned = false;
+};
+
+struct BatchLaunch {
+    Group *g;
+    hipStream_t st;
+    template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
+    void run() {
+        constexpr int BLOCK = block_of(KIND);
+        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, g->d_counter);
+        hipLaunchKernelGGL((k_matvec_batch<W, KIND, CHI, CPLX, NR, LX, LY, NZ>), dim3(g->grid), dim3(BLOCK), g->lds,
+                           st, g->d_jobs, g->d_tiles, g->n_tiles, g->d_counter, g->rpl);
+        (void)BLOCK;
+    }
+};
+
+int block_for(const Variant &v) { return block_of(v.kind); }
+
+// Tiles for the current rows-per-lane, ordered by decreasing job cost.
+void build_tiles(Group &g, hipStream_t st) {
+    const uint64_t rows_per_tile = static_cast<uint64_t>(block_for(g.v)) * g.rpl;
+    std::vector<uint32_t> order(g.jobs.size());
+    for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return g.cost[a] > g.cost[b]; });
+    std::vector<Tile> tiles;
+    for (uint32_t j : order)
+        for (uint64_t r = 0; r < g.jobs[j].dim; r += rows_per_tile) tiles.push_back(Tile{j, 0, r});
+    if (g.d_tiles) hipFree(g.d_tiles);
+    g.d_tiles = nullptr;
+    LS_HIP_CHECK(hipMalloc(&g.d_tiles, std::max<size_t>(tiles.size(), 1) * sizeof(Tile)));
+    if (!tiles.empty())
+        LS_HIP_CHECK(hipMemcpyAsync(g.d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
+    LS_HIP_CHECK(hipStreamSynchronize(st));
+    g.n_tiles = static_cast<uint32_t>(tiles.size());
+}
+
+void upload_jobs(Group &g, hipStream_t st) {
+    LS_HIP_CHECK(hipMemcpyAsync(g.d_jobs, g.jobs.data(), g.jobs.size() * sizeof(MatvecJob), hipMemcpyHostToDevice,
+                                st));
+}
+
+using TuneKey = std::tuple<int, int, int, uint32_t, uint32_t, int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<uint32_t, uint32_t>> g_tune_cache;   // -> (rpl, workgroups per CU)
+std::map<std::tuple<uint64_t, uint64_t, uint64_t>, uint32_t> g_bits_cache;   // (dim, kmin, kmax) -> bits
+
+TuneKey tune_key(const Group &g) {
+    uint64_t rows = 0;
+    for (const auto &j : g.jobs) rows += j.dim;
+    int lg = 0;
+    while ((1ull << lg) < rows) ++lg;
+    int lj = 0;
+    while ((1u << lj) < g.jobs.size()) ++lj;
+    return TuneKey{g.v.word64, g.v.kind, g.v.chi, g.v.lx, g.v.ly, g.v.cplx ? 1 : 0, g.nr, lg, lj};
+}
+
+float time_group(Group &g, hipStream_t st) {
+    hipEvent_t e0, e1;
+    LS_HIP_CHECK(hipEventCreate(&e0));
+    LS_HIP_CHECK(hipEventCreate(&e1));
+    BatchLaunch L{&g, st};
+    dispatch(g.v, g.nr, L);   // warm
+    LS_HIP_CHECK(hipEventRecord(e0, st));
+    dispatch(g.v, g.nr, L);
+    LS_HIP_CHECK(hipEventRecord(e1, st));
+    LS_HIP_CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    LS_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    LS_HIP_CHECK(hipGetLastError());
+    return ms;
+}
+
+void tune_group(Group &g, hipStream_t st, int n_cu) {
+    const int block = block_for(g.v);
+    const int max_wg_per_cu = std::max(1, 2048 / block);   // 32 waves per CU
+    const TuneKey key = tune_key(g);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            g.rpl = it->second.first;
+            g.grid = static_cast<uint32_t>(n_cu * it->second.second);
+            build_tiles(g, st);
+            g.tuned = true;
+            return;
+        }
+    }
+    float best = 1e30f;
+    uint32_t best_rpl = 4, best_wpc = static_cast<uint32_t>(max_wg_per_cu);
+    for (uint32_t rpl : {1u, 2u, 4u, 8u}) {
+        g.rpl = rpl;
+        build_tiles(g, st);
+        for (int wpc = 1; wpc <= max_wg_per_cu; wpc *= 2) {
+            g.grid = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(n_cu) * wpc,
+                                                              std::max<uint32_t>(g.n_tiles, 1)));
+            const float ms = time_group(g, st);
+            if (ms < best) {
+                best = ms;
+                best_rpl = rpl;
+                best_wpc = static_cast<uint32_t>(wpc);
+            }
+        }
+    }
+    g.rpl = best_rpl;
+    g.grid = static_cast<uint32_t>(n_cu * best_wpc);
+    build_tiles(g, st);
+    g.tuned = true;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = {best_rpl, best_wpc};
+}
+
+}  // namespace
+
+}  // namespace ls
+
+struct ls_batch {
+    std::vector<const ls_operator *> ops;
+    std::vector<uint32_t> nrhs;
+    std::vector<ls::Group> groups;
+    std::vector<const void *> cur_x;
+    std::vector<void *> cur_y;
+    std::vector<uint32_t *> own_buckets;     // tuned search layouts (one per basis)
+    std::vector<ls::SearchDev> search;       // per item
+    hipStream_t cap = nullptr;               // stream used for graph capture
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool use_graph = true;
+    bool ready = false;
+    int n_cu = 256;
+};
+
+namespace ls {
+
+namespace {
+
+// Tune the bucket bits of one basis by timing lookup sweeps; returns a
+// batch-owned search layout (or the basis's own when it is not a search).
+SearchDev tuned_search(ls_batch *B, const ls_basis *b, hipStream_t st) {
+    SearchDev S = b->search_dev;
+    if (S.mode != kLookupSearch || b->dim < 4096) return S;
+    const auto key = std::make_tuple(b->dim, S.kmin, S.kmax);
+    uint32_t bits = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_bits_cache.find(key);
+        if (it != g_bits_cache.end()) bits = it->second;
+    }
+    const uint64_t range = S.kmax - S.kmin;
+    uint32_t len = 0;
+    while (len < 64 && (range >> len) != 0) ++len;
+    auto build = [&](uint32_t nbits, uint32_t **out, uint32_t *shift) {
+        *shift = len > nbits ? len - nbits : 0;
+        const uint64_t nb = (range >> *shift) + 1;
+        LS_HIP_CHECK(hipMalloc(out, (nb + 1) * sizeof(uint32_t)));
+        hipLaunchKernelGGL(k_buckets_tuned, dim3(static_cast<uint32_t>((b->dim + 255) / 256)), dim3(256), 0, st,
+                           b->d_reps, b->dim, S.kmin, *shift, nb, *out);
+        LS_HIP_CHECK(hipGetLastError());
+    };
+    if (bits == 0) {
+        uint64_t *sink = nullptr;
+        LS_HIP_CHECK(hipMalloc(&sink, sizeof(uint64_t)));
+        hipEvent_t e0, e1;
+        LS_HIP_CHECK(hipEventCreate(&e0));
+        LS_HIP_CHECK(hipEventCreate(&e1));
+        float best = 1e30f;
+        const uint64_t n = std::min<uint64_t>(b->dim, 1u << 22);
+        for (int d = -4; d <= 4; d += 2) {
+            const int cand = static_cast<int>(S.bits) + d;
+            if (cand < 8 || cand > 24) continue;
+            uint32_t *tab = nullptr, shift = 0;
+            build(static_cast<uint32_t>(cand), &tab, &shift);
+            SearchDev T = S;
+            T.bits = static_cast<uint32_t>(cand);
+            T.shift = shift;
+            T.buckets = tab;
+            hipLaunchKernelGGL(k_lookup_sweep, dim3(static_cast<uint32_t>((n + 255) / 256)), dim3(256), 0, st, T, n,
+                               ~0ULL - 1, sink);
+            LS_HIP_CHECK(hipEventRecord(e0, st));
+            hipLaunchKernelGGL(k_lookup_sweep, dim3(static_cast<uint32_t>((n + 255) / 256)), dim3(256), 0, st, T, n,
+                               ~0ULL - 1, sink);
+            LS_HIP_CHECK(hipEventRecord(e1, st));
+            LS_HIP_CHECK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            LS_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+            hipFree(tab);
+            if (ms < best) {
+                best = ms;
+                bits = static_cast<uint32_t>(cand);
+            }
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        hipFree(sink);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_bits_cache[key] = bits;
+    }
+    uint32_t *tab = nullptr, shift = 0;
+    build(bits, &tab, &shift);
+    B->own_buckets.push_back(tab);
+    S.bits = bits;
+    S.shift = shift;
+    S.buckets = tab;
+    return S;
+}
+
+void free_batch(ls_batch *B) {
+    if (!B) return;
+    for (auto &g : B->groups) {
+        hipFree(g.d_jobs);
+        hipFree(g.d_tiles);
+        hipFree(g.d_counter);
+    }
+    for (auto *p : B->own_buckets) hipFree(p);
+    if (B->exec) hipGraphExecDestroy(B->exec);
+    if (B->graph) hipGraphDestroy(B->graph);
+    if (B->cap) hipStreamDestroy(B->cap);
+    delete B;
+}
+
+}  // namespace
+
+void batch_create(uint32_t n, const ls_operator *const *ops, const uint32_t *nrhs, ls_batch **out) {
+    LS_REQUIRE(n >= 1 && ops != nullptr && nrhs != nullptr && out != nullptr, "invalid batch arguments");
+    ls_batch *B = new ls_batch();
+    try {
+        for (uint32_t i = 0; i < n; ++i) {
+            LS_REQUIRE(ops[i] != nullptr, "operator must not be NULL");
+            LS_REQUIRE(nrhs[i] >= 1 && nrhs[i] <= 64, "nrhs must be in 1..64");
+            B->ops.push_back(ops[i]);
+            B->nrhs.push_back(nrhs[i]);
+        }
+        B->cur_x.assign(n, nullptr);
+        B->cur_y.assign(n, nullptr);
+        int dev = 0;
+        LS_HIP_CHECK(hipGetDevice(&dev));
+        LS_HIP_CHECK(hipDeviceGetAttribute(&B->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+        LS_HIP_CHECK(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+    } catch (...) {
+        free_batch(B);
+        throw;
+    }
+    *out = B;
+}
+
+void batch_destroy(ls_batch *B) {
+    hipDeviceSynchronize();
+    free_batch(B);
+}
+
+// First call: search layouts, grouping, tiles, tuning; later calls reuse them.
+static void batch_prepare(ls_batch *B, hipStream_t st) {
+    const uint32_t n = static_cast<uint32_t>(B->ops.size());
+    // one tuned search layout per distinct basis
+    std::map<const ls_basis *, SearchDev> by_basis;
+    B->search.resize(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        const ls_basis *b = B->ops[i]->basis;
+        auto it = by_basis.find(b);
+        if (it == by_basis.end()) it = by_basis.emplace(b, tuned_search(B, b, st)).first;
+        B->search[i] = it->second;
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+        const ls_operator *op = B->ops[i];
+        if (op->basis->dim == 0) continue;
+        const Variant v = variant_of(op);
+        uint32_t col = 0;
+        while (col < B->nrhs[i]) {
+            const int nr = nr_chunk(B->nrhs[i] - col);
+            Group *g = nullptr;
+            for (auto &gg : B->groups)
+                if (gg.v == v && gg.nr == nr) g = &gg;
+            if (!g) {
+                B->groups.emplace_back();
+                g = &B->groups.back();
+                g->v = v;
+                g->nr = nr;
+            }
+            MatvecJob j = job_of(op, B->cur_x[i], B->cur_y[i], B->nrhs[i], col);
+            j.search = B->search[i];
+            g->jobs.push_back(j);
+            g->item_col.push_back({i, col});
+            const double nterm = static_cast<double>(op->n_off) + 1.0;
+            g->cost.push_back(static_cast<double>(op->basis->dim) * nterm * op->basis->plan.n_elements);
+            g->lds = std::max(g->lds, lds_bytes(v.kind, op->n_diag + op->n_off, op->n_off, op->basis->plan.lx));
+            col += static_cast<uint32_t>(nr);
+        }
+    }
+    for (auto &g : B->groups) {
+        LS_HIP_CHECK(hipMalloc(&g.d_jobs, g.jobs.size() * sizeof(MatvecJob)));
+        LS_HIP_CHECK(hipMalloc(&g.d_counter, sizeof(uint32_t)));
+        upload_jobs(g, st);
+        tune_group(g, st, B->n_cu);
+    }
+    B->ready = true;
+}
+
+void batch_matvec(ls_batch *B, const void *const *xs, void *const *ys, hipStream_t st) {
+    const uint32_t n = static_cast<uint32_t>(B->ops.size());
+    LS_REQUIRE(xs != nullptr && ys != nullptr, "x and y arrays must not be NULL");
+    bool changed = false;
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint64_t dim = B->ops[i]->basis->dim;
+        if (dim == 0) continue;
+        LS_REQUIRE(xs[i] != nullptr && ys[i] != nullptr, "x and y must not be NULL");
+        const size_t bytes = dim * B->nrhs[i] * (B->ops[i]->is_complex ? 16u : 8u);
+        const char *xb = static_cast<const char *>(xs[i]);
+        const char *yb = static_cast<const char *>(ys[i]);
+        LS_REQUIRE(xb + bytes <= yb || yb + bytes <= xb, "x and y must not overlap");
+        if (xs[i] != B->cur_x[i] || ys[i] != B->cur_y[i]) changed = true;
+        B->cur_x[i] = xs[i];
+        B->cur_y[i] = ys[i];
+    }
+    if (changed && B->ready) {
+        for (auto &g : B->groups) {
+            for (size_t k = 0; k < g.jobs.size(); ++k) {
+                const uint32_t item = g.item_col[k].first;
+                g.jobs[k].x = B->cur_x[item];
+                g.jobs[k].y = B->cur_y[item];
+            }
+            upload_jobs(g, st);
+        }
+    }
+    if (!B->ready) batch_prepare(B, st);
+    if (B->groups.empty()) return;
+    if (!B->use_graph) {
+        for (auto &g : B->groups) {
+            BatchLaunch L{&g, st};
+            dispatch(g.v, g.nr, L);
+            LS_HIP_CHECK(hipGetLastError());
+        }
+        return;
+    }
+    if (!B->exec) {
+        // capture on the library's own stream; the graph reads job tables by
+        // pointer, so later pointer changes only rewrite those tables
+        LS_HIP_CHECK(hipStreamSynchronize(st));
+        LS_HIP_CHECK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+        for (auto &g : B->groups) {
+            BatchLaunch L{&g, B->cap};
+            dispatch(g.v, g.nr, L);
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(B->cap, &graph);
+        LS_HIP_CHECK(e);
+        B->graph = graph;
+        LS_HIP_CHECK(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    }
+    LS_HIP_CHECK(hipGraphLaunch(B->exec, st));
+}
+
+void batch_info(const ls_batch *B, uint32_t *n_launches, uint32_t *n_tiles, uint32_t *graph) {
+    if (n_launches) *n_launches = static_cast<uint32_t>(B->groups.size());
+    if (n_tiles) {
+        uint32_t t = 0;
+        for (const auto &g : B->groups) t += g.n_tiles;
+        *n_tiles = t;
+    }
+    if (graph) *graph = B->exec != nullptr ? 1u : 0u;
+}
+
+void batch_set_graph(ls_batch *B, bool on) { B->use_graph = on; }
+
+}  // namespace ls

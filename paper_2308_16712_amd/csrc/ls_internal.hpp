@@ -178,6 +178,13 @@ void compile_terms(const ls_basis *b, uint32_t n_terms, const ls_term *terms, ls
 uint32_t matvec_max_terms();   // the term table is staged in LDS
 void launch_matvec(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t stream);
 
+// batch.hip
+void batch_create(uint32_t n, const ls_operator *const *ops, const uint32_t *nrhs, ls_batch **out);
+void batch_destroy(ls_batch *b);
+void batch_matvec(ls_batch *b, const void *const *xs, void *const *ys, hipStream_t stream);
+void batch_info(const ls_batch *b, uint32_t *n_launches, uint32_t *n_tiles, uint32_t *graph);
+void batch_set_graph(ls_batch *b, bool on);
+
 // lanczos.hip
 ls_status run_lanczos(const ls_operator *op, const ls_lanczos_opts *o, hipStream_t stream,
                       double *e0, uint32_t *iters, double *resid);

@@ -1,0 +1,234 @@
+// Device implementation of the on-the-fly product, shared by the single
+// launch (matvec.hip) and the persistent batched launch (batch.hip).
+//
+// Row i of the sector Hamiltonian is generated from its representative r:
+//   acc = (sum of diagonal terms acting on r) * x_i
+//   for each off-diagonal term t acting on r (r & sel == val):
+//       s    = r ^ flip_t,  a = conj(c_t) (-1)^popcount(r & sign_t)
+//       rep  = orbit minimum of s, g* an element reaching it   (getRow)
+//       j    = stateToIndex(rep)                                (lookup)
+//       acc += a * chi(g*) * sqrt(stab_j / stab_i) * x_j
+//   y_i = acc                                     (one store, no atomics)
+// This is <r~_i|H|r~_j> written with P|s> = conj(chi(g*)) P|rep> and the
+// Hermiticity of H; a neighbour whose orbit the projector annihilates is
+// absent from the basis and contributes nothing.
+//
+// Work layout.  Each off-diagonal term acts on only part of the rows (a
+// Heisenberg exchange term on about a quarter of them), so a loop over the
+// terms that is uniform across a wavefront would run the orbit search for
+// every term with most lanes idle.  Instead every lane walks its own list:
+// one loop iteration = one element (the lane's next acting term of its
+// current row); when a lane's row is exhausted it stores y_i and moves to
+// its next row.  A lane owns several rows strided by a fixed step, so
+// per-row differences in the number of acting terms average out.  The term
+// table is staged in LDS once per workgroup (per item in a batch).
+//
+// Tori (pruned search): permutations act linearly on bits, so for a coset
+// representative p, p(r ^ f) = p(r) ^ pi_p(f).  A lane computes p(r) once per
+// row and each neighbour's images with one XOR per coset, reading pi_p(f)
+// from a per-operator table staged in LDS.  Workgroups of 1024 threads share
+// the LDS tables among 16 wavefronts.
+//
+// Right-hand sides: x and y are [dim][ld] row-major; a job handles NR
+// consecutive columns starting at `col`, so the orbit search is shared by
+// NR vectors.
+#pragma once
+
+#include "orbit.hpp"
+
+namespace ls {
+
+constexpr int kMaxLdsTerms = 1024;
+constexpr size_t kMaxLds = 64 * 1024;
+
+// One product (or a column slice of one): everything a workgroup needs.
+struct MatvecJob {
+    PlanDev plan;
+    SearchDev search;
+    const uint16_t *stab;
+    const ls_term_dev *terms;
+    const uint64_t *cflip;  // [n_off][kTorusCosetSlots] (torus search only)
+    uint32_t n_diag, n_terms;
+    uint64_t dim;
+    uint32_t ld;           // row stride of x and y in elements
+    uint32_t col;          // first column handled
+    const void *x;
+    void *y;
+};
+
+__device__ __forceinline__ double sign_of(uint64_t v) {
+    return (__builtin_popcountll(v) & 1) ? -1.0 : 1.0;
+}
+
+template <bool CPLX>
+struct Val;
+template <>
+struct Val<false> {
+    using T = double;
+};
+template <>
+struct Val<true> {
+    using T = double2;
+};
+
+constexpr int block_of(int kind) { return kind == kOrbitTorus ? 1024 : 256; }
+
+__host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
+
+// LDS layout: terms | pair table | col_ge | flip images (torus only)
+inline size_t lds_bytes(int kind, uint32_t n_terms, uint32_t n_off, uint32_t lx) {
+    size_t b = align16((n_terms > 0 ? n_terms : 1) * sizeof(ls_term_dev));
+    if (kind == kOrbitTorus)
+        b += align16((size_t(1) << (2 * lx)) * sizeof(uint32_t)) + 64 +
+             static_cast<size_t>(n_off) * kTorusCosetSlots * sizeof(uint64_t);
+    return b;
+}
+
+struct LdsTables {
+    ls_term_dev *terms;
+    uint32_t *lut;
+    uint64_t *col;
+    uint64_t *cflip;   // [slot][n_off]
+};
+
+template <int KIND, uint32_t LX, int BLOCK>
+__device__ __forceinline__ LdsTables lds_tables(const MatvecJob &a, unsigned char *smem) {
+    LdsTables L;
+    L.terms = reinterpret_cast<ls_term_dev *>(smem);
+    const size_t terms_bytes = align16(static_cast<size_t>(a.n_terms > 0 ? a.n_terms : 1) * sizeof(ls_term_dev));
+    L.lut = reinterpret_cast<uint32_t *>(smem + terms_bytes);
+    const uint32_t lut_n = KIND == kOrbitTorus ? (1u << (2 * (LX ? LX : a.plan.lx))) : 0u;
+    L.col = reinterpret_cast<uint64_t *>(smem + terms_bytes + align16(lut_n * sizeof(uint32_t)));
+    L.cflip = L.col + 8;
+    return L;
+}
+
+// All threads of the workgroup stage the job's tables; caller syncs.
+template <int KIND, uint32_t LX, int BLOCK>
+__device__ __forceinline__ void stage_tables(const MatvecJob &a, const LdsTables &L) {
+    for (uint32_t t = threadIdx.x; t < a.n_terms; t += BLOCK) L.terms[t] = a.terms[t];
+    if constexpr (KIND == kOrbitTorus) {
+        const uint32_t n_off = a.n_terms - a.n_diag;
+        const uint32_t lut_n = 1u << (2 * (LX ? LX : a.plan.lx));
+        for (uint32_t q = threadIdx.x; q < lut_n; q += BLOCK) L.lut[q] = a.plan.pair_lut[q];
+        if (threadIdx.x < 8) L.col[threadIdx.x] = a.plan.col_ge[threadIdx.x];
+        for (uint32_t q = threadIdx.x; q < n_off * kTorusCosetSlots; q += BLOCK) {
+            const uint32_t k = q / kTorusCosetSlots, p = q % kTorusCosetSlots;
+            L.cflip[p * n_off + k] = a.cflip[q];   // transposed: lanes spread over banks
+        }
+    }
+}
+
+// Rows row0, row0 + step, ... (count of them, below dim) of one job.
+template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
+__device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L, uint64_t row0, uint64_t step,
+                                         uint32_t count) {
+    constexpr bool TRACK = CHI != kChiTrivial;
+    using T = typename Val<CPLX>::T;
+    const T *x = static_cast<const T *>(a.x);
+    T *y = static_cast<T *>(a.y);
+    const ls_term_dev *sterm = L.terms;
+    const uint32_t n_off = a.n_terms - a.n_diag;
+
+    uint64_t row = row0;
+    uint32_t k = 0;
+    if (count == 0 || row >= a.dim) return;
+
+    uint64_t r = 0;
+    double st_i = 1.0;
+    T acc[NR];
+    uint32_t t = a.n_diag;
+    W pr[kTorusCosetSlots] = {};   // p(r) for every coset (torus search)
+
+    auto begin_row = [&]() {
+        r = a.search.reps[row];
+        st_i = static_cast<double>(a.stab[row]);
+        double dre = 0.0, dim_ = 0.0;
+        for (uint32_t q = 0; q < a.n_diag; ++q) {
+            const ls_term_dev &D = sterm[q];
+            if ((r & D.sel) != D.val) continue;
+            const double sg = sign_of(r & D.sign);
+            dre += sg * D.re;
+            if constexpr (CPLX) dim_ += sg * D.im;
+        }
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const T v = x[row * a.ld + a.col + q];
+            if constexpr (CPLX) acc[q] = make_double2(dre * v.x - dim_ * v.y, dre * v.y + dim_ * v.x);
+            else acc[q] = dre * v;
+        }
+        if constexpr (KIND == kOrbitTorus) {
+#pragma unroll
+            for (uint32_t p = 0; p < kTorusCosetSlots; ++p)
+                if (p < a.plan.n_cosets) pr[p] = apply_coset<W>(a.plan.cosets[p], static_cast<W>(r), a.plan);
+        }
+        t = a.n_diag;
+    };
+    begin_row();
+
+    for (;;) {
+        while (t < a.n_terms && (r & sterm[t].sel) != sterm[t].val) ++t;
+        if (t >= a.n_terms) {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) y[row * a.ld + a.col + q] = acc[q];
+            ++k;
+            row += step;
+            if (k >= count || row >= a.dim) break;
+            begin_row();
+            continue;
+        }
+        const ls_term_dev &Tm = sterm[t];
+        uint32_t code;
+        W rep;
+        if constexpr (KIND == kOrbitTorus) {
+            const uint32_t ko = t - a.n_diag;
+            W us[kTorusCosetSlots];
+#pragma unroll
+            for (uint32_t p = 0; p < kTorusCosetSlots; ++p)
+                us[p] = p < a.plan.n_cosets ? (pr[p] ^ static_cast<W>(L.cflip[p * n_off + ko])) : W(0);
+            rep = torus_orbit_min<W, TRACK, LX, LY, NZ>(a.plan, us, L.lut, L.col, code);
+        } else {
+            const W s = static_cast<W>(r ^ Tm.flip);
+            rep = orbit_min<W, KIND, TRACK>(a.plan, s, code);
+        }
+        ++t;
+        const int64_t j = lookup_index(a.search, static_cast<uint64_t>(rep));
+        if (j < 0) continue;
+        const double f = sign_of(r & Tm.sign) * __dsqrt_rn(__ddiv_rn(static_cast<double>(a.stab[j]), st_i));
+        if constexpr (!CPLX) {
+            double coef = f * Tm.re;
+            if constexpr (CHI == kChiReal) coef *= a.plan.chi[code].x;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) acc[q] = fma(coef, x[j * a.ld + a.col + q], acc[q]);
+        } else {
+            double cre = f * Tm.re, cim = f * Tm.im;
+            if constexpr (CHI != kChiTrivial) {
+                const double2 c = a.plan.chi[code];
+                const double tre = cre * c.x - cim * c.y;
+                cim = cre * c.y + cim * c.x;
+                cre = tre;
+            }
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                const double2 v = x[j * a.ld + a.col + q];
+                acc[q].x = fma(cre, v.x, fma(-cim, v.y, acc[q].x));
+                acc[q].y = fma(cre, v.y, fma(cim, v.x, acc[q].y));
+            }
+        }
+    }
+}
+
+// Kernel variant of an operator: word size, orbit kind, torus shape.
+struct Variant {
+    int word64;      // 0: 32-bit states, 1: 64-bit
+    int kind;        // OrbitKind
+    uint32_t lx, ly, nz;   // compile-time torus shape (0 = runtime)
+    int chi;         // ChiMode used by the kernel
+    bool cplx;
+    bool operator==(const Variant &o) const {
+        return word64 == o.word64 && kind == o.kind && lx == o.lx && ly == o.ly && nz == o.nz && chi == o.chi &&
+               cplx == o.cplx;
+    }
+};
+
+}  // namespace ls
