@@ -90,6 +90,68 @@ def cpu_baseline(sector, budget_s: float):
                       f"weight-{w} states), {elems} element applications in {dt:.1f} s, single thread"}
 
 
+def batched_vs_plain(count: int, nrhs: int, reps_timed: int = 3):
+    """64 independent ring sectors (N uniform in {20..32}, J2 ~ U[0,0.6],
+    random k, translations only, complex), nrhs right-hand sides each:
+    one batched call (persistent launch, graph replay) vs count*nrhs plain
+    single-RHS ls_matvec calls on the same data."""
+    import numpy as np
+    import torch
+    import paper_2308_16712_amd as ls
+    from workloads import configs, rng
+
+    secs = configs.batched_rings(count)
+    ops, xs, ys, xp, yp = [], [], [], [], []
+    elements = 0
+    t0 = time.perf_counter()
+    for k, sec in enumerate(secs):
+        b = ls.ls_basis_build(sec)
+        op = ls.ls_operator_create(b, sec.terms)
+        elements += (op.count_elements() + b.dim) * nrhs
+        x = torch.from_numpy(rng.vector(sec.seed, b.dim, nrhs, complex_=op.is_complex)).cuda()
+        ops.append(op)
+        xs.append(x)
+        ys.append(torch.empty_like(x))
+        xp.append([x[:, q].contiguous() for q in range(nrhs)])
+        yp.append([torch.empty_like(xp[-1][q]) for q in range(nrhs)])
+    build_s = time.perf_counter() - t0
+    batch = ls.Batch(ops, [nrhs] * count)
+    batch.matvec(xs, ys)          # tunes and captures
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        best = 1e30
+        for _ in range(reps_timed):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    def plain():
+        for op, xl, yl in zip(ops, xp, yp):
+            for q in range(nrhs):
+                ls.ls_matvec(op, xl[q], yl[q])
+
+    t_batch = timed(lambda: batch.matvec(xs, ys))
+    t_plain = timed(plain)
+    # same results (the row arithmetic is shared)
+    same = all(torch.equal(ys[k][:, q], yp[k][q]) for k in range(count) for q in range(nrhs))
+    dims = [op.dim for op in ops]
+    return {"sectors": count, "nrhs": nrhs, "dtype": "c128", "dim_min": min(dims), "dim_max": max(dims),
+            "dim_total": int(sum(dims)), "element_applications": elements,
+            "batched_ms": t_batch, "plain_ms": t_plain, "speedup": t_plain / t_batch,
+            "batched_elements_per_s": elements / (t_batch * 1e-3),
+            "plain_elements_per_s": elements / (t_plain * 1e-3),
+            "identical_results": bool(same), "launches_batched": batch.info()["launches"],
+            "launches_plain": count * nrhs, "basis_build_s": build_s}
+
+
 def traffic_record(name: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source."""
@@ -114,6 +176,9 @@ def main():
     ap.add_argument("--workload", default="square6x6")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--batched-count", type=int, default=64)
+    ap.add_argument("--batched-nrhs", type=int, default=4)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run only a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -146,9 +211,7 @@ def main():
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     op = ls.ls_operator_create(basis, sector.terms)
-    reps_t, _ = basis.copy()
-    reps = reps_t.cpu().numpy().view(np.uint64)
-    n_off, rows = count_elements(reps, sector.terms)
+    n_off, rows = op.count_elements(), basis.dim
     elements = n_off + rows
     x = torch.from_numpy(rng.vector(sector.seed, basis.dim, complex_=op.is_complex)).cuda()
     y = torch.empty_like(x)
@@ -190,6 +253,11 @@ def main():
         "hbm_algorithmic_gbps": alg_bytes / (kernel_ms * 1e-3) / 1e9,
         "basis_build_s": build_s,
     }
+    if not args.no_batched:
+        print("[bench] batched vs plain", file=sys.stderr, flush=True)
+        del x, y, op, basis
+        torch.cuda.empty_cache()
+        out["batched"] = batched_vs_plain(args.batched_count, args.batched_nrhs)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sector, args.cpu_budget)

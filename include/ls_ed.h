@@ -157,6 +157,12 @@ void ls_operator_destroy(ls_operator *op);
  * complex coefficients).                                                   */
 ls_status ls_operator_info(const ls_operator *op, int *is_complex, uint64_t *dim);
 
+/* Number of off-diagonal element applications of one product: the sum over
+ * rows of the off-diagonal terms acting on the row's representative.  A
+ * product applies this many off-diagonal elements plus one diagonal element
+ * per row.  Runs on `stream` and blocks until the count is known.          */
+ls_status ls_operator_count(const ls_operator *op, uint64_t *n_offdiag, void *stream);
+
 /* y = H x (Section 5.3, the first listing's row-by-row ("pull") form: each
  * row's elements are generated from its representative, looked up, and
  * accumulated; no atomics, since H is Hermitian).

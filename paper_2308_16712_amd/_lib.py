@@ -20,7 +20,8 @@ LS_OK, LS_WNOTCONV, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_EINTERNAL = 0, 1, -1, -
 _NAMES = {0: "LS_OK", 1: "LS_WNOTCONV", -1: "LS_EINVAL", -2: "LS_ENOMEM", -3: "LS_EDEVICE", -4: "LS_EINTERNAL"}
 
 EXPORTS = ["ls_sector_check", "ls_basis_build", "ls_basis_info", "ls_basis_copy", "ls_basis_destroy", "ls_state_info",
-           "ls_index_lookup", "ls_operator_create", "ls_operator_destroy", "ls_operator_info", "ls_matvec",
+           "ls_index_lookup", "ls_operator_create", "ls_operator_destroy", "ls_operator_info",
+           "ls_operator_count", "ls_matvec",
            "ls_batch_create", "ls_batch_matvec", "ls_batch_info", "ls_batch_set_graph", "ls_batch_destroy",
            "ls_lanczos", "ls_last_error", "ls_version"]
 
@@ -72,6 +73,7 @@ def load(path: str = LIB_PATH):
         "ls_operator_create": ([P, u32, P, P], i32),
         "ls_operator_destroy": ([P], None),
         "ls_operator_info": ([P, P, P], i32),
+        "ls_operator_count": ([P, P, P], i32),
         "ls_matvec": ([P, u32, P, P, P], i32),
         "ls_batch_create": ([u32, P, P, P], i32),
         "ls_batch_matvec": ([P, P, P, P], i32),
@@ -226,6 +228,12 @@ class Operator:
     @property
     def handle(self):
         return self._h
+
+    def count_elements(self, stream=None) -> int:
+        """Off-diagonal element applications of one product (ls_operator_count)."""
+        n = ctypes.c_uint64()
+        _check(load().ls_operator_count(self._h, ctypes.byref(n), _stream_ptr(stream)))
+        return int(n.value)
 
     def matvec(self, x, y=None, stream=None):
         """y = H x for x of shape [dim] or [dim][nrhs] (float64 / complex128)."""

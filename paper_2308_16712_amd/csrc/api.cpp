@@ -185,6 +185,14 @@ ls_status ls_operator_info(const ls_operator *op, int *is_complex, uint64_t *dim
     });
 }
 
+ls_status ls_operator_count(const ls_operator *op, uint64_t *n_offdiag, void *stream) {
+    return guarded([&] {
+        LS_REQUIRE(op != nullptr && n_offdiag != nullptr, "operator and output must not be NULL");
+        *n_offdiag = ls::count_elements(op, as_stream(stream));
+        return LS_OK;
+    });
+}
+
 ls_status ls_matvec(const ls_operator *op, uint32_t nrhs, const void *d_x, void *d_y, void *stream) {
     return guarded([&] {
         LS_REQUIRE(op != nullptr, "operator must not be NULL");

@@ -176,6 +176,7 @@ void compile_terms(const ls_basis *b, uint32_t n_terms, const ls_term *terms, ls
 
 // matvec.hip
 uint32_t matvec_max_terms();   // the term table is staged in LDS
+uint64_t count_elements(const ls_operator *op, hipStream_t stream);
 void launch_matvec(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t stream);
 
 // batch.hip

@@ -38,7 +38,46 @@ struct SingleLaunch {
     }
 };
 
+// Off-diagonal element applications: per row, the acting off-diagonal terms.
+__global__ void __launch_bounds__(256) k_count_elements(const uint64_t *reps, uint64_t dim,
+                                                        const ls_term_dev *terms, uint32_t n_diag, uint32_t n_terms,
+                                                        unsigned long long *total) {
+    __shared__ unsigned long long sh[256];
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
+    unsigned long long c = 0;
+    if (i < dim) {
+        const uint64_t r = reps[i];
+        for (uint32_t t = n_diag; t < n_terms; ++t) c += (r & terms[t].sel) == terms[t].val ? 1ull : 0ull;
+    }
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (static_cast<int>(threadIdx.x) < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(total, sh[0]);
+}
+
 }  // namespace
+
+uint64_t count_elements(const ls_operator *op, hipStream_t st) {
+    const ls_basis *b = op->basis;
+    if (b->dim == 0) return 0;
+    unsigned long long *d = nullptr;
+    LS_HIP_CHECK(hipMalloc(&d, sizeof(unsigned long long)));
+    unsigned long long h = 0;
+    hipError_t e = hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_count_elements, dim3(static_cast<uint32_t>((b->dim + 255) / 256)), dim3(256), 0, st,
+                           b->d_reps, b->dim, op->d_terms, op->n_diag, op->n_diag + op->n_off, d);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipFree(d);
+    LS_HIP_CHECK(e);
+    return h;
+}
 
 uint32_t matvec_max_terms() { return kMaxLdsTerms; }
 

@@ -88,6 +88,17 @@ def test_batch_pointer_change_and_direct_launch():
         assert batch.info()["graph"] == graph
 
 
+def test_operator_count_matches_host_count():
+    for sec in _mixed_sectors()[:5]:
+        b = ls.ls_basis_build(sec)
+        op = ls.ls_operator_create(b, sec.terms)
+        reps = b.copy()[0].cpu().numpy().view(np.uint64)
+        off = sec.terms[sec.terms["flip"] != 0]
+        want = sum(int(np.count_nonzero((reps & np.uint64(t["sel_mask"])) == np.uint64(t["sel_value"])))
+                   for t in off)
+        assert op.count_elements() == want
+
+
 def test_batch_rejects_bad_input():
     sectors = _mixed_sectors()[:2]
     ops, xs, ys, refs = _setup(sectors, [1, 1])
