@@ -241,6 +241,35 @@ typedef struct {
 ls_status ls_lanczos(const ls_operator *op, const ls_lanczos_opts *opts, void *stream,
                      double *e0, uint32_t *iters, double *resid_bound);
 
+/* ---- Lanczos stepper for serving ------------------------------------------
+ * A solver holds one Lanczos solve (the recurrence, start vector, stop rule
+ * and arithmetic of ls_lanczos) with its Krylov vectors resident in HBM.
+ * ls_solver_step advances every listed solver that is not done by one
+ * iteration: the products of all of them run as one fused launch (the
+ * batched kernel), alpha and beta stay on the device, and the step ends with
+ * one synchronisation.  A solve stepped alone or among others produces the
+ * same numbers.  Calls to ls_solver_step are serialised inside the library. */
+typedef struct ls_solver ls_solver;
+
+/* Device bytes a solver for `op` with `max_iter` steps allocates.          */
+ls_status ls_solver_footprint(const ls_operator *op, uint32_t max_iter, uint64_t *bytes);
+
+/* Allocates the Krylov space and normalises the start vector (blocks).
+ * opts: as for ls_lanczos (alpha/beta outputs are ignored).
+ * Errors: LS_EINVAL, LS_ENOMEM when the Krylov space does not fit.         */
+ls_status ls_solver_create(const ls_operator *op, const ls_lanczos_opts *opts, void *stream, ls_solver **out);
+
+/* One iteration for each of the n solvers (host array; done ones skipped). */
+ls_status ls_solver_step(ls_solver *const *solvers, uint32_t n, void *stream);
+
+/* Current lowest Ritz value, steps taken, residual bound, whether the solve
+ * is finished (converged, max_iter reached or Krylov space exhausted) and
+ * whether the tolerance was met.  Any output may be NULL.                  */
+ls_status ls_solver_result(const ls_solver *solver, double *e0, uint32_t *iters, double *resid_bound, int *done,
+                           int *converged);
+
+void ls_solver_destroy(ls_solver *solver);
+
 /* Thread-local description of the last non-OK status. */
 const char *ls_last_error(void);
 

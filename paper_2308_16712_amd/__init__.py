@@ -13,7 +13,7 @@ ABI's names and only marshal arguments; device buffers are torch tensors.
 """
 from __future__ import annotations
 
-from ._lib import (EXPORTS, LIB_PATH, LSError, Basis, Batch, Operator, load, sector_check)  # noqa: F401
+from ._lib import (EXPORTS, LIB_PATH, LSError, Basis, Batch, Operator, Solver, load, sector_check)  # noqa: F401
 
 
 def ls_batch_create(ops, nrhs, graph: bool = True) -> Batch:

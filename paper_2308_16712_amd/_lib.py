@@ -23,7 +23,8 @@ EXPORTS = ["ls_sector_check", "ls_basis_build", "ls_basis_info", "ls_basis_copy"
            "ls_index_lookup", "ls_operator_create", "ls_operator_destroy", "ls_operator_info",
            "ls_operator_count", "ls_matvec",
            "ls_batch_create", "ls_batch_matvec", "ls_batch_info", "ls_batch_set_graph", "ls_batch_destroy",
-           "ls_lanczos", "ls_last_error", "ls_version"]
+           "ls_lanczos", "ls_solver_footprint", "ls_solver_create", "ls_solver_step", "ls_solver_result",
+           "ls_solver_destroy", "ls_last_error", "ls_version"]
 
 
 class LSError(RuntimeError):
@@ -81,6 +82,11 @@ def load(path: str = LIB_PATH):
         "ls_batch_set_graph": ([P, ctypes.c_int], i32),
         "ls_batch_destroy": ([P], None),
         "ls_lanczos": ([P, P, P, P, P, P], i32),
+        "ls_solver_footprint": ([P, u32, P], i32),
+        "ls_solver_create": ([P, P, P, P], i32),
+        "ls_solver_step": ([P, u32, P], i32),
+        "ls_solver_result": ([P, P, P, P, P, P], i32),
+        "ls_solver_destroy": ([P], None),
         "ls_last_error": ([], ctypes.c_char_p),
         "ls_version": ([], ctypes.c_char_p),
     }
@@ -268,6 +274,54 @@ class Operator:
     def close(self):
         if getattr(self, "_h", None):
             load().ls_operator_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver:
+    """One Lanczos solve advanced step by step (ls_solver_create); many
+    solvers advance together with Solver.step_all (one fused product)."""
+
+    def __init__(self, op: "Operator", max_iter: int, tol: float = 0.0, seed: int = 1, v0=None,
+                 reorth: bool = True, stream=None):
+        self.op = op
+        opts = LanczosOpts(int(max_iter), 1 if reorth else 0, float(tol), int(seed),
+                           _dptr(v0) if v0 is not None else None, None, None)
+        h = ctypes.c_void_p()
+        _check(load().ls_solver_create(op.handle, ctypes.byref(opts), _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def footprint(op: "Operator", max_iter: int) -> int:
+        b = ctypes.c_uint64()
+        _check(load().ls_solver_footprint(op.handle, int(max_iter), ctypes.byref(b)))
+        return int(b.value)
+
+    @staticmethod
+    def step_all(solvers, stream=None):
+        n = len(solvers)
+        if n == 0:
+            return
+        arr = (ctypes.c_void_p * n)(*[s._h.value for s in solvers])
+        _check(load().ls_solver_step(arr, n, _stream_ptr(stream)))
+
+    def result(self) -> dict:
+        e0, res = ctypes.c_double(), ctypes.c_double()
+        it = ctypes.c_uint32()
+        done, conv = ctypes.c_int(), ctypes.c_int()
+        _check(load().ls_solver_result(self._h, ctypes.byref(e0), ctypes.byref(it), ctypes.byref(res),
+                                       ctypes.byref(done), ctypes.byref(conv)))
+        return dict(e0=e0.value, iters=it.value, resid=res.value, done=bool(done.value),
+                    converged=bool(conv.value))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().ls_solver_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -243,6 +243,47 @@ void ls_batch_destroy(ls_batch *batch) {
     if (batch) ls::batch_destroy(batch);
 }
 
+ls_status ls_solver_footprint(const ls_operator *op, uint32_t max_iter, uint64_t *bytes) {
+    return guarded([&] {
+        LS_REQUIRE(op != nullptr && bytes != nullptr, "operator and output must not be NULL");
+        *bytes = ls::solver_footprint(op, max_iter);
+        return LS_OK;
+    });
+}
+
+ls_status ls_solver_create(const ls_operator *op, const ls_lanczos_opts *opts, void *stream, ls_solver **out) {
+    return guarded([&] {
+        LS_REQUIRE(op != nullptr && opts != nullptr && out != nullptr, "operator, opts and out must not be NULL");
+        LS_REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
+        LS_REQUIRE(opts->reorth <= 1, "reorth must be 0 or 1");
+        LS_REQUIRE(std::isfinite(opts->tol) && opts->tol >= 0, "tol must be >= 0");
+        LS_REQUIRE(op->basis->dim > 0, "the basis is empty");
+        *out = ls::solver_create(op, opts, as_stream(stream));
+        return LS_OK;
+    });
+}
+
+ls_status ls_solver_step(ls_solver *const *solvers, uint32_t n, void *stream) {
+    return guarded([&] {
+        LS_REQUIRE(n == 0 || solvers != nullptr, "solvers must not be NULL");
+        ls::solver_step(solvers, n, as_stream(stream));
+        return LS_OK;
+    });
+}
+
+ls_status ls_solver_result(const ls_solver *solver, double *e0, uint32_t *iters, double *resid_bound, int *done,
+                           int *converged) {
+    return guarded([&] {
+        LS_REQUIRE(solver != nullptr, "solver must not be NULL");
+        ls::solver_result(solver, e0, iters, resid_bound, done, converged);
+        return LS_OK;
+    });
+}
+
+void ls_solver_destroy(ls_solver *solver) {
+    if (solver) ls::solver_destroy(solver);
+}
+
 ls_status ls_lanczos(const ls_operator *op, const ls_lanczos_opts *opts, void *stream, double *e0, uint32_t *iters,
                      double *resid_bound) {
     return guarded([&] {

@@ -97,6 +97,7 @@ struct Group {
     uint32_t grid = 0;
     size_t lds = 0;
     bool tuned = false;
+    size_t cap_jobs = 0, cap_tiles = 0;   // device table capacities (fused path)
 };
 
 struct BatchLaunch {
@@ -459,5 +460,109 @@ void batch_info(const ls_batch *B, uint32_t *n_launches, uint32_t *n_tiles, uint
 }
 
 void batch_set_graph(ls_batch *B, bool on) { B->use_graph = on; }
+
+// ---- fused products for the Lanczos stepper --------------------------------
+//
+// The set of products changes from call to call (solves join and leave), so
+// there is no graph and no tuning here: tiles use the tuned parameters of a
+// matching batch when the cache has them, else 4 rows per lane and two
+// workgroups per CU.  Device tables grow by doubling and are reused.
+
+struct FusedState {
+    std::vector<Group> groups;
+    std::vector<std::vector<Tile>> host_tiles;
+    int n_cu = 256;
+};
+
+FusedState *fused_create() {
+    FusedState *f = new FusedState();
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess)
+        hipDeviceGetAttribute(&f->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    return f;
+}
+
+void fused_destroy(FusedState *f) {
+    if (!f) return;
+    for (auto &g : f->groups) {
+        hipFree(g.d_jobs);
+        hipFree(g.d_tiles);
+        hipFree(g.d_counter);
+    }
+    delete f;
+}
+
+namespace {
+template <typename T>
+void ensure_capacity(T **p, size_t *cap, size_t need) {
+    if (need <= *cap) return;
+    size_t c = std::max<size_t>(need, *cap * 2 + 16);
+    if (*p) LS_HIP_CHECK(hipFree(*p));
+    *p = nullptr;
+    LS_HIP_CHECK(hipMalloc(p, c * sizeof(T)));
+    *cap = c;
+}
+}  // namespace
+
+void fused_matvec(FusedState *f, uint32_t n, const ls_operator *const *ops, const void *const *xs, void *const *ys,
+                  hipStream_t st) {
+    for (auto &g : f->groups) {
+        g.jobs.clear();
+        g.cost.clear();
+        g.lds = 0;
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+        const ls_operator *op = ops[i];
+        if (op->basis->dim == 0) continue;
+        const Variant v = variant_of(op);
+        Group *g = nullptr;
+        for (auto &gg : f->groups)
+            if (gg.v == v) g = &gg;
+        if (!g) {
+            f->groups.emplace_back();
+            g = &f->groups.back();
+            g->v = v;
+            g->nr = 1;
+            LS_HIP_CHECK(hipMalloc(&g->d_counter, sizeof(uint32_t)));
+        }
+        g->jobs.push_back(job_of(op, xs[i], ys[i], 1, 0));
+        g->cost.push_back(static_cast<double>(op->basis->dim) * (op->n_off + 1.0) * op->basis->plan.n_elements);
+        g->lds = std::max(g->lds, lds_bytes(v.kind, op->n_diag + op->n_off, op->n_off, op->basis->plan.lx));
+    }
+    f->host_tiles.resize(f->groups.size());
+    for (size_t gi = 0; gi < f->groups.size(); ++gi) {
+        Group &g = f->groups[gi];
+        if (g.jobs.empty()) continue;
+        g.rpl = 4;
+        uint32_t wpc = 2;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune_cache.find(tune_key(g));
+            if (it != g_tune_cache.end()) {
+                g.rpl = it->second.first;
+                wpc = it->second.second;
+            }
+        }
+        const uint64_t rows_per_tile = static_cast<uint64_t>(block_for(g.v)) * g.rpl;
+        std::vector<uint32_t> order(g.jobs.size());
+        for (uint32_t j = 0; j < order.size(); ++j) order[j] = j;
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return g.cost[a] > g.cost[b]; });
+        auto &tiles = f->host_tiles[gi];
+        tiles.clear();
+        for (uint32_t j : order)
+            for (uint64_t r = 0; r < g.jobs[j].dim; r += rows_per_tile) tiles.push_back(Tile{j, 0, r});
+        ensure_capacity(&g.d_jobs, &g.cap_jobs, g.jobs.size());
+        ensure_capacity(&g.d_tiles, &g.cap_tiles, tiles.size());
+        LS_HIP_CHECK(hipMemcpyAsync(g.d_jobs, g.jobs.data(), g.jobs.size() * sizeof(MatvecJob),
+                                    hipMemcpyHostToDevice, st));
+        LS_HIP_CHECK(hipMemcpyAsync(g.d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
+                                    st));
+        g.n_tiles = static_cast<uint32_t>(tiles.size());
+        g.grid = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(f->n_cu) * wpc, g.n_tiles));
+        BatchLaunch L{&g, st};
+        dispatch(g.v, 1, L);
+        LS_HIP_CHECK(hipGetLastError());
+    }
+}
 
 }  // namespace ls

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "ls_internal.hpp"
@@ -358,6 +359,255 @@ ls_status run_lanczos(const ls_operator *op, const ls_lanczos_opts *o, hipStream
                       double *resid) {
     if (op->is_complex) return lanczos_impl<true>(op, o, st, e0, iters, resid);
     return lanczos_impl<false>(op, o, st, e0, iters, resid);
+}
+
+// ---- the stepper: one Lanczos iteration for many solves at once ----------
+//
+// Same recurrence, start vector, stop rule and arithmetic as run_lanczos,
+// but alpha and beta stay on the device (kernels read them through
+// pointers), the products of all active solves run as one fused launch, and
+// a step ends with one copy of every solve's (alpha, beta) and one sync.
+
+namespace {
+
+// w -= alpha v + beta_prev vp with alpha = s[0].x and beta_prev = *bp
+template <bool CPLX>
+__global__ void __launch_bounds__(kBlock) k_three_term_dev(void *pw, const void *pv, const void *pvp, uint64_t n,
+                                                           const double2 *s, const double *bp) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double alpha = s[0].x;
+    const double beta = pvp ? *bp : 0.0;
+    if constexpr (CPLX) {
+        double2 w = static_cast<double2 *>(pw)[i];
+        const double2 v = static_cast<const double2 *>(pv)[i];
+        w.x -= alpha * v.x;
+        w.y -= alpha * v.y;
+        if (pvp) {
+            const double2 u = static_cast<const double2 *>(pvp)[i];
+            w.x -= beta * u.x;
+            w.y -= beta * u.y;
+        }
+        static_cast<double2 *>(pw)[i] = w;
+    } else {
+        double w = static_cast<double *>(pw)[i];
+        w -= alpha * static_cast<const double *>(pv)[i];
+        if (pvp) w -= beta * static_cast<const double *>(pvp)[i];
+        static_cast<double *>(pw)[i] = w;
+    }
+}
+
+// scal[0] = alpha (from the reduced dot), scal[1] = sqrt(reduced norm^2)
+__global__ void k_alpha_beta(const double2 *dot_a, const double2 *dot_b, double *scal) {
+    scal[0] = dot_a[0].x;
+    scal[1] = __dsqrt_rn(dot_b[0].x);   // correctly rounded, as std::sqrt on the host
+}
+
+__global__ void __launch_bounds__(kBlock) k_div_dev(double *dst, const double *src, uint64_t n, const double *s) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < n) dst[i] = src[i] / *s;
+}
+
+}  // namespace
+
+}  // namespace ls
+
+struct ls_solver {
+    const ls_operator *op = nullptr;
+    bool cplx = false;
+    uint64_t n = 0;
+    uint32_t m = 0;
+    double tol = 0.0;
+    bool reorth = true;
+    void *V = nullptr;            // [m][n]
+    void *w = nullptr;            // [n]
+    double2 *partial = nullptr;   // [kDotBlocks][m]
+    double2 *hs = nullptr;        // [m] reorthogonalisation coefficients
+    double2 *dots = nullptr;      // [2]: <v_k, w>, <w, w>
+    double *scal = nullptr;       // [2]: alpha_k, beta_{k+1}
+    double *bprev = nullptr;      // beta_k (device copy)
+    double *host = nullptr;       // pinned [2]
+    std::vector<double> alpha, beta;
+    uint32_t k = 0;
+    double e0 = 0.0, resid = INFINITY, prev = 0.0;
+    bool have_prev = false, done = false, converged = false;
+};
+
+namespace ls {
+
+namespace {
+std::mutex g_step_mu;
+FusedState *g_fused = nullptr;
+
+void free_solver(ls_solver *s) {
+    if (!s) return;
+    hipFree(s->V);
+    hipFree(s->w);
+    hipFree(s->partial);
+    hipFree(s->hs);
+    hipFree(s->dots);
+    hipFree(s->scal);
+    hipFree(s->bprev);
+    if (s->host) hipHostFree(s->host);
+    delete s;
+}
+
+template <bool CPLX>
+void enqueue_dot(ls_solver *s, const void *a, const void *b, double2 *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_dot_partial<CPLX>, dim3(kDotBlocks), dim3(kBlock), 0, st, a, b, s->n, s->partial);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, s->partial, kDotBlocks, 1, out);
+}
+
+// everything of step k after the product
+template <bool CPLX>
+void enqueue_after_product(ls_solver *s, hipStream_t st) {
+    using T = typename V<CPLX>::T;
+    const uint64_t n = s->n;
+    T *Vb = static_cast<T *>(s->V);
+    T *w = static_cast<T *>(s->w);
+    const uint32_t k = s->k;
+    T *vk = Vb + static_cast<uint64_t>(k) * n;
+    enqueue_dot<CPLX>(s, vk, w, s->dots, st);
+    hipLaunchKernelGGL(k_three_term_dev<CPLX>, dim3(grid(n)), dim3(kBlock), 0, st, w, vk,
+                       k > 0 ? Vb + static_cast<uint64_t>(k - 1) * n : nullptr, n, s->dots, s->bprev);
+    if (s->reorth) {
+        const int nv = static_cast<int>(k) + 1;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int j0 = 0; j0 < nv; j0 += kTile)
+                hipLaunchKernelGGL(k_multidot_partial<CPLX>, dim3(kDotBlocks), dim3(kBlock), 0, st, Vb, n, j0,
+                                   std::min(kTile, nv - j0), w, s->partial, static_cast<int>(s->m));
+            hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(kBlock), 0, st, s->partial, kDotBlocks,
+                               static_cast<int>(s->m), s->hs);
+            hipLaunchKernelGGL(k_gemv_sub<CPLX>, dim3(grid(n)), dim3(kBlock), 0, st, Vb, n, nv, s->hs, w);
+        }
+    }
+    enqueue_dot<CPLX>(s, w, w, s->dots + 1, st);
+    hipLaunchKernelGGL(k_alpha_beta, dim3(1), dim3(1), 0, st, s->dots, s->dots + 1, s->scal);
+    if (k + 1 < s->m) {
+        const uint64_t nd = n * (CPLX ? 2 : 1);
+        hipLaunchKernelGGL(k_div_dev, dim3(grid(nd)), dim3(kBlock), 0, st,
+                           reinterpret_cast<double *>(Vb + static_cast<uint64_t>(k + 1) * n),
+                           reinterpret_cast<const double *>(w), nd, s->scal + 1);
+        LS_HIP_CHECK(hipMemcpyAsync(s->bprev, s->scal + 1, sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+    LS_HIP_CHECK(hipMemcpyAsync(s->host, s->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    LS_HIP_CHECK(hipGetLastError());
+}
+
+// host bookkeeping of step k, identical to run_lanczos
+void finish_step(ls_solver *s) {
+    const double a = s->host[0], bnext = s->host[1];
+    s->alpha.push_back(a);
+    s->e0 = tridiag_lowest(s->alpha, s->beta);
+    s->resid = bnext * tridiag_last_component(s->alpha, s->beta, s->e0);
+    const double scale = std::max(1.0, std::fabs(s->e0));
+    if (s->tol > 0 && s->have_prev && std::fabs(s->e0 - s->prev) < s->tol * scale &&
+        s->resid < std::sqrt(s->tol) * scale) {
+        s->converged = true;
+        s->done = true;
+        return;
+    }
+    s->prev = s->e0;
+    s->have_prev = true;
+    s->k += 1;
+    if (s->k >= s->m || bnext == 0.0) {
+        s->done = true;
+        return;
+    }
+    s->beta.push_back(bnext);
+}
+
+}  // namespace
+
+uint64_t solver_footprint(const ls_operator *op, uint32_t max_iter) {
+    const uint64_t n = op->basis->dim;
+    const uint64_t m = std::min<uint64_t>(max_iter, n);
+    const uint64_t es = op->is_complex ? 16 : 8;
+    return (m + 1) * n * es + static_cast<uint64_t>(kDotBlocks) * std::max<uint64_t>(m, 1) * 16 + 4096;
+}
+
+ls_solver *solver_create(const ls_operator *op, const ls_lanczos_opts *o, hipStream_t st) {
+    ls_solver *s = new ls_solver();
+    try {
+        s->op = op;
+        s->cplx = op->is_complex;
+        s->n = op->basis->dim;
+        s->m = static_cast<uint32_t>(std::min<uint64_t>(o->max_iter, s->n));
+        s->tol = o->tol;
+        s->reorth = o->reorth != 0;
+        const size_t es = s->cplx ? 16 : 8;
+        if (hipMalloc(&s->V, static_cast<size_t>(s->m) * s->n * es) != hipSuccess)
+            throw Error{LS_ENOMEM, "cannot allocate the Krylov vectors"};
+        LS_HIP_CHECK(hipMalloc(&s->w, s->n * es));
+        LS_HIP_CHECK(hipMalloc(&s->partial, static_cast<size_t>(kDotBlocks) * std::max<uint32_t>(s->m, 1) *
+                                                sizeof(double2)));
+        LS_HIP_CHECK(hipMalloc(&s->hs, std::max<uint32_t>(s->m, 1) * sizeof(double2)));
+        LS_HIP_CHECK(hipMalloc(&s->dots, 2 * sizeof(double2)));
+        LS_HIP_CHECK(hipMalloc(&s->scal, 2 * sizeof(double)));
+        LS_HIP_CHECK(hipMalloc(&s->bprev, sizeof(double)));
+        LS_HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&s->host), 2 * sizeof(double)));
+        // start vector, normalised exactly as run_lanczos does
+        const uint64_t nd = s->n * (s->cplx ? 2 : 1);
+        if (o->d_v0)
+            LS_HIP_CHECK(hipMemcpyAsync(s->w, o->d_v0, s->n * es, hipMemcpyDeviceToDevice, st));
+        else
+            hipLaunchKernelGGL(k_fill_uniform, dim3(grid(nd)), dim3(kBlock), 0, st, static_cast<double *>(s->w), nd,
+                               o->seed);
+        if (s->cplx) enqueue_dot<true>(s, s->w, s->w, s->dots, st);
+        else enqueue_dot<false>(s, s->w, s->w, s->dots, st);
+        double2 r;
+        LS_HIP_CHECK(hipMemcpyAsync(&r, s->dots, sizeof(double2), hipMemcpyDeviceToHost, st));
+        LS_HIP_CHECK(hipStreamSynchronize(st));
+        const double nrm0 = std::sqrt(r.x);
+        if (!(nrm0 > 0.0)) throw Error{LS_EINVAL, "the start vector is zero"};
+        hipLaunchKernelGGL(k_div, dim3(grid(nd)), dim3(kBlock), 0, st, static_cast<double *>(s->V),
+                           static_cast<const double *>(s->w), nd, nrm0);
+        LS_HIP_CHECK(hipGetLastError());
+        LS_HIP_CHECK(hipStreamSynchronize(st));
+    } catch (...) {
+        free_solver(s);
+        throw;
+    }
+    return s;
+}
+
+void solver_destroy(ls_solver *s) {
+    hipDeviceSynchronize();
+    free_solver(s);
+}
+
+void solver_step(ls_solver *const *ss, uint32_t n, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_step_mu);
+    if (!g_fused) g_fused = fused_create();
+    std::vector<ls_solver *> act;
+    for (uint32_t i = 0; i < n; ++i)
+        if (ss[i] && !ss[i]->done) act.push_back(ss[i]);
+    if (act.empty()) return;
+    // one fused launch for every active solve's product w = H v_k
+    std::vector<const ls_operator *> ops;
+    std::vector<const void *> xs;
+    std::vector<void *> ys;
+    for (ls_solver *s : act) {
+        const size_t es = s->cplx ? 16 : 8;
+        ops.push_back(s->op);
+        xs.push_back(static_cast<const char *>(s->V) + static_cast<size_t>(s->k) * s->n * es);
+        ys.push_back(s->w);
+    }
+    fused_matvec(g_fused, static_cast<uint32_t>(act.size()), ops.data(), xs.data(), ys.data(), st);
+    for (ls_solver *s : act) {
+        if (s->cplx) enqueue_after_product<true>(s, st);
+        else enqueue_after_product<false>(s, st);
+    }
+    LS_HIP_CHECK(hipStreamSynchronize(st));
+    for (ls_solver *s : act) finish_step(s);
+}
+
+void solver_result(const ls_solver *s, double *e0, uint32_t *iters, double *resid, int *done, int *converged) {
+    if (e0) *e0 = s->e0;
+    if (iters) *iters = static_cast<uint32_t>(s->alpha.size());
+    if (resid) *resid = s->resid;
+    if (done) *done = s->done ? 1 : 0;
+    if (converged) *converged = s->converged ? 1 : 0;
 }
 
 }  // namespace ls

@@ -186,6 +186,20 @@ void batch_matvec(ls_batch *b, const void *const *xs, void *const *ys, hipStream
 void batch_info(const ls_batch *b, uint32_t *n_launches, uint32_t *n_tiles, uint32_t *graph);
 void batch_set_graph(ls_batch *b, bool on);
 
+// fused products over a changing set of operators (batch.hip)
+struct FusedState;
+FusedState *fused_create();
+void fused_destroy(FusedState *f);
+void fused_matvec(FusedState *f, uint32_t n, const ls_operator *const *ops, const void *const *xs,
+                  void *const *ys, hipStream_t stream);
+
+// Lanczos stepper (lanczos.hip)
+uint64_t solver_footprint(const ls_operator *op, uint32_t max_iter);
+ls_solver *solver_create(const ls_operator *op, const ls_lanczos_opts *o, hipStream_t stream);
+void solver_destroy(ls_solver *s);
+void solver_step(ls_solver *const *solvers, uint32_t n, hipStream_t stream);
+void solver_result(const ls_solver *s, double *e0, uint32_t *iters, double *resid, int *done, int *converged);
+
 // lanczos.hip
 ls_status run_lanczos(const ls_operator *op, const ls_lanczos_opts *o, hipStream_t stream,
                       double *e0, uint32_t *iters, double *resid);

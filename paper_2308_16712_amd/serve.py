@@ -1,0 +1,215 @@
+"""Serving loop: Lanczos ground-state requests with continuous batching.
+
+Requests (a sector and its Hamiltonian) arrive over time.  The server
+admits a queued request when its HBM footprint fits the budget, builds its
+basis and operator, and creates a Lanczos solver whose Krylov vectors stay
+resident.  Every iteration of the loop advances *all* admitted solves by one
+Lanczos step with one fused product launch (ls_solver_step); a solve leaves
+as soon as it converges and its memory returns to the budget, so requests
+that arrive while others run join the next step.
+
+The baseline serves the same trace one request at a time with ls_lanczos.
+
+The footprint is known before anything is allocated: the sector dimension
+follows from the character formula dim = (1/|G|) sum_g conj(chi(g)) fix_w(g),
+where fix_w(g) counts the weight-w states that g fixes (a product over the
+cycles of the permutation).
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+from ._lib import Basis, Operator, Solver
+
+
+def _cycles(perm) -> List[int]:
+    n = len(perm)
+    seen = [False] * n
+    out = []
+    for i in range(n):
+        if seen[i]:
+            continue
+        L, j = 0, i
+        while not seen[j]:
+            seen[j] = True
+            j = int(perm[j])
+            L += 1
+        out.append(L)
+    return out
+
+
+def _fixed(perm, flip, n, w) -> int:
+    cyc = _cycles(perm)
+    if flip:
+        if any(L % 2 for L in cyc) or (w >= 0 and 2 * w != n):
+            return 0
+        return 2 ** len(cyc)
+    if w < 0:
+        return 2 ** len(cyc)
+    poly = [1]
+    for L in cyc:
+        nxt = [0] * (len(poly) + L)
+        for k, c in enumerate(poly):
+            nxt[k] += c
+            nxt[k + L] += c
+        poly = nxt
+    return poly[w] if w < len(poly) else 0
+
+
+def sector_dimension(sector) -> int:
+    g = sector.group
+    chi = g.chi[:, 0] - 1j * g.chi[:, 1]          # conj(chi)
+    tot = 0j
+    for e in range(g.size):
+        tot += chi[e] * _fixed(g.perm[e], g.flip[e], sector.n_sites, sector.weight)
+    return int(round((tot / g.size).real))
+
+
+def footprint_bytes(sector, max_iter: int) -> int:
+    """Device bytes a request holds while admitted: representatives and
+    stabilizers, search layout, Krylov space, and the build's mark words."""
+    from math import comb
+    dim = sector_dimension(sector)
+    complex_ = not (np.all(sector.group.chi[:, 1] == 0) and np.all(sector.terms["im"] == 0))
+    es = 16 if complex_ else 8
+    m = min(max_iter, max(dim, 1))
+    cand = comb(sector.n_sites, sector.weight) if sector.weight >= 0 else 2 ** sector.n_sites
+    return dim * 10 + (1 << 24) + (m + 1) * dim * es + 1024 * m * 16 + cand // 8 + (64 << 20)
+
+
+@dataclass
+class Record:
+    rid: int
+    name: str
+    dim: int
+    arrival: float
+    admitted: float = 0.0
+    done: float = 0.0
+    e0: float = float("nan")
+    iters: int = 0
+    converged: bool = False
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclass
+class _Live:
+    rec: Record
+    basis: Basis
+    op: Operator
+    solver: Solver
+    bytes: int
+
+
+@dataclass
+class ServeStats:
+    records: List[Record] = field(default_factory=list)
+    makespan: float = 0.0
+    steps: int = 0
+    max_active: int = 0
+    peak_bytes: int = 0
+
+    def summary(self) -> dict:
+        lat = np.array([r.latency for r in self.records]) * 1e3
+        return dict(requests=len(self.records), makespan_s=self.makespan,
+                    throughput_rps=len(self.records) / self.makespan if self.makespan > 0 else 0.0,
+                    p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                    mean_ms=float(lat.mean()), steps=self.steps, max_active=self.max_active,
+                    peak_bytes=self.peak_bytes,
+                    converged=int(sum(r.converged for r in self.records)))
+
+
+def _wait_until(t0: float, t: float):
+    d = t - (time.perf_counter() - t0)
+    if d > 0:
+        time.sleep(d)
+
+
+def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=None) -> ServeStats:
+    """Continuous batching: admit by footprint, step every admitted solve
+    together, retire converged ones.  Arrivals are replayed in real time."""
+    import torch
+    pending = sorted(trace, key=lambda r: r.arrival)
+    queue: List = []
+    live: List[_Live] = []
+    used = 0
+    stats = ServeStats()
+    t0 = time.perf_counter()
+    i = 0
+    while i < len(pending) or queue or live:
+        now = time.perf_counter() - t0
+        while i < len(pending) and pending[i].arrival <= now:
+            queue.append(pending[i])
+            i += 1
+        # first-fit admission in arrival order
+        for req in list(queue):
+            need = footprint_bytes(req.sector, max_iter)
+            if need > hbm_budget:
+                raise ValueError(f"request {req.rid} needs {need} bytes, more than the whole budget")
+            if used + need > hbm_budget:
+                continue
+            queue.remove(req)
+            rec = Record(req.rid, req.sector.name, 0, req.arrival, admitted=time.perf_counter() - t0)
+            b = Basis.from_sector(req.sector)
+            op = Operator(b, req.sector.terms)
+            s = Solver(op, max_iter, tol=tol, seed=req.sector.seed)
+            rec.dim = b.dim
+            live.append(_Live(rec, b, op, s, need))
+            used += need
+            stats.peak_bytes = max(stats.peak_bytes, used)
+            if log:
+                log(f"[serve] t={rec.admitted:.3f}s admit {req.rid} {req.sector.name} dim={b.dim} active={len(live)}")
+        if live:
+            stats.max_active = max(stats.max_active, len(live))
+            Solver.step_all([lv.solver for lv in live])
+            stats.steps += 1
+            keep = []
+            for lv in live:
+                r = lv.solver.result()
+                if r["done"]:
+                    lv.rec.done = time.perf_counter() - t0
+                    lv.rec.e0, lv.rec.iters, lv.rec.converged = r["e0"], r["iters"], r["converged"]
+                    stats.records.append(lv.rec)
+                    lv.solver.close()
+                    lv.op.close()
+                    lv.basis.close()
+                    used -= lv.bytes
+                else:
+                    keep.append(lv)
+            live = keep
+        elif i < len(pending) and not queue:
+            _wait_until(t0, pending[i].arrival)
+        torch.cuda.synchronize()
+    stats.makespan = time.perf_counter() - t0
+    stats.records.sort(key=lambda r: r.rid)
+    return stats
+
+
+def serve_one_at_a_time(trace, max_iter: int = 150, tol: float = 1e-10) -> ServeStats:
+    """Baseline: each request in arrival order, alone, with ls_lanczos."""
+    pending = sorted(trace, key=lambda r: r.arrival)
+    stats = ServeStats()
+    t0 = time.perf_counter()
+    for req in pending:
+        _wait_until(t0, req.arrival)
+        rec = Record(req.rid, req.sector.name, 0, req.arrival, admitted=time.perf_counter() - t0)
+        b = Basis.from_sector(req.sector)
+        op = Operator(b, req.sector.terms)
+        r = op.lanczos(max_iter, tol=tol, seed=req.sector.seed)
+        rec.dim = b.dim
+        rec.done = time.perf_counter() - t0
+        rec.e0, rec.iters, rec.converged = r["e0"], r["iters"], r["converged"]
+        stats.records.append(rec)
+        stats.steps += r["iters"]
+        op.close()
+        b.close()
+    stats.makespan = time.perf_counter() - t0
+    stats.max_active = 1
+    stats.records.sort(key=lambda r: r.rid)
+    return stats
