@@ -152,6 +152,31 @@ def batched_vs_plain(count: int, nrhs: int, reps_timed: int = 3):
             "launches_plain": count * nrhs, "basis_build_s": build_s}
 
 
+def serving(count: int, rate: float, budget_gb: float, max_iter: int, tol: float):
+    """Poisson stream of ground-state requests (rings N in {24..36}, 4x6 and
+    6x6 J1-J2, fully symmetric sectors), served with continuous batching and
+    one at a time on the same trace."""
+    import numpy as np
+    from paper_2308_16712_amd import serve as sv
+    from workloads import configs
+
+    trace = configs.serving_trace(count=count, rate=rate)
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    served = sv.serve(trace, int(budget_gb * 2 ** 30), max_iter=max_iter, tol=tol, log=log)
+    alone = sv.serve_one_at_a_time(trace, max_iter=max_iter, tol=tol)
+    de = max(abs(a.e0 - b.e0) / max(1.0, abs(b.e0)) for a, b in zip(served.records, alone.records))
+    s, b = served.summary(), alone.summary()
+    work = sum(r.dim * r.iters for r in served.records)
+    return {"requests": count, "arrival_rate_per_s": rate, "tol": tol, "max_iter": max_iter,
+            "hbm_budget_gb": budget_gb, "dims": sorted({r.dim for r in served.records}),
+            "served": s, "one_at_a_time": b,
+            "speedup_throughput": s["throughput_rps"] / b["throughput_rps"],
+            "p50_ratio": b["p50_ms"] / s["p50_ms"], "p99_ratio": b["p99_ms"] / s["p99_ms"],
+            "max_rel_e0_diff_served_vs_alone": de, "row_steps": work,
+            "offered_load_note": "arrivals at the stated rate exceed capacity for the large sectors; "
+                                 "latency includes queueing"}
+
+
 def traffic_record(name: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source."""
@@ -179,6 +204,11 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--batched-count", type=int, default=64)
     ap.add_argument("--batched-nrhs", type=int, default=4)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving comparison")
+    ap.add_argument("--serve-count", type=int, default=12)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-max-iter", type=int, default=150)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run only a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -258,6 +288,12 @@ def main():
         del x, y, op, basis
         torch.cuda.empty_cache()
         out["batched"] = batched_vs_plain(args.batched_count, args.batched_nrhs)
+        torch.cuda.empty_cache()
+    if not args.no_serving:
+        print("[bench] serving", file=sys.stderr, flush=True)
+        out["serving"] = serving(args.serve_count, args.serve_rate, args.serve_budget_gb, args.serve_max_iter,
+                                 1e-10)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sector, args.cpu_budget)

@@ -465,8 +465,9 @@ void batch_set_graph(ls_batch *B, bool on) { B->use_graph = on; }
 //
 // The set of products changes from call to call (solves join and leave), so
 // there is no graph and no tuning here: tiles use the tuned parameters of a
-// matching batch when the cache has them, else 4 rows per lane and two
-// workgroups per CU.  Device tables grow by doubling and are reused.
+// matching batch when the cache has them, else 4 rows per lane and as many
+// workgroups per CU as occupancy allows.  Device tables grow by doubling and
+// are reused.
 
 struct FusedState {
     std::vector<Group> groups;
@@ -534,7 +535,7 @@ void fused_matvec(FusedState *f, uint32_t n, const ls_operator *const *ops, cons
         Group &g = f->groups[gi];
         if (g.jobs.empty()) continue;
         g.rpl = 4;
-        uint32_t wpc = 2;
+        uint32_t wpc = static_cast<uint32_t>(std::max(1, 2048 / block_for(g.v)));   // full occupancy
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tune_cache.find(tune_key(g));

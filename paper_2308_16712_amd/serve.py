@@ -131,9 +131,31 @@ def _wait_until(t0: float, t: float):
         time.sleep(d)
 
 
-def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=None) -> ServeStats:
-    """Continuous batching: admit by footprint, step every admitted solve
-    together, retire converged ones.  Arrivals are replayed in real time."""
+SMALL_DIM = 1 << 20   # below this a single product cannot fill the GPU
+
+
+def _pick(live, policy: str):
+    """Solves advanced in this iteration.
+
+    "small-first": every small solve (its product alone cannot fill the
+    GPU, so fusing them costs little) plus the oldest large one; large
+    solves saturate the device on their own, so they advance one at a time
+    in arrival order instead of slowing every small solve down.
+    "all": every admitted solve in one fused step (plain lock-step)."""
+    if policy == "all":
+        return list(live)
+    small = [lv for lv in live if lv.rec.dim < SMALL_DIM]
+    large = [lv for lv in live if lv.rec.dim >= SMALL_DIM]
+    if large:
+        small.append(min(large, key=lambda lv: (lv.rec.arrival, lv.rec.rid)))
+    return small
+
+
+def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=None,
+          policy: str = "small-first") -> ServeStats:
+    """Continuous batching: admit by footprint, advance the admitted solves
+    with fused steps (see _pick), retire converged ones.  Arrivals are
+    replayed in real time."""
     import torch
     pending = sorted(trace, key=lambda r: r.arrival)
     queue: List = []
@@ -167,11 +189,13 @@ def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=N
                 log(f"[serve] t={rec.admitted:.3f}s admit {req.rid} {req.sector.name} dim={b.dim} active={len(live)}")
         if live:
             stats.max_active = max(stats.max_active, len(live))
-            Solver.step_all([lv.solver for lv in live])
+            step = _pick(live, policy)
+            Solver.step_all([lv.solver for lv in step])
             stats.steps += 1
             keep = []
+            stepped = {id(lv) for lv in step}
             for lv in live:
-                r = lv.solver.result()
+                r = lv.solver.result() if id(lv) in stepped else {"done": False}
                 if r["done"]:
                     lv.rec.done = time.perf_counter() - t0
                     lv.rec.e0, lv.rec.iters, lv.rec.converged = r["e0"], r["iters"], r["converged"]
