@@ -101,6 +101,21 @@ typedef struct {
  * LS_EDEVICE, LS_EINTERNAL (a group-compiler self-check failed).          */
 ls_status ls_basis_build(const ls_sector_desc *desc, void *stream, ls_basis **out);
 
+/* Count-only enumeration: the filter of ls_basis_build (Section 5.2) over
+ * the candidates whose rank lies in [rank_begin, rank_end), without storing
+ * anything; it gives the sector dimensions of Section 6, Table 2, for
+ * sectors whose representatives would not fit in memory.  The rank of a
+ * candidate is its colex rank among the weight-w bitstrings (with U(1)) or
+ * the bitstring itself (without); rank_end is clamped to the number of
+ * candidates, so rank_end = UINT64_MAX counts the whole sector, and
+ * consecutive ranges add up (callers may split the range to report
+ * progress).  Outputs (host): *n_members, and *n_candidates = C(N, w) or
+ * 2^N (may be NULL).  Blocks until the count on `stream` has finished;
+ * device scratch is 16 KiB plus the compiled group.
+ * Errors: as ls_basis_build; LS_EINVAL also for rank_begin > rank_end.   */
+ls_status ls_sector_count(const ls_sector_desc *desc, uint64_t rank_begin, uint64_t rank_end,
+                          uint64_t *n_members, uint64_t *n_candidates, void *stream);
+
 /* Validates a sector descriptor and compiles its group on the host only (no
  * device work): the checks of ls_basis_build plus the group compiler's own
  * self-checks (Benes routing verified on every wire).  Optional outputs

@@ -13,7 +13,8 @@ ABI's names and only marshal arguments; device buffers are torch tensors.
 """
 from __future__ import annotations
 
-from ._lib import (EXPORTS, LIB_PATH, LSError, Basis, Batch, Operator, Solver, load, sector_check)  # noqa: F401
+from ._lib import (EXPORTS, LIB_PATH, LSError, Basis, Batch, Operator, Solver, load, sector_check,
+                   sector_count)  # noqa: F401
 
 
 def ls_batch_create(ops, nrhs, graph: bool = True) -> Batch:
@@ -29,6 +30,13 @@ def ls_sector_check(sector) -> dict:
     """Validate a sector and compile its group on the host only."""
     g = sector.group
     return sector_check(sector.n_sites, sector.weight, g.perm, g.flip, g.chi)
+
+
+def ls_sector_count(sector, rank_begin: int = 0, rank_end: int = 2**64 - 1, stream=None) -> tuple:
+    """(members, candidates) of a sector over a candidate-rank range, without
+    storing the representatives."""
+    g = sector.group
+    return sector_count(sector.n_sites, sector.weight, g.perm, g.flip, g.chi, rank_begin, rank_end, stream)
 
 
 def ls_basis_build(sector, stream=None) -> Basis:

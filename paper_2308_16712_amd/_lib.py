@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libls_ed.so")
 LS_OK, LS_WNOTCONV, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_EINTERNAL = 0, 1, -1, -2, -3, -4
 _NAMES = {0: "LS_OK", 1: "LS_WNOTCONV", -1: "LS_EINVAL", -2: "LS_ENOMEM", -3: "LS_EDEVICE", -4: "LS_EINTERNAL"}
 
-EXPORTS = ["ls_sector_check", "ls_basis_build", "ls_basis_info", "ls_basis_copy", "ls_basis_destroy", "ls_state_info",
+EXPORTS = ["ls_sector_check", "ls_sector_count", "ls_basis_build", "ls_basis_info", "ls_basis_copy", "ls_basis_destroy", "ls_state_info",
            "ls_index_lookup", "ls_operator_create", "ls_operator_destroy", "ls_operator_info",
            "ls_operator_count", "ls_matvec",
            "ls_batch_create", "ls_batch_matvec", "ls_batch_info", "ls_batch_set_graph", "ls_batch_destroy",
@@ -65,6 +65,7 @@ def load(path: str = LIB_PATH):
     P, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
     sig = {
         "ls_sector_check": ([P, P, P, P, P], i32),
+        "ls_sector_count": ([P, u64, u64, P, P, P], i32),
         "ls_basis_build": ([P, P, P], i32),
         "ls_basis_info": ([P, P, P, P], i32),
         "ls_basis_copy": ([P, P, P, P], i32),
@@ -133,6 +134,23 @@ def sector_check(n_sites: int, hamming_weight: int, perm, flip, chi) -> dict:
     _check(L.ls_sector_check(ctypes.byref(desc), ctypes.byref(lx), ctypes.byref(ly), ctypes.byref(pf),
                              ctypes.byref(nc)))
     return dict(lx=lx.value, ly=ly.value, pair_flip=pf.value, n_cosets=nc.value)
+
+
+def sector_count(n_sites: int, hamming_weight: int, perm, flip, chi, rank_begin: int = 0,
+                 rank_end: int = 2**64 - 1, stream=None) -> tuple:
+    """(members, candidates) among the candidates of rank [rank_begin,
+    rank_end), counted on the GPU without storing them (ls_sector_count)."""
+    L = load()
+    perm = np.ascontiguousarray(perm, dtype=np.uint16)
+    flip = np.ascontiguousarray(flip, dtype=np.uint8)
+    chi = np.ascontiguousarray(chi, dtype=np.float64)
+    desc = SectorDesc(n_sites, hamming_weight, perm.shape[0], perm.ctypes.data, flip.ctypes.data,
+                      chi.ctypes.data)
+    m, c = ctypes.c_uint64(), ctypes.c_uint64()
+    # synchronous: without a stream the count runs on the null stream
+    _check(L.ls_sector_count(ctypes.byref(desc), rank_begin, rank_end, ctypes.byref(m), ctypes.byref(c),
+                             _stream_ptr(stream) if stream is not None else None))
+    return m.value, c.value
 
 
 class Basis:

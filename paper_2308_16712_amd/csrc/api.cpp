@@ -76,6 +76,26 @@ ls_status ls_basis_build(const ls_sector_desc *desc, void *stream, ls_basis **ou
     return st;
 }
 
+ls_status ls_sector_count(const ls_sector_desc *desc, uint64_t rank_begin, uint64_t rank_end, uint64_t *n_members,
+                          uint64_t *n_candidates, void *stream) {
+    ls_basis *b = nullptr;
+    ls_status st = guarded([&] {
+        LS_REQUIRE(desc != nullptr && n_members != nullptr, "desc and n_members must not be NULL");
+        LS_REQUIRE(rank_begin <= rank_end, "rank_begin must not exceed rank_end");
+        ls::GroupPlan plan = ls::compile_group(*desc);
+        b = new ls_basis();
+        b->plan = std::move(plan);
+        b->weight = desc->hamming_weight;
+        LS_HIP_CHECK(hipGetDevice(&b->device));
+        ls::upload_plan(b);
+        *n_members = ls::count_members(b, rank_begin, rank_end, as_stream(stream));
+        if (n_candidates) *n_candidates = ls::candidate_count(b);
+        return LS_OK;
+    });
+    free_basis(b);
+    return st;
+}
+
 ls_status ls_sector_check(const ls_sector_desc *desc, uint32_t *lx, uint32_t *ly, uint32_t *pair_flip,
                           uint32_t *n_cosets) {
     return guarded([&] {

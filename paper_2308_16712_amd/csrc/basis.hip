@@ -51,18 +51,93 @@ __device__ __forceinline__ W next_combination(W x) {
     return (((r ^ x) >> 2) >> z) | r;
 }
 
-// s kept iff no image is smaller and every image equal to s has chi == 1.
-template <typename W, int KIND>
-__device__ __forceinline__ bool is_member(const PlanDev &P, W s) {
-    bool keep = true;
-    for_each_image<W, KIND>(P, s, [&](W v, uint32_t code) {
-        if (v < s || (v == s && !chi_is_one(P, code))) {
-            keep = false;
-            return false;
+// Membership of cnt consecutive candidates s, next(s), ...: s is kept iff no
+// group image is smaller and every image equal to s has chi == 1.  hit(q)
+// is called for every kept candidate q.
+//
+// Most candidates are rejected after one or two images, while a member (about
+// one candidate in |G|) needs every image.  A loop over candidates with the
+// group walk inside would run each wave at the pace of its slowest lane for
+// every candidate; here one iteration checks one image (with its spin-flipped
+// partner) of the lane's current candidate, and a lane moves on to its next
+// candidate as soon as the current one is decided, so a wave's time is the
+// largest per-lane total over the run rather than the sum of per-candidate
+// maxima.  Group order as in for_each_image: coset p, y-shift b, x-shift a.
+template <typename W, int KIND, typename Hit>
+__device__ __forceinline__ void walk_members(const PlanDev &P, W s, uint32_t cnt, bool gosper, Hit &&hit) {
+    const W full = static_cast<W>(P.full);
+    const bool pf = P.pair_flip != 0;
+    const uint32_t nz = pf ? 2u : 1u;
+    const uint32_t n = P.n_sites, lx = P.lx, ly = P.ly, nc = P.n_cosets, nt = P.n_trans;
+    uint32_t q = 0, a = 0, b = 0, p = 0;
+    // cosets[0] is the identity: the walk of every candidate starts at s
+    W ub = s, v = s;
+    uint32_t lo = 0, hi = 0;   // ring32: the coset image doubled into 64 bits
+    if constexpr (KIND == kOrbitRing32) {
+        const uint64_t uu = static_cast<uint64_t>(s) | (static_cast<uint64_t>(s) << n);
+        lo = static_cast<uint32_t>(uu);
+        hi = static_cast<uint32_t>(uu >> 32);
+    }
+    for (;;) {
+        const W vf = static_cast<W>(v ^ full);
+        bool out = v < s || (pf && vf < s);
+        if (!out && (v == s || (pf && vf == s))) {
+            uint32_t code;
+            if constexpr (KIND == kOrbitRing32) code = (p * n + (a == 0 ? 0u : n - a)) * nz;
+            else code = (p * nt + a + lx * b) * nz;
+            if (v == s && !chi_is_one(P, code)) out = true;
+            if (pf && vf == s && !chi_is_one(P, code + 1)) out = true;
         }
-        return true;
-    });
-    return keep;
+        bool end = false;
+        if constexpr (KIND == kOrbitRing32) {
+            // a counts right rotations here
+            if (++a < n) {
+                v = static_cast<W>(__builtin_amdgcn_alignbit(hi, lo, a)) & full;
+            } else {
+                a = 0;
+                if (++p < nc) {
+                    const W u = apply_coset<W>(P.cosets[p], s, P);
+                    const uint64_t uu = static_cast<uint64_t>(u) | (static_cast<uint64_t>(u) << n);
+                    lo = static_cast<uint32_t>(uu);
+                    hi = static_cast<uint32_t>(uu >> 32);
+                    v = u;
+                } else {
+                    end = true;
+                }
+            }
+        } else {
+            if (++a < lx) {
+                v = xrot<W>(v, P);
+            } else {
+                a = 0;
+                if (++b < ly) {
+                    ub = yrot<W>(ub, P);
+                    v = ub;
+                } else {
+                    b = 0;
+                    if (++p < nc) {
+                        ub = apply_coset<W>(P.cosets[p], s, P);
+                        v = ub;
+                    } else {
+                        end = true;
+                    }
+                }
+            }
+        }
+        if (out || end) {
+            if (!out) hit(q);
+            if (++q >= cnt) break;
+            if (gosper) s = next_combination<W>(s);
+            else s = static_cast<W>(s + 1);
+            a = b = p = 0;
+            ub = v = s;
+            if constexpr (KIND == kOrbitRing32) {
+                const uint64_t uu = static_cast<uint64_t>(s) | (static_cast<uint64_t>(s) << n);
+                lo = static_cast<uint32_t>(uu);
+                hi = static_cast<uint32_t>(uu >> 32);
+            }
+        }
+    }
 }
 
 __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *sh) {
@@ -125,15 +200,30 @@ __global__ void __launch_bounds__(kBlock) k_enum_mark(EnumArgs a) {
     uint64_t mask = 0;
     if (start < a.total) {
         const uint32_t cnt = static_cast<uint32_t>(min<uint64_t>(kCandPerLane, a.total - start));
-        W s = first_candidate<W>(a, start);
-        for (uint32_t q = 0; q < cnt; ++q) {
-            if (is_member<W, KIND>(a.plan, s)) mask |= 1ULL << q;
-            if (q + 1 < cnt) s = next_candidate<W>(a, s);
-        }
+        walk_members<W, KIND>(a.plan, first_candidate<W>(a, start), cnt, a.weight >= 0,
+                              [&](uint32_t q) { mask |= 1ULL << q; });
         a.marks[lane] = mask;
     }
     const uint32_t c = block_sum(static_cast<uint32_t>(__builtin_popcountll(mask)), sh);
     if (threadIdx.x == 0) a.counts[blockIdx.x] = c;
+}
+
+// Count-only pass over candidates [begin, end): each lane takes per_lane
+// consecutive candidates; block totals are added into acc[blockIdx.x], so
+// launches on one stream over consecutive ranges accumulate.
+template <typename W, int KIND>
+__global__ void __launch_bounds__(kBlock) k_enum_count(EnumArgs a, uint64_t begin, uint64_t end, uint32_t per_lane,
+                                                       uint64_t *acc) {
+    __shared__ uint32_t sh[kBlock];
+    const uint64_t lane = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    const uint64_t start = begin + lane * per_lane;
+    uint32_t c = 0;
+    if (start < end) {
+        const uint32_t cnt = static_cast<uint32_t>(min<uint64_t>(per_lane, end - start));
+        walk_members<W, KIND>(a.plan, first_candidate<W>(a, start), cnt, a.weight >= 0, [&](uint32_t) { ++c; });
+    }
+    const uint32_t t = block_sum(c, sh);
+    if (threadIdx.x == 0) acc[blockIdx.x] += t;
 }
 
 template <typename W>
@@ -326,7 +416,8 @@ uint64_t host_binom(uint32_t n, uint32_t k) {
 
 }  // namespace
 
-void build_basis(ls_basis *b, hipStream_t st) {
+// Binomial table and the compiled group in device memory (PlanDev).
+void upload_plan(ls_basis *b) {
     const GroupPlan &gp = b->plan;
     const uint32_t n = gp.n_sites;
     // binomial table
@@ -366,11 +457,70 @@ void build_basis(ls_basis *b, hipStream_t st) {
                                hipMemcpyHostToDevice));
         pd.pair_lut = b->d_pair_lut;
     }
+}
+
+uint64_t candidate_count(const ls_basis *b) {
+    const uint32_t n = b->plan.n_sites;
+    if (b->weight >= 0) return host_binom(n, static_cast<uint32_t>(b->weight));
+    return n == 64 ? ~0ULL : (1ULL << n);
+}
+
+template <typename W>
+uint64_t count_impl(ls_basis *b, uint64_t begin, uint64_t end, hipStream_t st) {
+    // 8 workgroups per CU; a launch covers 2^29 candidates, a few ms of work
+    constexpr uint32_t kBlocks = 2048, kPerLane = 1024;
+    constexpr uint64_t kSpan = static_cast<uint64_t>(kBlocks) * kBlock * kPerLane;
+    uint64_t *acc = nullptr;
+    LS_HIP_CHECK(hipMalloc(&acc, kBlocks * sizeof(uint64_t)));
+    uint64_t total = 0;
+    try {
+        LS_HIP_CHECK(hipMemsetAsync(acc, 0, kBlocks * sizeof(uint64_t), st));
+        EnumArgs a{};
+        a.plan = b->plan_dev;
+        a.binom = b->d_binom;
+        a.total = end;
+        a.n_sites = b->plan.n_sites;
+        a.weight = b->weight;
+        const int kind = orbit_kind<W>(b->plan);
+        for (uint64_t lo = begin; lo < end;) {
+            const uint64_t hi = end - lo > kSpan ? lo + kSpan : end;
+            const uint64_t lanes = (hi - lo + kPerLane - 1) / kPerLane;
+            const uint32_t blocks = static_cast<uint32_t>((lanes + kBlock - 1) / kBlock);
+            if (kind == kOrbitRing32)
+                hipLaunchKernelGGL((k_enum_count<W, kOrbitRing32>), dim3(blocks), dim3(kBlock), 0, st, a, lo, hi,
+                                   kPerLane, acc);
+            else
+                hipLaunchKernelGGL((k_enum_count<W, kOrbitGeneric>), dim3(blocks), dim3(kBlock), 0, st, a, lo, hi,
+                                   kPerLane, acc);
+            LS_HIP_CHECK(hipGetLastError());
+            lo = hi;
+        }
+        std::vector<uint64_t> h(kBlocks);
+        LS_HIP_CHECK(hipMemcpyAsync(h.data(), acc, kBlocks * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        LS_HIP_CHECK(hipStreamSynchronize(st));
+        for (uint64_t v : h) total += v;
+    } catch (...) {
+        hipFree(acc);
+        throw;
+    }
+    hipFree(acc);
+    return total;
+}
+
+uint64_t count_members(ls_basis *b, uint64_t begin, uint64_t end, hipStream_t st) {
+    const uint64_t total = candidate_count(b);
+    end = std::min(end, total);
+    if (begin >= end) return 0;
+    return b->plan.n_sites <= 32 ? count_impl<uint32_t>(b, begin, end, st) : count_impl<uint64_t>(b, begin, end, st);
+}
+
+void build_basis(ls_basis *b, hipStream_t st) {
+    const GroupPlan &gp = b->plan;
+    const uint32_t n = gp.n_sites;
+    upload_plan(b);
 
     // candidates
-    uint64_t total;
-    if (b->weight >= 0) total = host_binom(n, static_cast<uint32_t>(b->weight));
-    else total = 1ULL << n;
+    const uint64_t total = candidate_count(b);
     if (n <= 32) enumerate_impl<uint32_t>(b, st, total, &b->d_reps, &b->dim);
     else enumerate_impl<uint64_t>(b, st, total, &b->d_reps, &b->dim);
     if (b->dim >= 0xFFFFFFFFull) throw Error{LS_EINVAL, "basis dimension must be below 2^32 - 1"};

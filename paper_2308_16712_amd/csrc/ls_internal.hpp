@@ -165,7 +165,13 @@ struct ls_operator {
 namespace ls {
 
 // basis.hip
+void upload_plan(ls_basis *b);
+// C(N, w) with U(1), else 2^N
+uint64_t candidate_count(const ls_basis *b);
 void build_basis(ls_basis *b, hipStream_t stream);
+// Members among the candidates of colex rank [begin, end) (end clamped to
+// the number of candidates); the plan must be uploaded.
+uint64_t count_members(ls_basis *b, uint64_t begin, uint64_t end, hipStream_t stream);
 void launch_state_info(const ls_basis *b, uint64_t n, const uint64_t *states, uint64_t *reps,
                        double *chi, double *norm, hipStream_t stream);
 void launch_index_lookup(const ls_basis *b, uint64_t n, const uint64_t *keys, int64_t *index,

@@ -137,18 +137,19 @@ SMALL_DIM = 1 << 20   # below this a single product cannot fill the GPU
 def _pick(live, policy: str):
     """Solves advanced in this iteration.
 
-    "small-first": every small solve (its product alone cannot fill the
-    GPU, so fusing them costs little) plus the oldest large one; large
-    solves saturate the device on their own, so they advance one at a time
-    in arrival order instead of slowing every small solve down.
+    "small-first": while any small solve is admitted (its product alone
+    cannot fill the GPU), the iteration advances all small solves together
+    in one fused step and nothing else, so a short request is never paced by
+    a long one; otherwise the oldest large solve advances (large solves
+    saturate the device on their own, so they run one at a time, in arrival
+    order).
     "all": every admitted solve in one fused step (plain lock-step)."""
     if policy == "all":
         return list(live)
     small = [lv for lv in live if lv.rec.dim < SMALL_DIM]
-    large = [lv for lv in live if lv.rec.dim >= SMALL_DIM]
-    if large:
-        small.append(min(large, key=lambda lv: (lv.rec.arrival, lv.rec.rid)))
-    return small
+    if small:
+        return small
+    return [min(live, key=lambda lv: (lv.rec.arrival, lv.rec.rid))]
 
 
 def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=None,

@@ -93,6 +93,10 @@ def test_invalid_sector_is_rejected_before_device_work(case):
     assert st == _lib.LS_EINVAL, (case, st, msg)
     assert msg
     assert not h.value
+    # the count-only enumeration runs the same checks first
+    with pytest.raises(_lib.LSError) as e:
+        _lib.sector_count(n, w, perm, flip, chi)
+    assert e.value.status == _lib.LS_EINVAL
 
 
 def test_null_arguments():
@@ -103,6 +107,12 @@ def test_null_arguments():
     assert L.ls_state_info(None, 0, None, None, None, None, None) == _lib.LS_EINVAL
     assert L.ls_index_lookup(None, 0, None, None, None) == _lib.LS_EINVAL
     assert L.ls_lanczos(None, None, None, None, None, None) == _lib.LS_EINVAL
+    m = ctypes.c_uint64()
+    assert L.ls_sector_count(None, 0, 1, ctypes.byref(m), None, None) == _lib.LS_EINVAL
+    g = lattice.ring_group(6, 0)
+    with pytest.raises(_lib.LSError) as e:     # rank_begin > rank_end
+        _lib.sector_count(6, 3, g.perm, g.flip, g.chi, 5, 4)
+    assert e.value.status == _lib.LS_EINVAL
     L.ls_basis_destroy(None)
     L.ls_operator_destroy(None)
 
