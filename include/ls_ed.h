@@ -95,7 +95,14 @@ typedef struct {
  * representative condition; here every weight-w bitstring in increasing
  * order, kept iff it is its orbit's minimum and P does not annihilate it).
  * The handle owns reps (uint64 [dim], strictly increasing), their
- * stabilizer sizes and the search layout used by ls_index_lookup.
+ * stabilizer sizes and the search layout used by ls_index_lookup and the
+ * products (stateToIndex, Section 5.3): a hash index of 16-byte slots
+ * (key, index, stabilizer size; linear probing from slot hash64_01(key),
+ * the paper's Section 5.1 hash; load factor at most 1/2, or 3/4 where the
+ * table would pass 32 GiB), or, where it would pass 64 GiB or the
+ * environment variable LS_ED_SEARCH is "buckets" at build time, a bucket
+ * table over the keys' high bits with binary search in reps.  A group of
+ * one element needs neither (colex rank, or the state itself).
  * Blocks until the build on `stream` has finished.
  * Errors: LS_EINVAL (invalid descriptor: see ls_sector_desc), LS_ENOMEM,
  * LS_EDEVICE, LS_EINTERNAL (a group-compiler self-check failed).          */

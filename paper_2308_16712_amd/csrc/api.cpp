@@ -39,6 +39,7 @@ void free_basis(ls_basis *b) {
     hipFree(b->d_reps);
     hipFree(b->d_stab);
     hipFree(b->d_buckets);
+    hipFree(b->d_table);
     hipFree(b->d_binom);
     hipFree(b->d_cosets);
     hipFree(b->d_chi);

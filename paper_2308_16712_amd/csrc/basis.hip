@@ -18,6 +18,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <string>
 
 #include "orbit.hpp"
 
@@ -281,15 +283,45 @@ __global__ void __launch_bounds__(kBlock) k_stab(PlanDev P, const uint64_t *reps
     stab[i] = static_cast<uint16_t>(cnt);
 }
 
+// buckets[k] = first index whose key reaches bucket k (k = 0 .. nb; entry
+// nb is d): one binary search per bucket, so empty stretches of the key
+// range cost no more than full ones.
 __global__ void __launch_bounds__(kBlock) k_buckets(const uint64_t *reps, uint64_t d, uint64_t kmin, uint32_t shift,
                                                     uint64_t nb, uint32_t *buckets) {
+    const uint64_t k = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+    if (k > nb) return;
+    uint64_t lo = 0, hi = d;
+    if (k < nb) {
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (((reps[mid] - kmin) >> shift) < k) lo = mid + 1; else hi = mid;
+        }
+    } else {
+        lo = d;
+    }
+    buckets[k] = static_cast<uint32_t>(lo);
+}
+
+// Hash index insert: keys are distinct, so each claims the first free slot
+// of its probe sequence with a compare-and-swap; the table has more slots
+// than keys, so every sequence ends.
+__global__ void __launch_bounds__(kBlock) k_hash_insert(const uint64_t *reps, const uint16_t *stab, uint64_t d,
+                                                        HashSlot *table, uint64_t mask) {
     const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i >= d) return;
-    const uint64_t bi = (reps[i] - kmin) >> shift;
-    const int64_t prev = i == 0 ? -1 : static_cast<int64_t>((reps[i - 1] - kmin) >> shift);
-    for (int64_t k = prev + 1; k <= static_cast<int64_t>(bi); ++k) buckets[k] = static_cast<uint32_t>(i);
-    if (i == d - 1)
-        for (uint64_t k = bi + 1; k <= nb; ++k) buckets[k] = static_cast<uint32_t>(d);
+    const uint64_t key = reps[i];
+    uint64_t s = slot_hash(key) & mask;
+    for (;;) {
+        const unsigned long long prev =
+            atomicCAS(reinterpret_cast<unsigned long long *>(&table[s].key), static_cast<unsigned long long>(kEmptyKey),
+                      static_cast<unsigned long long>(key));
+        if (prev == kEmptyKey) {
+            table[s].idx = static_cast<uint32_t>(i);
+            table[s].stab = stab[i];
+            return;
+        }
+        s = (s + 1) & mask;
+    }
 }
 
 template <typename W, int KIND>
@@ -541,7 +573,6 @@ void build_basis(ls_basis *b, hipStream_t st) {
     } else if (gp.n_elements == 1) {
         S.mode = kLookupRank;
     } else {
-        S.mode = kLookupSearch;
         uint64_t kmin = 0, kmax = 0;
         if (b->dim > 0) {
             LS_HIP_CHECK(hipMemcpy(&kmin, b->d_reps, sizeof(uint64_t), hipMemcpyDeviceToHost));
@@ -549,6 +580,30 @@ void build_basis(ls_basis *b, hipStream_t st) {
         }
         S.kmin = kmin;
         S.kmax = kmax;
+        // Hash index: load factor at most 1/2 (at most 3/4 when the table would
+        // pass 32 GiB); above 64 GiB, or when asked for, the bucket search.
+        const char *env = std::getenv("LS_ED_SEARCH");
+        const bool want_buckets = env != nullptr && std::string(env) == "buckets";
+        uint64_t cap = 1024;
+        while (cap < 2 * b->dim) cap <<= 1;
+        if (cap * sizeof(HashSlot) > (32ULL << 30)) {
+            cap = 1024;
+            while (cap * 3 < 4 * b->dim) cap <<= 1;
+        }
+        if (!want_buckets && cap * sizeof(HashSlot) <= (64ULL << 30) && kmax != kEmptyKey) {
+            S.mode = kLookupHash;
+            S.hash_mask = cap - 1;
+            LS_HIP_CHECK(hipMalloc(&b->d_table, cap * sizeof(HashSlot)));
+            LS_HIP_CHECK(hipMemsetAsync(b->d_table, 0xFF, cap * sizeof(HashSlot), st));
+            if (b->dim > 0)
+                hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(b->dim)), dim3(kBlock), 0, st, b->d_reps, b->d_stab,
+                                   b->dim, b->d_table, S.hash_mask);
+            LS_HIP_CHECK(hipGetLastError());
+            S.table = b->d_table;
+            LS_HIP_CHECK(hipStreamSynchronize(st));
+            return;
+        }
+        S.mode = kLookupSearch;
         // about 4 keys per bucket, 2^8 .. 2^22 buckets
         uint32_t bits = 8;
         while (bits < 22 && (1ULL << bits) * 4 < b->dim) ++bits;
@@ -559,11 +614,8 @@ void build_basis(ls_basis *b, hipStream_t st) {
         S.shift = len > bits ? len - bits : 0;
         const uint64_t nb = (range >> S.shift) + 1;   // buckets 0 .. nb-1
         LS_HIP_CHECK(hipMalloc(&b->d_buckets, (nb + 1) * sizeof(uint32_t)));
-        if (b->dim > 0)
-            hipLaunchKernelGGL(k_buckets, dim3(grid_for(b->dim)), dim3(kBlock), 0, st, b->d_reps, b->dim, kmin,
-                               S.shift, nb, b->d_buckets);
-        else
-            LS_HIP_CHECK(hipMemsetAsync(b->d_buckets, 0, (nb + 1) * sizeof(uint32_t), st));
+        hipLaunchKernelGGL(k_buckets, dim3(grid_for(nb + 1)), dim3(kBlock), 0, st, b->d_reps, b->dim, kmin, S.shift,
+                           nb, b->d_buckets);
         LS_HIP_CHECK(hipGetLastError());
         S.buckets = b->d_buckets;
     }

@@ -63,13 +63,18 @@ __global__ void k_reset_counter(uint32_t *c) { *c = 0u; }
 // Bucket table for a candidate number of bits (same rule as the basis build).
 __global__ void k_buckets_tuned(const uint64_t *reps, uint64_t d, uint64_t kmin, uint32_t shift, uint64_t nb,
                                 uint32_t *buckets) {
-    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= d) return;
-    const uint64_t bi = (reps[i] - kmin) >> shift;
-    const int64_t prev = i == 0 ? -1 : static_cast<int64_t>((reps[i - 1] - kmin) >> shift);
-    for (int64_t k = prev + 1; k <= static_cast<int64_t>(bi); ++k) buckets[k] = static_cast<uint32_t>(i);
-    if (i == d - 1)
-        for (uint64_t k = bi + 1; k <= nb; ++k) buckets[k] = static_cast<uint32_t>(d);
+    const uint64_t k = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (k > nb) return;
+    uint64_t lo = 0, hi = d;
+    if (k < nb) {
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (((reps[mid] - kmin) >> shift) < k) lo = mid + 1; else hi = mid;
+        }
+    } else {
+        lo = d;
+    }
+    buckets[k] = static_cast<uint32_t>(lo);
 }
 
 // Lookup sweep used to time a search layout: keys are representatives taken
@@ -253,7 +258,7 @@ SearchDev tuned_search(ls_batch *B, const ls_basis *b, hipStream_t st) {
         *shift = len > nbits ? len - nbits : 0;
         const uint64_t nb = (range >> *shift) + 1;
         LS_HIP_CHECK(hipMalloc(out, (nb + 1) * sizeof(uint32_t)));
-        hipLaunchKernelGGL(k_buckets_tuned, dim3(static_cast<uint32_t>((b->dim + 255) / 256)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_buckets_tuned, dim3(static_cast<uint32_t>((nb + 1 + 255) / 256)), dim3(256), 0, st,
                            b->d_reps, b->dim, S.kmin, *shift, nb, *out);
         LS_HIP_CHECK(hipGetLastError());
     };

@@ -105,7 +105,16 @@ struct PlanDev {
     uint64_t col_ge[8];
 };
 
-enum LookupMode : uint32_t { kLookupSearch = 0, kLookupRank = 1, kLookupIdentity = 2 };
+enum LookupMode : uint32_t { kLookupSearch = 0, kLookupRank = 1, kLookupIdentity = 2, kLookupHash = 3 };
+
+// One slot of the hash index: a representative, its position in the sorted
+// array and its stabilizer size, read with one 16-byte load.
+struct alignas(16) HashSlot {
+    uint64_t key;       // kEmptyKey when free
+    uint32_t idx;
+    uint32_t stab;
+};
+constexpr uint64_t kEmptyKey = ~0ULL;
 
 struct SearchDev {
     uint32_t mode;      // LookupMode
@@ -119,6 +128,8 @@ struct SearchDev {
     const uint64_t *reps;       // device [dim]
     const uint32_t *buckets;    // device [2^bits + 1]
     const uint64_t *binom;      // device [65][65]
+    const HashSlot *table;      // device [hash_mask + 1] (hash mode)
+    uint64_t hash_mask;
 };
 
 }  // namespace ls
@@ -136,6 +147,7 @@ struct ls_basis {
     uint64_t *d_reps = nullptr;
     uint16_t *d_stab = nullptr;
     uint32_t *d_buckets = nullptr;
+    ls::HashSlot *d_table = nullptr;
     uint64_t *d_binom = nullptr;
     ls::CosetRep *d_cosets = nullptr;
     double2 *d_chi = nullptr;

@@ -6,7 +6,7 @@
 //   for each off-diagonal term t acting on r (r & sel == val):
 //       s    = r ^ flip_t,  a = conj(c_t) (-1)^popcount(r & sign_t)
 //       rep  = orbit minimum of s, g* an element reaching it   (getRow)
-//       j    = stateToIndex(rep)                                (lookup)
+//       j    = stateToIndex(rep), with stab_j                   (lookup)
 //       acc += a * chi(g*) * sqrt(stab_j / stab_i) * x_j
 //   y_i = acc                                     (one store, no atomics)
 // This is <r~_i|H|r~_j> written with P|s> = conj(chi(g*)) P|rep> and the
@@ -192,9 +192,10 @@ __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L,
             rep = orbit_min<W, KIND, TRACK>(a.plan, s, code);
         }
         ++t;
-        const int64_t j = lookup_index(a.search, static_cast<uint64_t>(rep));
+        uint32_t st_j = 0;
+        const int64_t j = lookup_index_stab(a.search, static_cast<uint64_t>(rep), a.stab, st_j);
         if (j < 0) continue;
-        const double f = sign_of(r & Tm.sign) * __dsqrt_rn(__ddiv_rn(static_cast<double>(a.stab[j]), st_i));
+        const double f = sign_of(r & Tm.sign) * __dsqrt_rn(__ddiv_rn(static_cast<double>(st_j), st_i));
         if constexpr (!CPLX) {
             double coef = f * Tm.re;
             if constexpr (CHI == kChiReal) coef *= a.plan.chi[code].x;

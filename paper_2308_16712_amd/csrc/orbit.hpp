@@ -286,8 +286,38 @@ __device__ __forceinline__ uint64_t colex_rank(uint64_t s, const uint64_t *tab) 
     return r;
 }
 
-// stateToIndex: bucket of the key's high bits, then binary search.
+// Slot of a key in the hash index: the paper's hash64_01 (the SplitMix64
+// output function, Section 5.1), which there picks a vector entry's owner.
+__host__ __device__ __forceinline__ uint64_t slot_hash(uint64_t x) {
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebULL;
+    return x ^ (x >> 31);
+}
+
+// Hash index: linear probing from the key's slot; the table always has free
+// slots, so every probe sequence ends.  One 16-byte load per probe.
+__device__ __forceinline__ int64_t lookup_hash(const SearchDev &S, uint64_t key, uint32_t &stab) {
+    uint64_t s = slot_hash(key) & S.hash_mask;
+    for (;;) {
+        const uint4 e = *reinterpret_cast<const uint4 *>(S.table + s);
+        const uint64_t k = static_cast<uint64_t>(e.x) | (static_cast<uint64_t>(e.y) << 32);
+        if (k == key) {
+            stab = e.w;
+            return static_cast<int64_t>(e.z);
+        }
+        if (k == kEmptyKey) return -1;
+        s = (s + 1) & S.hash_mask;
+    }
+}
+
+// stateToIndex: hash index, or bucket of the key's high bits then binary
+// search, or the colex rank (U(1) without lattice symmetry).
 __device__ __forceinline__ int64_t lookup_index(const SearchDev &S, uint64_t key) {
+    if (S.mode == kLookupHash) {
+        if (key < S.kmin || key > S.kmax) return -1;
+        uint32_t st;
+        return lookup_hash(S, key, st);
+    }
     if (S.mode == kLookupIdentity)
         return (S.n_sites == 64 || (key >> S.n_sites) == 0) ? static_cast<int64_t>(key) : -1;
     if (S.mode == kLookupRank) {
@@ -304,6 +334,18 @@ __device__ __forceinline__ int64_t lookup_index(const SearchDev &S, uint64_t key
         if (S.reps[mid] < key) lo = mid + 1; else hi = mid;
     }
     return (lo < end && S.reps[lo] == key) ? static_cast<int64_t>(lo) : -1;
+}
+
+// Index and stabilizer size of a key (the hash index holds both in one slot).
+__device__ __forceinline__ int64_t lookup_index_stab(const SearchDev &S, uint64_t key, const uint16_t *stab_arr,
+                                                     uint32_t &stab) {
+    if (S.mode == kLookupHash) {
+        if (key < S.kmin || key > S.kmax) return -1;
+        return lookup_hash(S, key, stab);
+    }
+    const int64_t j = lookup_index(S, key);
+    if (j >= 0) stab = stab_arr[j];
+    return j;
 }
 
 }  // namespace ls

@@ -69,6 +69,19 @@ def sector_dimension(sector) -> int:
     return int(round((tot / g.size).real))
 
 
+def _search_bytes(dim: int) -> int:
+    """Hash index of the basis build: 16-byte slots, a power of two at least
+    twice the dimension (three quarters full above 32 GiB)."""
+    cap = 1024
+    while cap < 2 * dim:
+        cap *= 2
+    if cap * 16 > 32 << 30:
+        cap = 1024
+        while cap * 3 < 4 * dim:
+            cap *= 2
+    return cap * 16
+
+
 def footprint_bytes(sector, max_iter: int) -> int:
     """Device bytes a request holds while admitted: representatives and
     stabilizers, search layout, Krylov space, and the build's mark words."""
@@ -78,7 +91,7 @@ def footprint_bytes(sector, max_iter: int) -> int:
     es = 16 if complex_ else 8
     m = min(max_iter, max(dim, 1))
     cand = comb(sector.n_sites, sector.weight) if sector.weight >= 0 else 2 ** sector.n_sites
-    return dim * 10 + (1 << 24) + (m + 1) * dim * es + 1024 * m * 16 + cand // 8 + (64 << 20)
+    return dim * 10 + _search_bytes(dim) + (m + 1) * dim * es + 1024 * m * 16 + cand // 8 + (64 << 20)
 
 
 @dataclass
@@ -114,6 +127,8 @@ class ServeStats:
     steps: int = 0
     max_active: int = 0
     peak_bytes: int = 0
+    build_s: float = 0.0      # basis + operator + solver set-up
+    step_s: float = 0.0       # Lanczos steps (or whole solves, one at a time)
 
     def summary(self) -> dict:
         lat = np.array([r.latency for r in self.records]) * 1e3
@@ -121,7 +136,7 @@ class ServeStats:
                     throughput_rps=len(self.records) / self.makespan if self.makespan > 0 else 0.0,
                     p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                     mean_ms=float(lat.mean()), steps=self.steps, max_active=self.max_active,
-                    peak_bytes=self.peak_bytes,
+                    peak_bytes=self.peak_bytes, build_s=self.build_s, step_s=self.step_s,
                     converged=int(sum(r.converged for r in self.records)))
 
 
@@ -137,23 +152,27 @@ SMALL_DIM = 1 << 20   # below this a single product cannot fill the GPU
 def _pick(live, policy: str):
     """Solves advanced in this iteration.
 
-    "small-first": while any small solve is admitted (its product alone
+    "sjf" (default): while any small solve is admitted (its product alone
     cannot fill the GPU), the iteration advances all small solves together
-    in one fused step and nothing else, so a short request is never paced by
-    a long one; otherwise the oldest large solve advances (large solves
-    saturate the device on their own, so they run one at a time, in arrival
-    order).
+    in one fused step and nothing else; otherwise the large solve with the
+    smallest dimension advances (ties: oldest first).  Large solves saturate
+    the device on their own, so running them one at a time, shortest first
+    and preemptively (a paused solve keeps its Krylov space resident), loses
+    no throughput and minimises the mean latency.
+    "fifo": as "sjf", but the oldest large solve advances.
     "all": every admitted solve in one fused step (plain lock-step)."""
     if policy == "all":
         return list(live)
     small = [lv for lv in live if lv.rec.dim < SMALL_DIM]
     if small:
         return small
-    return [min(live, key=lambda lv: (lv.rec.arrival, lv.rec.rid))]
+    if policy == "fifo":
+        return [min(live, key=lambda lv: (lv.rec.arrival, lv.rec.rid))]
+    return [min(live, key=lambda lv: (lv.rec.dim, lv.rec.arrival, lv.rec.rid))]
 
 
 def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=None,
-          policy: str = "small-first") -> ServeStats:
+          policy: str = "sjf") -> ServeStats:
     """Continuous batching: admit by footprint, advance the admitted solves
     with fused steps (see _pick), retire converged ones.  Arrivals are
     replayed in real time."""
@@ -178,11 +197,13 @@ def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=N
             if used + need > hbm_budget:
                 continue
             queue.remove(req)
-            rec = Record(req.rid, req.sector.name, 0, req.arrival, admitted=time.perf_counter() - t0)
+            tb = time.perf_counter()
+            rec = Record(req.rid, req.sector.name, 0, req.arrival, admitted=tb - t0)
             b = Basis.from_sector(req.sector)
             op = Operator(b, req.sector.terms)
             s = Solver(op, max_iter, tol=tol, seed=req.sector.seed)
             rec.dim = b.dim
+            stats.build_s += time.perf_counter() - tb
             live.append(_Live(rec, b, op, s, need))
             used += need
             stats.peak_bytes = max(stats.peak_bytes, used)
@@ -191,7 +212,9 @@ def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=N
         if live:
             stats.max_active = max(stats.max_active, len(live))
             step = _pick(live, policy)
+            ts = time.perf_counter()
             Solver.step_all([lv.solver for lv in step])
+            stats.step_s += time.perf_counter() - ts
             stats.steps += 1
             keep = []
             stepped = {id(lv) for lv in step}
@@ -223,10 +246,14 @@ def serve_one_at_a_time(trace, max_iter: int = 150, tol: float = 1e-10) -> Serve
     t0 = time.perf_counter()
     for req in pending:
         _wait_until(t0, req.arrival)
-        rec = Record(req.rid, req.sector.name, 0, req.arrival, admitted=time.perf_counter() - t0)
+        tb = time.perf_counter()
+        rec = Record(req.rid, req.sector.name, 0, req.arrival, admitted=tb - t0)
         b = Basis.from_sector(req.sector)
         op = Operator(b, req.sector.terms)
+        ts = time.perf_counter()
+        stats.build_s += ts - tb
         r = op.lanczos(max_iter, tol=tol, seed=req.sector.seed)
+        stats.step_s += time.perf_counter() - ts
         rec.dim = b.dim
         rec.done = time.perf_counter() - t0
         rec.e0, rec.iters, rec.converged = r["e0"], r["iters"], r["converged"]

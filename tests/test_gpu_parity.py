@@ -206,6 +206,30 @@ def test_lanczos_parity(sec):
     assert abs(got2["e0"] - want["e0"]) <= LANCZOS_TOL * max(1.0, abs(want["e0"]))
 
 
+@pytest.mark.parametrize("sec", [s for s in SMALL if s.name in
+                                 ("ringD20_0pp", "torus4x6_full", "ring40_w3_D", "torus6x6_w4_k10",
+                                  "ringT10_noU1_k1", "scrambled4x4_full", "ringTZ18_k5")],
+                         ids=lambda s: s.name)
+def test_bucket_search_layout(sec, monkeypatch):
+    """The bucket-table search layout (the fallback of the hash index) gives
+    the oracle's indices and the same products bit for bit."""
+    P, reps, stab, b, op = _built(sec)
+    monkeypatch.setenv("LS_ED_SEARCH", "buckets")
+    b2 = ls.ls_basis_build(sec)
+    monkeypatch.delenv("LS_ED_SEARCH")
+    try:
+        op2 = ls.ls_operator_create(b2, sec.terms)
+        n = sec.n_sites
+        extra = rng.counter_u64(8, np.arange(2000, dtype=np.uint64)) & np.uint64((1 << n) - 1)
+        keys = np.concatenate([reps, extra]).astype(np.uint64)
+        assert np.array_equal(b2.index_lookup(_dev_u64(keys)).cpu().numpy(), oracle.index_lookup(reps, keys))
+        x = torch.from_numpy(rng.vector(31, len(reps), 2, complex_=op.is_complex)).cuda()
+        assert torch.equal(op.matvec(x), op2.matvec(x))
+        op2.close()
+    finally:
+        b2.close()
+
+
 def test_lanczos_converges_cfg1():
     sec = SMALL[0]
     P, reps, stab, b, op = _built(sec)

@@ -35,3 +35,19 @@ def test_records_summary():
     s = st.summary()
     assert s["requests"] == 10 and abs(s["throughput_rps"] - 100.0) < 1e-9
     assert 50.0 <= s["p50_ms"] <= 60.0 and s["p99_ms"] <= 100.0
+
+
+def _live(rid, dim, arrival):
+    return serve._Live(serve.Record(rid, f"r{rid}", dim, arrival), None, None, None, 0)
+
+
+def test_step_policy():
+    big_old, big_small, mid = _live(0, 60_000_000, 0.0), _live(1, 4_000_000, 0.5), _live(2, 15_000_000, 0.2)
+    small_a, small_b = _live(3, 10_000, 0.9), _live(4, 100_000, 1.0)
+    # small solves go first, all together
+    assert serve._pick([big_old, small_a, mid, small_b], "sjf") == [small_a, small_b]
+    assert serve._pick([big_old, small_a, mid, small_b], "fifo") == [small_a, small_b]
+    # then one large solve: the smallest (sjf) or the oldest (fifo)
+    assert serve._pick([big_old, mid, big_small], "sjf") == [big_small]
+    assert serve._pick([big_old, mid, big_small], "fifo") == [big_old]
+    assert serve._pick([big_old, mid], "all") == [big_old, mid]
