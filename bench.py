@@ -168,7 +168,9 @@ def serving(count: int, rate: float, budget_gb: float, max_iter: int, tol: float
     s, b = served.summary(), alone.summary()
     work = sum(r.dim * r.iters for r in served.records)
     return {"requests": count, "arrival_rate_per_s": rate, "tol": tol, "max_iter": max_iter,
-            "hbm_budget_gb": budget_gb, "dims": sorted({r.dim for r in served.records}),
+            "hbm_budget_gb": budget_gb, "policy": "sjf (small solves fused first, then shortest large; "
+                                                  "builds overlapped with steps)",
+            "dims": sorted({r.dim for r in served.records}),
             "served": s, "one_at_a_time": b,
             "speedup_throughput": s["throughput_rps"] / b["throughput_rps"],
             "p50_ratio": b["p50_ms"] / s["p50_ms"], "p99_ratio": b["p99_ms"] / s["p99_ms"],

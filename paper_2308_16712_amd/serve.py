@@ -175,65 +175,95 @@ def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=N
           policy: str = "sjf") -> ServeStats:
     """Continuous batching: admit by footprint, advance the admitted solves
     with fused steps (see _pick), retire converged ones.  Arrivals are
-    replayed in real time."""
+    replayed in real time.
+
+    Bases and operators of admitted requests are built by a worker thread on
+    a stream of their own while the loop keeps stepping the live solves on
+    another (the library releases the interpreter lock in every call); a
+    request joins the steps once its build has finished."""
     import torch
+    from concurrent.futures import FIRST_COMPLETED, ThreadPoolExecutor, wait
+
     pending = sorted(trace, key=lambda r: r.arrival)
     queue: List = []
     live: List[_Live] = []
+    building = []           # (request, bytes, record, future)
     used = 0
     stats = ServeStats()
+    step_stream = torch.cuda.Stream()
+    build_stream = torch.cuda.Stream()
+
+    def build(req):
+        t = time.perf_counter()
+        b = Basis.from_sector(req.sector, build_stream)
+        op = Operator(b, req.sector.terms)
+        return b, op, time.perf_counter() - t
+
+    pool = ThreadPoolExecutor(max_workers=1)
     t0 = time.perf_counter()
     i = 0
-    while i < len(pending) or queue or live:
-        now = time.perf_counter() - t0
-        while i < len(pending) and pending[i].arrival <= now:
-            queue.append(pending[i])
-            i += 1
-        # first-fit admission in arrival order
-        for req in list(queue):
-            need = footprint_bytes(req.sector, max_iter)
-            if need > hbm_budget:
-                raise ValueError(f"request {req.rid} needs {need} bytes, more than the whole budget")
-            if used + need > hbm_budget:
-                continue
-            queue.remove(req)
-            tb = time.perf_counter()
-            rec = Record(req.rid, req.sector.name, 0, req.arrival, admitted=tb - t0)
-            b = Basis.from_sector(req.sector)
-            op = Operator(b, req.sector.terms)
-            s = Solver(op, max_iter, tol=tol, seed=req.sector.seed)
-            rec.dim = b.dim
-            stats.build_s += time.perf_counter() - tb
-            live.append(_Live(rec, b, op, s, need))
-            used += need
-            stats.peak_bytes = max(stats.peak_bytes, used)
-            if log:
-                log(f"[serve] t={rec.admitted:.3f}s admit {req.rid} {req.sector.name} dim={b.dim} active={len(live)}")
-        if live:
-            stats.max_active = max(stats.max_active, len(live))
-            step = _pick(live, policy)
-            ts = time.perf_counter()
-            Solver.step_all([lv.solver for lv in step])
-            stats.step_s += time.perf_counter() - ts
-            stats.steps += 1
-            keep = []
-            stepped = {id(lv) for lv in step}
-            for lv in live:
-                r = lv.solver.result() if id(lv) in stepped else {"done": False}
-                if r["done"]:
-                    lv.rec.done = time.perf_counter() - t0
-                    lv.rec.e0, lv.rec.iters, lv.rec.converged = r["e0"], r["iters"], r["converged"]
-                    stats.records.append(lv.rec)
-                    lv.solver.close()
-                    lv.op.close()
-                    lv.basis.close()
-                    used -= lv.bytes
-                else:
-                    keep.append(lv)
-            live = keep
-        elif i < len(pending) and not queue:
-            _wait_until(t0, pending[i].arrival)
-        torch.cuda.synchronize()
+    try:
+        with torch.cuda.stream(step_stream):
+            while i < len(pending) or queue or live or building:
+                now = time.perf_counter() - t0
+                while i < len(pending) and pending[i].arrival <= now:
+                    queue.append(pending[i])
+                    i += 1
+                # first-fit admission in arrival order; the build starts now
+                for req in list(queue):
+                    need = footprint_bytes(req.sector, max_iter)
+                    if need > hbm_budget:
+                        raise ValueError(f"request {req.rid} needs {need} bytes, more than the whole budget")
+                    if used + need > hbm_budget:
+                        continue
+                    queue.remove(req)
+                    rec = Record(req.rid, req.sector.name, 0, req.arrival, admitted=time.perf_counter() - t0)
+                    building.append((req, need, rec, pool.submit(build, req)))
+                    used += need
+                    stats.peak_bytes = max(stats.peak_bytes, used)
+                # finished builds join the live set
+                for item in list(building):
+                    req, need, rec, fut = item
+                    if not fut.done():
+                        continue
+                    building.remove(item)
+                    b, op, dt = fut.result()
+                    stats.build_s += dt
+                    s = Solver(op, max_iter, tol=tol, seed=req.sector.seed)
+                    rec.dim = b.dim
+                    live.append(_Live(rec, b, op, s, need))
+                    if log:
+                        log(f"[serve] t={time.perf_counter() - t0:.3f}s start {req.rid} {req.sector.name} "
+                            f"dim={b.dim} active={len(live)}")
+                if live:
+                    stats.max_active = max(stats.max_active, len(live))
+                    step = _pick(live, policy)
+                    ts = time.perf_counter()
+                    Solver.step_all([lv.solver for lv in step])
+                    stats.step_s += time.perf_counter() - ts
+                    stats.steps += 1
+                    keep = []
+                    stepped = {id(lv) for lv in step}
+                    for lv in live:
+                        r = lv.solver.result() if id(lv) in stepped else {"done": False}
+                        if r["done"]:
+                            lv.rec.done = time.perf_counter() - t0
+                            lv.rec.e0, lv.rec.iters, lv.rec.converged = r["e0"], r["iters"], r["converged"]
+                            stats.records.append(lv.rec)
+                            lv.solver.close()
+                            lv.op.close()
+                            lv.basis.close()
+                            used -= lv.bytes
+                        else:
+                            keep.append(lv)
+                    live = keep
+                elif building:
+                    wait([item[3] for item in building], return_when=FIRST_COMPLETED)
+                elif i < len(pending) and not queue:
+                    _wait_until(t0, pending[i].arrival)
+    finally:
+        pool.shutdown(wait=True)
+    step_stream.synchronize()
     stats.makespan = time.perf_counter() - t0
     stats.records.sort(key=lambda r: r.rid)
     return stats
