@@ -280,6 +280,12 @@ def main():
             "kernel": "k_matvec", "kernel_ms": kernel_ms,
             "ops_model": f"{sector.group.size} group images x {words} word-min per off-diagonal element"}
     alg_bytes = rows * (8 + 8 + 8 + 2) + n_off * (8 + 8 + 2)
+    if roof["traffic"] is not None:
+        # the HBM-side view: counter bytes per launch over the live kernel time
+        t_bps = roof["traffic"] / (kernel_ms * 1e-3)
+        roof["traffic_gbps"] = t_bps / 1e9
+        roof["traffic_frac_of_hbm_peak"] = t_bps / PEAK_HBM
+        roof["gather_efficiency"] = alg_bytes / roof["traffic"]
     out = {
         "metric": "H matrix elements/s", "value": value, "unit": "elements/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
