@@ -2,12 +2,16 @@
 
 Every source is compiled for gfx950 only; packed FP32 instructions are
 disabled (``-packed-fp32-ops``); no fast-math, so FP64 division and square
-root round correctly.
+root round correctly; no floating-point contraction (``-ffp-contract=off``):
+a multiply-add is fused only where the source writes fma(), so two kernels
+built from the same row code (the single and the persistent batched launch)
+round identically whatever their register budgets and block layouts.
 """
 from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import subprocess
 import sys
 
@@ -22,7 +26,19 @@ HEADERS = ["ls_internal.hpp", "orbit.hpp", "matvec_impl.hpp", "dispatch.hpp"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
-          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function"]
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=off",
+          "-Wall", "-Wno-unused-function"]
+
+
+def _scratch_kernels(remarks: str):
+    """Kernels whose resource-usage remark reports scratch (register spills
+    to memory), from hipcc's -Rpass-analysis=kernel-resource-usage output."""
+    out = []
+    for block in re.split(r"remark: Function Name: ", remarks)[1:]:
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", block)
+        if m and int(m.group(1)) > 0:
+            out.append((block.split()[0], int(m.group(1))))
+    return out
 
 
 def _compile(src: str) -> str:
@@ -30,9 +46,15 @@ def _compile(src: str) -> str:
     cmd = ["hipcc", "-c", os.path.join(CSRC, src), "-o", out] + COMMON
     if src.endswith(".hip"):
         cmd[1:1] = ["-x", "hip"]
+        cmd.append("-Rpass-analysis=kernel-resource-usage")
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+    # every kernel must run from registers: a spill costs a memory round trip
+    # per access inside the element loop
+    spills = _scratch_kernels(r.stderr)
+    if spills:
+        raise RuntimeError(f"{src}: kernels spill to scratch: {spills}")
     return out
 
 

@@ -306,11 +306,11 @@ __global__ void __launch_bounds__(kBlock) k_buckets(const uint64_t *reps, uint64
 // of its probe sequence with a compare-and-swap; the table has more slots
 // than keys, so every sequence ends.
 __global__ void __launch_bounds__(kBlock) k_hash_insert(const uint64_t *reps, const uint16_t *stab, uint64_t d,
-                                                        HashSlot *table, uint64_t mask) {
+                                                        HashSlot *table, uint64_t mask, uint32_t shift) {
     const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
     if (i >= d) return;
     const uint64_t key = reps[i];
-    uint64_t s = slot_hash(key) & mask;
+    uint64_t s = slot_of(key, shift);
     for (;;) {
         const unsigned long long prev =
             atomicCAS(reinterpret_cast<unsigned long long *>(&table[s].key), static_cast<unsigned long long>(kEmptyKey),
@@ -593,11 +593,13 @@ void build_basis(ls_basis *b, hipStream_t st) {
         if (!want_buckets && cap * sizeof(HashSlot) <= (64ULL << 30) && kmax != kEmptyKey) {
             S.mode = kLookupHash;
             S.hash_mask = cap - 1;
+            S.hash_shift = 64;
+            for (uint64_t c = cap; c > 1; c >>= 1) --S.hash_shift;
             LS_HIP_CHECK(hipMalloc(&b->d_table, cap * sizeof(HashSlot)));
             LS_HIP_CHECK(hipMemsetAsync(b->d_table, 0xFF, cap * sizeof(HashSlot), st));
             if (b->dim > 0)
                 hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(b->dim)), dim3(kBlock), 0, st, b->d_reps, b->d_stab,
-                                   b->dim, b->d_table, S.hash_mask);
+                                   b->dim, b->d_table, S.hash_mask, S.hash_shift);
             LS_HIP_CHECK(hipGetLastError());
             S.table = b->d_table;
             LS_HIP_CHECK(hipStreamSynchronize(st));

@@ -77,6 +77,16 @@ __global__ void k_buckets_tuned(const uint64_t *reps, uint64_t d, uint64_t kmin,
     buckets[k] = static_cast<uint32_t>(lo);
 }
 
+// Right-hand sides per job of the persistent kernel.  Its tile loop holds
+// more live state than the single launch, and with 1024-thread workgroups
+// (128 VGPRs at most) the wider torus variants would spill to scratch; the
+// cap keeps every instantiated variant in registers.  Columns are computed
+// independently, so the cap changes no result bit.
+constexpr int nr_cap(bool word64, int kind, int chi) {
+    return kind != kOrbitTorus ? 8 : (word64 && chi == kChiComplex) ? 1 : 2;
+}
+int batch_nr_cap(const Variant &v) { return nr_cap(v.word64 != 0, v.kind, v.chi); }
+
 // Lookup sweep used to time a search layout: keys are representatives taken
 // in a scattered order; the sum of indices defeats dead-code elimination.
 __global__ void k_lookup_sweep(SearchDev S, uint64_t n, uint64_t magic, uint64_t *sink) {
@@ -110,11 +120,15 @@ struct BatchLaunch {
     hipStream_t st;
     template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
     void run() {
-        constexpr int BLOCK = block_of(KIND);
-        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, g->d_counter);
-        hipLaunchKernelGGL((k_matvec_batch<W, KIND, CHI, CPLX, NR, LX, LY, NZ>), dim3(g->grid), dim3(BLOCK), g->lds,
-                           st, g->d_jobs, g->d_tiles, g->n_tiles, g->d_counter, g->rpl);
-        (void)BLOCK;
+        // variants above the cap are never grouped (batch_nr_cap) and never built
+        if constexpr (NR > nr_cap(sizeof(W) == 8, KIND, CHI)) {
+            throw Error{LS_EINTERNAL, "batched job wider than its variant's cap"};
+        } else {
+            constexpr int BLOCK = block_of(KIND);
+            hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, g->d_counter);
+            hipLaunchKernelGGL((k_matvec_batch<W, KIND, CHI, CPLX, NR, LX, LY, NZ>), dim3(g->grid), dim3(BLOCK),
+                               g->lds, st, g->d_jobs, g->d_tiles, g->n_tiles, g->d_counter, g->rpl);
+        }
     }
 };
 
@@ -371,7 +385,7 @@ static void batch_prepare(ls_batch *B, hipStream_t st) {
         const Variant v = variant_of(op);
         uint32_t col = 0;
         while (col < B->nrhs[i]) {
-            const int nr = nr_chunk(B->nrhs[i] - col);
+            const int nr = std::min(nr_chunk(B->nrhs[i] - col), batch_nr_cap(v));
             Group *g = nullptr;
             for (auto &gg : B->groups)
                 if (gg.v == v && gg.nr == nr) g = &gg;

@@ -122,7 +122,7 @@ struct SearchDev {
     uint32_t shift;     // bucket = (key - kmin) >> shift
     int32_t weight;     // for rank / identity validation
     uint32_t n_sites;
-    uint32_t pad_;
+    uint32_t hash_shift;        // slot = (key * golden) >> hash_shift (hash mode)
     uint64_t dim;
     uint64_t kmin, kmax;
     const uint64_t *reps;       // device [dim]

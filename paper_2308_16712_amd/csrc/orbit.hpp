@@ -286,18 +286,16 @@ __device__ __forceinline__ uint64_t colex_rank(uint64_t s, const uint64_t *tab) 
     return r;
 }
 
-// Slot of a key in the hash index: the paper's hash64_01 (the SplitMix64
-// output function, Section 5.1), which there picks a vector entry's owner.
-__host__ __device__ __forceinline__ uint64_t slot_hash(uint64_t x) {
-    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
-    x = (x ^ (x >> 27)) * 0x94d049bb133111ebULL;
-    return x ^ (x >> 31);
+// Home slot of a key in a hash index of 2^(64 - shift) slots: Fibonacci
+// hashing (the top bits of key * 2^64/phi), so every key bit moves the slot.
+__host__ __device__ __forceinline__ uint64_t slot_of(uint64_t key, uint32_t shift) {
+    return (key * 0x9E3779B97F4A7C15ULL) >> shift;
 }
 
 // Hash index: linear probing from the key's slot; the table always has free
 // slots, so every probe sequence ends.  One 16-byte load per probe.
 __device__ __forceinline__ int64_t lookup_hash(const SearchDev &S, uint64_t key, uint32_t &stab) {
-    uint64_t s = slot_hash(key) & S.hash_mask;
+    uint64_t s = slot_of(key, S.hash_shift);
     for (;;) {
         const uint4 e = *reinterpret_cast<const uint4 *>(S.table + s);
         const uint64_t k = static_cast<uint64_t>(e.x) | (static_cast<uint64_t>(e.y) << 32);
