@@ -179,6 +179,60 @@ def serving(count: int, rate: float, budget_gb: float, max_iter: int, tol: float
                                  "latency includes queueing"}
 
 
+def table2_dims():
+    """Closed-chain sector dimensions printed in the paper (Section 6, Table 2)."""
+    out = {}
+    for line in open(os.path.join(ROOT, "tests", "golden", "table2_chain_dims.txt")):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            n, d = line.split()
+            out[int(n)] = int(d)
+    return out
+
+
+def enumeration(count_ns, build_n):
+    """Count-only enumeration (ls_sector_count) of the fully symmetric
+    closed-chain sectors of Table 2, split into rank slices that print
+    progress, and one stored basis build; candidates filtered per second."""
+    from math import comb
+    import torch
+    import paper_2308_16712_amd as ls
+    from workloads import configs
+
+    want = table2_dims()
+    out = {}
+    for n in count_ns:
+        sec = configs.ring_symmetric(n, 0, 1, 1)
+        total = comb(n, n // 2)
+        slices = max(1, min(64, total >> 40))
+        got = 0
+        t0 = time.perf_counter()
+        for k in range(slices):
+            m, _ = ls.ls_sector_count(sec, total * k // slices, total * (k + 1) // slices)
+            got += m
+            if slices > 1:
+                print(f"[bench] N={n} slice {k + 1}/{slices} t={time.perf_counter() - t0:.1f}s", file=sys.stderr,
+                      flush=True)
+        dt = time.perf_counter() - t0
+        out[f"count_N{n}"] = {"dim": got, "table2": want.get(n), "matches_table2": got == want.get(n),
+                              "candidates": total, "s": dt, "candidates_per_s": total / dt}
+        print(f"[bench] count N={n}: {got} in {dt:.2f}s", file=sys.stderr, flush=True)
+    if build_n:
+        sec = configs.ring_symmetric(build_n, 0, 1, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b = ls.ls_basis_build(sec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"build_N{build_n}"] = {"dim": b.dim, "table2": want.get(build_n),
+                                    "matches_table2": b.dim == want.get(build_n), "s": dt,
+                                    "candidates_per_s": comb(build_n, build_n // 2) / dt,
+                                    "reps_gb": b.dim * 8 / 1e9}
+        b.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 # the sources that make up the product kernel: a counter record taken on
 # other sources no longer describes it
 TRAFFIC_SOURCES = ("matvec.hip", "matvec_impl.hpp", "dispatch.hpp", "orbit.hpp")
@@ -216,6 +270,9 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--serve-max-iter", type=int, default=150)
+    ap.add_argument("--no-enumeration", action="store_true", help="skip the Table 2 enumeration leg")
+    ap.add_argument("--enum-counts", default="40,42", help="chain sizes counted without storage")
+    ap.add_argument("--enum-build", type=int, default=40, help="chain size built and stored (0: none)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run only a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -302,6 +359,10 @@ def main():
         torch.cuda.empty_cache()
         out["batched"] = batched_vs_plain(args.batched_count, args.batched_nrhs)
         torch.cuda.empty_cache()
+    if not args.no_enumeration:
+        print("[bench] enumeration", file=sys.stderr, flush=True)
+        ns = [int(v) for v in args.enum_counts.split(",") if v]
+        out["enumeration"] = enumeration(ns, args.enum_build)
     if not args.no_serving:
         print("[bench] serving", file=sys.stderr, flush=True)
         out["serving"] = serving(args.serve_count, args.serve_rate, args.serve_budget_gb, args.serve_max_iter,
