@@ -179,6 +179,44 @@ def serving(count: int, rate: float, budget_gb: float, max_iter: int, tol: float
                                  "latency includes queueing"}
 
 
+def stored_product(basis, sector, x, y, fly_ms: float, elements: int, steps: int):
+    """The same product from stored elements (ls_operator_store): store time
+    and size, product time on the launch stream, and bit-identity with the
+    on-the-fly result."""
+    import torch
+    import paper_2308_16712_amd as ls
+
+    op = ls.ls_operator_create(basis, sector.terms)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nbytes = op.store()
+    torch.cuda.synchronize()
+    store_s = time.perf_counter() - t0
+    y2 = torch.empty_like(y)
+    ls.ls_matvec(op, x, y2)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        ls.ls_matvec(op, x, y2)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    fly = ls.ls_operator_create(basis, sector.terms)
+    ls.ls_matvec(fly, x, y)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(y, y2))
+    op.close()
+    fly.close()
+    del y2
+    torch.cuda.empty_cache()
+    return {"bytes": nbytes, "store_s": store_s, "ms_per_product": ms, "elements_per_s": elements / (ms * 1e-3),
+            "speedup_vs_on_the_fly": fly_ms / ms, "identical_to_on_the_fly": same,
+            "layout": "sliced ELLPACK, 64-row slices, uint32 column + value per slot"}
+
+
 def table2_dims():
     """Closed-chain sector dimensions printed in the paper (Section 6, Table 2)."""
     out = {}
@@ -271,6 +309,7 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--serve-max-iter", type=int, default=150)
     ap.add_argument("--no-enumeration", action="store_true", help="skip the Table 2 enumeration leg")
+    ap.add_argument("--no-stored", action="store_true", help="skip the stored-elements product")
     ap.add_argument("--enum-counts", default="40,42", help="chain sizes counted without storage")
     ap.add_argument("--enum-build", type=int, default=40, help="chain size built and stored (0: none)")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -353,6 +392,9 @@ def main():
         "hbm_algorithmic_gbps": alg_bytes / (kernel_ms * 1e-3) / 1e9,
         "basis_build_s": build_s,
     }
+    if not args.no_stored:
+        print("[bench] stored elements", file=sys.stderr, flush=True)
+        out["stored"] = stored_product(basis, sector, x, y, kernel_ms, elements, args.steps)
     if not args.no_batched:
         print("[bench] batched vs plain", file=sys.stderr, flush=True)
         del x, y, op, basis

@@ -179,6 +179,25 @@ void ls_operator_destroy(ls_operator *op);
  * complex coefficients).                                                   */
 ls_status ls_operator_info(const ls_operator *op, int *is_complex, uint64_t *dim);
 
+/* Stores the operator's matrix elements in device memory, so that later
+ * products read them instead of regenerating them.  The paper generates
+ * elements on the fly because a stored H does not fit its machines
+ * (Section 2.2); where it fits one GPU, a stored product is bound by memory
+ * traffic rather than by the orbit searches.  Layout: sliced ELLPACK over
+ * slices of 64 consecutive rows (uint32 column and double / complex128 value
+ * per slot, plus each row's diagonal sum).
+ *   max_bytes  refuse (LS_ENOMEM, operator unchanged) if the stored form
+ *              would need more device memory than this.
+ *   bytes      out (may be NULL): device bytes held by the stored form.
+ * Afterwards ls_matvec, ls_lanczos and single-solve ls_solver_step use the
+ * stored elements; batched and fused products keep generating them.  Both
+ * forms run the same row arithmetic in the same order and give identical
+ * results bit for bit.  Storing again is a no-op.  This call changes the
+ * operator: make it before the handle is shared by concurrent calls.
+ * Blocks until the store on `stream` has finished; costs about one product.
+ * Errors: LS_EINVAL (NULL operator), LS_ENOMEM, LS_EDEVICE.                 */
+ls_status ls_operator_store(ls_operator *op, uint64_t max_bytes, void *stream, uint64_t *bytes);
+
 /* Number of off-diagonal element applications of one product: the sum over
  * rows of the off-diagonal terms acting on the row's representative.  A
  * product applies this many off-diagonal elements plus one diagonal element

@@ -57,6 +57,16 @@ def ls_operator_create(basis: Basis, term_table) -> Operator:
     return Operator(basis, term_table)
 
 
+def ls_operator_store(op: Operator, max_bytes: int = 2**64 - 1, stream=None) -> int:
+    """Keep the operator's matrix elements in device memory; later products
+    read them (bit-identical results).  Returns the bytes held."""
+    return op.store(max_bytes, stream)
+
+
+def ls_operator_count(op: Operator, stream=None) -> int:
+    return op.count_elements(stream)
+
+
 def ls_matvec(op: Operator, x, y=None, stream=None):
     return op.matvec(x, y, stream)
 

@@ -21,7 +21,7 @@ _NAMES = {0: "LS_OK", 1: "LS_WNOTCONV", -1: "LS_EINVAL", -2: "LS_ENOMEM", -3: "L
 
 EXPORTS = ["ls_sector_check", "ls_sector_count", "ls_basis_build", "ls_basis_info", "ls_basis_copy", "ls_basis_destroy", "ls_state_info",
            "ls_index_lookup", "ls_operator_create", "ls_operator_destroy", "ls_operator_info",
-           "ls_operator_count", "ls_matvec",
+           "ls_operator_count", "ls_operator_store", "ls_matvec",
            "ls_batch_create", "ls_batch_matvec", "ls_batch_info", "ls_batch_set_graph", "ls_batch_destroy",
            "ls_lanczos", "ls_solver_footprint", "ls_solver_create", "ls_solver_step", "ls_solver_result",
            "ls_solver_destroy", "ls_last_error", "ls_version"]
@@ -67,6 +67,7 @@ def load(path: str = LIB_PATH):
         "ls_sector_check": ([P, P, P, P, P], i32),
         "ls_sector_count": ([P, u64, u64, P, P, P], i32),
         "ls_basis_build": ([P, P, P], i32),
+        "ls_operator_store": ([P, u64, P, P], i32),
         "ls_basis_info": ([P, P, P, P], i32),
         "ls_basis_copy": ([P, P, P, P], i32),
         "ls_basis_destroy": ([P], None),
@@ -258,6 +259,13 @@ class Operator:
         n = ctypes.c_uint64()
         _check(load().ls_operator_count(self._h, ctypes.byref(n), _stream_ptr(stream)))
         return int(n.value)
+
+    def store(self, max_bytes: int = 2**64 - 1, stream=None) -> int:
+        """Keep the matrix elements in device memory for later products
+        (ls_operator_store); returns the bytes held."""
+        b = ctypes.c_uint64()
+        _check(load().ls_operator_store(self._h, int(max_bytes), _stream_ptr(stream), ctypes.byref(b)))
+        return int(b.value)
 
     def matvec(self, x, y=None, stream=None):
         """y = H x for x of shape [dim] or [dim][nrhs] (float64 / complex128)."""

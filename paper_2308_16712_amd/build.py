@@ -21,7 +21,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libls_ed.so")
-SOURCES = ["api.cpp", "group.cpp", "terms.cpp", "basis.hip", "matvec.hip", "batch.hip", "lanczos.hip"]
+SOURCES = ["api.cpp", "group.cpp", "terms.cpp", "basis.hip", "matvec.hip", "batch.hip", "lanczos.hip", "stored.hip"]
 HEADERS = ["ls_internal.hpp", "orbit.hpp", "matvec_impl.hpp", "dispatch.hpp"]
 
 ARCH = "gfx950"

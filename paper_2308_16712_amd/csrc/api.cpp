@@ -194,7 +194,21 @@ void ls_operator_destroy(ls_operator *op) {
     hipDeviceSynchronize();
     hipFree(op->d_terms);
     hipFree(op->d_cflip);
+    hipFree(op->d_st_off);
+    hipFree(op->d_st_width);
+    hipFree(op->d_st_cols);
+    hipFree(op->d_st_vals);
+    hipFree(op->d_st_diag);
     delete op;
+}
+
+ls_status ls_operator_store(ls_operator *op, uint64_t max_bytes, void *stream, uint64_t *bytes) {
+    return guarded([&] {
+        LS_REQUIRE(op != nullptr, "operator must not be NULL");
+        const uint64_t b = ls::store_elements(op, max_bytes, as_stream(stream));
+        if (bytes) *bytes = b;
+        return LS_OK;
+    });
 }
 
 ls_status ls_operator_info(const ls_operator *op, int *is_complex, uint64_t *dim) {

@@ -31,10 +31,15 @@ struct Tile {
     uint64_t row0;
 };
 
+// Workgroup size of the persistent kernel: the complex torus search holds
+// more live state than 128 VGPRs (the most a 1024-thread workgroup allows)
+// around the tile loop, so it runs in 512-thread workgroups.
+constexpr int batch_block(int kind, bool cplx) { return (kind == kOrbitTorus && cplx) ? 512 : block_of(kind); }
+
 template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
-__global__ void __launch_bounds__(block_of(KIND))
+__global__ void __launch_bounds__(batch_block(KIND, CPLX))
     k_matvec_batch(const MatvecJob *jobs, const Tile *tiles, uint32_t n_tiles, uint32_t *counter, uint32_t rpl) {
-    constexpr int BLOCK = block_of(KIND);
+    constexpr int BLOCK = batch_block(KIND, CPLX);
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_tile;
     uint32_t cur = 0xFFFFFFFFu;
@@ -124,7 +129,7 @@ struct BatchLaunch {
         if constexpr (NR > nr_cap(sizeof(W) == 8, KIND, CHI)) {
             throw Error{LS_EINTERNAL, "batched job wider than its variant's cap"};
         } else {
-            constexpr int BLOCK = block_of(KIND);
+            constexpr int BLOCK = batch_block(KIND, CPLX);
             hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, g->d_counter);
             hipLaunchKernelGGL((k_matvec_batch<W, KIND, CHI, CPLX, NR, LX, LY, NZ>), dim3(g->grid), dim3(BLOCK),
                                g->lds, st, g->d_jobs, g->d_tiles, g->n_tiles, g->d_counter, g->rpl);
@@ -132,7 +137,7 @@ struct BatchLaunch {
     }
 };
 
-int block_for(const Variant &v) { return block_of(v.kind); }
+int block_for(const Variant &v) { return batch_block(v.kind, v.cplx); }
 
 // Tiles for the current rows-per-lane, ordered by decreasing job cost.
 void build_tiles(Group &g, hipStream_t st) {

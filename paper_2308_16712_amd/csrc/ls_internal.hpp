@@ -172,6 +172,14 @@ struct ls_operator {
     // applied to every off-diagonal flip mask, [n_off][kTorusCosetSlots]
     std::vector<uint64_t> host_cflip;
     uint64_t *d_cflip = nullptr;
+    // stored elements (ls_operator_store), sliced ELLPACK over 64-row slices
+    bool stored = false;
+    uint64_t st_slots = 0, st_bytes = 0;
+    uint64_t *d_st_off = nullptr;       // [slices] first slot of each slice
+    uint32_t *d_st_width = nullptr;     // [slices] elements per row in the slice
+    uint32_t *d_st_cols = nullptr;      // [slots] column, or ~0 for none
+    void *d_st_vals = nullptr;          // [slots] double or double2
+    void *d_st_diag = nullptr;          // [dim] diagonal sum, double or double2
 };
 
 namespace ls {
@@ -196,6 +204,9 @@ void compile_terms(const ls_basis *b, uint32_t n_terms, const ls_term *terms, ls
 uint32_t matvec_max_terms();   // the term table is staged in LDS
 uint64_t count_elements(const ls_operator *op, hipStream_t stream);
 void launch_matvec(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t stream);
+// Stores the operator's elements (at most max_bytes); returns the bytes held.
+uint64_t store_elements(ls_operator *op, uint64_t max_bytes, hipStream_t stream);
+void launch_stored(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t stream);
 
 // batch.hip
 void batch_create(uint32_t n, const ls_operator *const *ops, const uint32_t *nrhs, ls_batch **out);

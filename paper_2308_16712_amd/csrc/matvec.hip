@@ -139,6 +139,10 @@ int nr_chunk(uint32_t left) { return left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ?
 
 void launch_matvec(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t st) {
     if (op->basis->dim == 0) return;
+    if (op->stored) {
+        launch_stored(op, nrhs, x, y, st);
+        return;
+    }
     const Variant v = variant_of(op);
     uint32_t col = 0;
     while (col < nrhs) {

@@ -71,6 +71,45 @@ struct Val<true> {
     using T = double2;
 };
 
+// Shared arithmetic of a row: the on-the-fly product, the element store and
+// the stored product all go through these, so they round identically.
+
+// acc = diagonal sum (dre + i dim) times x_i
+template <bool CPLX>
+__device__ __forceinline__ typename Val<CPLX>::T diag_times(double dre, double dim_, typename Val<CPLX>::T v) {
+    if constexpr (CPLX) return make_double2(dre * v.x - dim_ * v.y, dre * v.y + dim_ * v.x);
+    else return dre * v;
+}
+
+// Element value conj(c_t) (-1)^popcount(r & sign_t) chi(g*) sqrt(stab_j / stab_i)
+// (the term table already holds conj(c_t)).
+template <int CHI, bool CPLX>
+__device__ __forceinline__ typename Val<CPLX>::T element_value(const ls_term_dev &Tm, uint64_t r, uint32_t st_j,
+                                                               double st_i, const PlanDev &P, uint32_t code) {
+    const double f = sign_of(r & Tm.sign) * __dsqrt_rn(__ddiv_rn(static_cast<double>(st_j), st_i));
+    if constexpr (!CPLX) {
+        double coef = f * Tm.re;
+        if constexpr (CHI == kChiReal) coef *= P.chi[code].x;
+        return coef;
+    } else {
+        double cre = f * Tm.re, cim = f * Tm.im;
+        if constexpr (CHI != kChiTrivial) {
+            const double2 c = P.chi[code];
+            const double tre = cre * c.x - cim * c.y;
+            cim = cre * c.y + cim * c.x;
+            cre = tre;
+        }
+        return make_double2(cre, cim);
+    }
+}
+
+// acc += value * x_j
+__device__ __forceinline__ void accumulate(double &acc, double c, double v) { acc = fma(c, v, acc); }
+__device__ __forceinline__ void accumulate(double2 &acc, double2 c, double2 v) {
+    acc.x = fma(c.x, v.x, fma(-c.y, v.y, acc.x));
+    acc.y = fma(c.x, v.y, fma(c.y, v.x, acc.y));
+}
+
 constexpr int block_of(int kind) { return kind == kOrbitTorus ? 1024 : 256; }
 
 __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
@@ -119,6 +158,48 @@ __device__ __forceinline__ void stage_tables(const MatvecJob &a, const LdsTables
     }
 }
 
+// Sum of the diagonal terms acting on r: dre + i dim_.
+template <bool CPLX>
+__device__ __forceinline__ void diag_sum(const ls_term_dev *sterm, uint32_t n_diag, uint64_t r, double &dre,
+                                         double &dim_) {
+    dre = 0.0;
+    dim_ = 0.0;
+    for (uint32_t q = 0; q < n_diag; ++q) {
+        const ls_term_dev &D = sterm[q];
+        if ((r & D.sel) != D.val) continue;
+        const double sg = sign_of(r & D.sign);
+        dre += sg * D.re;
+        if constexpr (CPLX) dim_ += sg * D.im;
+    }
+}
+
+// Torus search: p(r) for every coset representative p of the row.
+template <typename W>
+__device__ __forceinline__ void row_images(const PlanDev &P, uint64_t r, W *pr) {
+#pragma unroll
+    for (uint32_t p = 0; p < kTorusCosetSlots; ++p)
+        if (p < P.n_cosets) pr[p] = apply_coset<W>(P.cosets[p], static_cast<W>(r), P);
+}
+
+// Orbit minimum of the neighbour r ^ flip_t of off-diagonal term t, and the
+// code of an element reaching it (tori: from the row's coset images).
+template <typename W, int KIND, bool TRACK, uint32_t LX, uint32_t LY, uint32_t NZ>
+__device__ __forceinline__ W neighbour_rep(const MatvecJob &a, const LdsTables &L, uint64_t r, const W *pr,
+                                           uint32_t t, uint32_t &code) {
+    if constexpr (KIND == kOrbitTorus) {
+        const uint32_t n_off = a.n_terms - a.n_diag;
+        const uint32_t ko = t - a.n_diag;
+        W us[kTorusCosetSlots];
+#pragma unroll
+        for (uint32_t p = 0; p < kTorusCosetSlots; ++p)
+            us[p] = p < a.plan.n_cosets ? (pr[p] ^ static_cast<W>(L.cflip[p * n_off + ko])) : W(0);
+        return torus_orbit_min<W, TRACK, LX, LY, NZ>(a.plan, us, L.lut, L.col, code);
+    } else {
+        (void)pr;
+        return orbit_min<W, KIND, TRACK>(a.plan, static_cast<W>(r ^ L.terms[t].flip), code);
+    }
+}
+
 // Rows row0, row0 + step, ... (count of them, below dim) of one job.
 template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
 __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L, uint64_t row0, uint64_t step,
@@ -128,7 +209,6 @@ __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L,
     const T *x = static_cast<const T *>(a.x);
     T *y = static_cast<T *>(a.y);
     const ls_term_dev *sterm = L.terms;
-    const uint32_t n_off = a.n_terms - a.n_diag;
 
     uint64_t row = row0;
     uint32_t k = 0;
@@ -143,25 +223,11 @@ __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L,
     auto begin_row = [&]() {
         r = a.search.reps[row];
         st_i = static_cast<double>(a.stab[row]);
-        double dre = 0.0, dim_ = 0.0;
-        for (uint32_t q = 0; q < a.n_diag; ++q) {
-            const ls_term_dev &D = sterm[q];
-            if ((r & D.sel) != D.val) continue;
-            const double sg = sign_of(r & D.sign);
-            dre += sg * D.re;
-            if constexpr (CPLX) dim_ += sg * D.im;
-        }
+        double dre, dim_;
+        diag_sum<CPLX>(sterm, a.n_diag, r, dre, dim_);
 #pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            const T v = x[row * a.ld + a.col + q];
-            if constexpr (CPLX) acc[q] = make_double2(dre * v.x - dim_ * v.y, dre * v.y + dim_ * v.x);
-            else acc[q] = dre * v;
-        }
-        if constexpr (KIND == kOrbitTorus) {
-#pragma unroll
-            for (uint32_t p = 0; p < kTorusCosetSlots; ++p)
-                if (p < a.plan.n_cosets) pr[p] = apply_coset<W>(a.plan.cosets[p], static_cast<W>(r), a.plan);
-        }
+        for (int q = 0; q < NR; ++q) acc[q] = diag_times<CPLX>(dre, dim_, x[row * a.ld + a.col + q]);
+        if constexpr (KIND == kOrbitTorus) row_images<W>(a.plan, r, pr);
         t = a.n_diag;
     };
     begin_row();
@@ -179,43 +245,14 @@ __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L,
         }
         const ls_term_dev &Tm = sterm[t];
         uint32_t code;
-        W rep;
-        if constexpr (KIND == kOrbitTorus) {
-            const uint32_t ko = t - a.n_diag;
-            W us[kTorusCosetSlots];
-#pragma unroll
-            for (uint32_t p = 0; p < kTorusCosetSlots; ++p)
-                us[p] = p < a.plan.n_cosets ? (pr[p] ^ static_cast<W>(L.cflip[p * n_off + ko])) : W(0);
-            rep = torus_orbit_min<W, TRACK, LX, LY, NZ>(a.plan, us, L.lut, L.col, code);
-        } else {
-            const W s = static_cast<W>(r ^ Tm.flip);
-            rep = orbit_min<W, KIND, TRACK>(a.plan, s, code);
-        }
+        const W rep = neighbour_rep<W, KIND, TRACK, LX, LY, NZ>(a, L, r, pr, t, code);
         ++t;
         uint32_t st_j = 0;
         const int64_t j = lookup_index_stab(a.search, static_cast<uint64_t>(rep), a.stab, st_j);
         if (j < 0) continue;
-        const double f = sign_of(r & Tm.sign) * __dsqrt_rn(__ddiv_rn(static_cast<double>(st_j), st_i));
-        if constexpr (!CPLX) {
-            double coef = f * Tm.re;
-            if constexpr (CHI == kChiReal) coef *= a.plan.chi[code].x;
+        const T c = element_value<CHI, CPLX>(Tm, r, st_j, st_i, a.plan, code);
 #pragma unroll
-            for (int q = 0; q < NR; ++q) acc[q] = fma(coef, x[j * a.ld + a.col + q], acc[q]);
-        } else {
-            double cre = f * Tm.re, cim = f * Tm.im;
-            if constexpr (CHI != kChiTrivial) {
-                const double2 c = a.plan.chi[code];
-                const double tre = cre * c.x - cim * c.y;
-                cim = cre * c.y + cim * c.x;
-                cre = tre;
-            }
-#pragma unroll
-            for (int q = 0; q < NR; ++q) {
-                const double2 v = x[j * a.ld + a.col + q];
-                acc[q].x = fma(cre, v.x, fma(-cim, v.y, acc[q].x));
-                acc[q].y = fma(cre, v.y, fma(cim, v.x, acc[q].y));
-            }
-        }
+        for (int q = 0; q < NR; ++q) accumulate(acc[q], c, x[j * a.ld + a.col + q]);
     }
 }
 

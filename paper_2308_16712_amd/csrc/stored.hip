@@ -1,0 +1,258 @@
+// Stored matrix elements: the products of an operator taken from memory
+// instead of being regenerated.
+//
+// The paper generates elements on the fly because a stored Hamiltonian does
+// not fit the memory of its machines (Section 2.2); one GPU with 288 GB of
+// HBM holds the elements of sectors with up to a few billion of them (the
+// 6x6 J1-J2 sector: 1.19e9 elements, 14 GB), and a product then reads them
+// at HBM speed instead of redoing the orbit searches.
+//
+// Layout (sliced ELLPACK, slice = 64 consecutive rows = one wavefront): for
+// slice g of width w_g (the most off-diagonal terms acting on one of its
+// rows), element k of row i sits at off[g] + 64 k + (i mod 64), so the 64
+// lanes of a wavefront read 64 consecutive slots.  Element k of a row is the
+// row's k-th acting term in term order; a term whose neighbour is not in the
+// basis, and padding, hold column kNoCol.  The diagonal sum of each row is
+// stored separately.
+//
+// The store runs the same row code as the on-the-fly product (diag_sum,
+// neighbour_rep, lookup, element_value) and the stored product accumulates
+// in the same order with the same operations, so both give the same bits.
+
+#include <algorithm>
+#include <vector>
+
+#include "dispatch.hpp"
+
+namespace ls {
+
+namespace {
+
+constexpr uint32_t kSlice = 64;
+constexpr uint32_t kNoCol = 0xFFFFFFFFu;
+
+// Width of every slice: the most acting off-diagonal terms over its rows.
+__global__ void __launch_bounds__(256) k_slice_width(const uint64_t *reps, uint64_t dim, const ls_term_dev *terms,
+                                                     uint32_t n_diag, uint32_t n_terms, uint32_t *width) {
+    const uint64_t row = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
+    uint32_t c = 0;
+    if (row < dim) {
+        const uint64_t r = reps[row];
+        for (uint32_t t = n_diag; t < n_terms; ++t) c += (r & terms[t].sel) == terms[t].val ? 1u : 0u;
+    }
+    // a wavefront is one slice: maximum over its 64 lanes
+    for (int o = 32; o > 0; o >>= 1) c = max(c, static_cast<uint32_t>(__shfl_xor(static_cast<int>(c), o, 64)));
+    if ((row & (kSlice - 1)) == 0 && row < dim) width[row / kSlice] = c;
+}
+
+struct StoreArgs {
+    MatvecJob job;
+    const uint64_t *off;     // [slices]
+    uint32_t *cols;          // [slots]
+    void *vals;              // [slots] double or double2
+    void *diag;              // [dim] double (dre) or double2 (dre, dim)
+};
+
+template <typename W, int KIND, int CHI, bool CPLX, uint32_t LX, uint32_t LY, uint32_t NZ>
+__global__ void __launch_bounds__(block_of(KIND)) k_store(StoreArgs s) {
+    constexpr int BLOCK = block_of(KIND);
+    constexpr bool TRACK = CHI != kChiTrivial;
+    using T = typename Val<CPLX>::T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const MatvecJob &a = s.job;
+    const LdsTables L = lds_tables<KIND, LX, BLOCK>(a, smem);
+    stage_tables<KIND, LX, BLOCK>(a, L);
+    __syncthreads();
+    const uint64_t row = static_cast<uint64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+    if (row >= a.dim) return;
+    const uint64_t r = a.search.reps[row];
+    const double st_i = static_cast<double>(a.stab[row]);
+    double dre, dim_;
+    diag_sum<CPLX>(L.terms, a.n_diag, r, dre, dim_);
+    if constexpr (CPLX) static_cast<double2 *>(s.diag)[row] = make_double2(dre, dim_);
+    else static_cast<double *>(s.diag)[row] = dre;
+    W pr[kTorusCosetSlots] = {};
+    if constexpr (KIND == kOrbitTorus) row_images<W>(a.plan, r, pr);
+    const uint64_t base = s.off[row / kSlice] + (row & (kSlice - 1));
+    uint32_t k = 0;
+    for (uint32_t t = a.n_diag; t < a.n_terms; ++t) {
+        const ls_term_dev &Tm = L.terms[t];
+        if ((r & Tm.sel) != Tm.val) continue;
+        uint32_t code;
+        const W rep = neighbour_rep<W, KIND, TRACK, LX, LY, NZ>(a, L, r, pr, t, code);
+        uint32_t st_j = 0;
+        const int64_t j = lookup_index_stab(a.search, static_cast<uint64_t>(rep), a.stab, st_j);
+        const uint64_t slot = base + static_cast<uint64_t>(k) * kSlice;
+        ++k;
+        if (j < 0) continue;   // the slot keeps kNoCol
+        s.cols[slot] = static_cast<uint32_t>(j);
+        static_cast<T *>(s.vals)[slot] = element_value<CHI, CPLX>(Tm, r, st_j, st_i, a.plan, code);
+    }
+}
+
+struct StoreLaunch {
+    StoreArgs args;
+    hipStream_t st;
+    template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
+    void run() {
+        if constexpr (NR != 1) {
+            throw Error{LS_EINTERNAL, "the element store runs with one right-hand side"};
+        } else {
+            constexpr int BLOCK = block_of(KIND);
+            const MatvecJob &j = args.job;
+            const size_t lds = lds_bytes(KIND, j.n_terms, j.n_terms - j.n_diag, j.plan.lx);
+            const uint64_t blocks = (j.dim + BLOCK - 1) / BLOCK;
+            hipLaunchKernelGGL((k_store<W, KIND, CHI, CPLX, LX, LY, NZ>), dim3(static_cast<uint32_t>(blocks)),
+                               dim3(BLOCK), lds, st, args);
+        }
+    }
+};
+
+// y = H x from the stored elements; one lane per row, NR columns.
+template <bool CPLX, int NR>
+__global__ void __launch_bounds__(256) k_spmv(const uint64_t *off, const uint32_t *width, const uint32_t *cols,
+                                              const void *vals_, const void *diag_, uint64_t dim, uint32_t ld,
+                                              uint32_t col0, const void *x_, void *y_) {
+    using T = typename Val<CPLX>::T;
+    const uint64_t row = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (row >= dim) return;
+    const T *x = static_cast<const T *>(x_);
+    const T *vals = static_cast<const T *>(vals_);
+    T *y = static_cast<T *>(y_);
+    double dre, dim_ = 0.0;
+    if constexpr (CPLX) {
+        const double2 d = static_cast<const double2 *>(diag_)[row];
+        dre = d.x;
+        dim_ = d.y;
+    } else {
+        dre = static_cast<const double *>(diag_)[row];
+    }
+    T acc[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[q] = diag_times<CPLX>(dre, dim_, x[row * ld + col0 + q]);
+    const uint64_t g = row / kSlice;
+    const uint32_t w = width[g];
+    const uint64_t base = off[g] + (row & (kSlice - 1));
+    for (uint32_t k = 0; k < w; ++k) {
+        const uint64_t slot = base + static_cast<uint64_t>(k) * kSlice;
+        const uint32_t j = cols[slot];
+        if (j == kNoCol) continue;
+        const T v = vals[slot];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) accumulate(acc[q], v, x[static_cast<uint64_t>(j) * ld + col0 + q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) y[row * ld + col0 + q] = acc[q];
+}
+
+template <bool CPLX>
+void launch_spmv_nr(const ls_operator *op, int nr, uint32_t nrhs, uint32_t col, const void *x, void *y,
+                    hipStream_t st) {
+    const uint64_t dim = op->basis->dim;
+    const dim3 grid(static_cast<uint32_t>((dim + 255) / 256));
+    switch (nr) {
+        case 8:
+            hipLaunchKernelGGL((k_spmv<CPLX, 8>), grid, dim3(256), 0, st, op->d_st_off, op->d_st_width, op->d_st_cols,
+                               op->d_st_vals, op->d_st_diag, dim, nrhs, col, x, y);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_spmv<CPLX, 4>), grid, dim3(256), 0, st, op->d_st_off, op->d_st_width, op->d_st_cols,
+                               op->d_st_vals, op->d_st_diag, dim, nrhs, col, x, y);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_spmv<CPLX, 2>), grid, dim3(256), 0, st, op->d_st_off, op->d_st_width, op->d_st_cols,
+                               op->d_st_vals, op->d_st_diag, dim, nrhs, col, x, y);
+            break;
+        default:
+            hipLaunchKernelGGL((k_spmv<CPLX, 1>), grid, dim3(256), 0, st, op->d_st_off, op->d_st_width, op->d_st_cols,
+                               op->d_st_vals, op->d_st_diag, dim, nrhs, col, x, y);
+            break;
+    }
+}
+
+}  // namespace
+
+uint64_t store_elements(ls_operator *op, uint64_t max_bytes, hipStream_t st) {
+    if (op->stored) return op->st_bytes;
+    const ls_basis *b = op->basis;
+    const uint64_t dim = b->dim;
+    const uint64_t slices = (dim + kSlice - 1) / kSlice;
+    const size_t es = op->is_complex ? sizeof(double2) : sizeof(double);
+    std::vector<uint32_t> width(slices, 0);
+    std::vector<uint64_t> off(slices, 0);
+    uint32_t *d_width = nullptr;
+    if (slices > 0) {
+        LS_HIP_CHECK(hipMalloc(&d_width, slices * sizeof(uint32_t)));
+        hipLaunchKernelGGL(k_slice_width, dim3(static_cast<uint32_t>((dim + 255) / 256)), dim3(256), 0, st, b->d_reps,
+                           dim, op->d_terms, op->n_diag, op->n_diag + op->n_off, d_width);
+        const hipError_t e = hipGetLastError();
+        if (e == hipSuccess) hipMemcpyAsync(width.data(), d_width, slices * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+        const hipError_t e2 = hipStreamSynchronize(st);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            hipFree(d_width);
+            throw Error{LS_EDEVICE, "slice widths failed"};
+        }
+    }
+    uint64_t slots = 0;
+    for (uint64_t g = 0; g < slices; ++g) {
+        off[g] = slots;
+        slots += static_cast<uint64_t>(width[g]) * kSlice;
+    }
+    const uint64_t bytes = slots * (sizeof(uint32_t) + es) + slices * (sizeof(uint64_t) + sizeof(uint32_t)) + dim * es;
+    if (bytes > max_bytes) {
+        hipFree(d_width);
+        throw Error{LS_ENOMEM, "the stored elements would exceed max_bytes"};
+    }
+    uint64_t *d_off = nullptr;
+    uint32_t *d_cols = nullptr;
+    void *d_vals = nullptr, *d_diag = nullptr;
+    auto release = [&]() {
+        hipFree(d_width);
+        hipFree(d_off);
+        hipFree(d_cols);
+        hipFree(d_vals);
+        hipFree(d_diag);
+    };
+    try {
+        if (hipMalloc(&d_off, std::max<uint64_t>(slices, 1) * sizeof(uint64_t)) != hipSuccess ||
+            hipMalloc(&d_cols, std::max<uint64_t>(slots, 1) * sizeof(uint32_t)) != hipSuccess ||
+            hipMalloc(&d_vals, std::max<uint64_t>(slots, 1) * es) != hipSuccess ||
+            hipMalloc(&d_diag, std::max<uint64_t>(dim, 1) * es) != hipSuccess)
+            throw Error{LS_ENOMEM, "device allocation for the stored elements failed"};
+        if (slices > 0)
+            LS_HIP_CHECK(hipMemcpyAsync(d_off, off.data(), slices * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+        if (slots > 0) LS_HIP_CHECK(hipMemsetAsync(d_cols, 0xFF, slots * sizeof(uint32_t), st));
+        if (dim > 0) {
+            StoreLaunch L{StoreArgs{job_of(op, nullptr, nullptr, 1, 0), d_off, d_cols, d_vals, d_diag}, st};
+            dispatch(variant_of(op), 1, L);
+            LS_HIP_CHECK(hipGetLastError());
+        }
+        LS_HIP_CHECK(hipStreamSynchronize(st));
+    } catch (...) {
+        release();
+        throw;
+    }
+    op->d_st_width = d_width;
+    op->d_st_off = d_off;
+    op->d_st_cols = d_cols;
+    op->d_st_vals = d_vals;
+    op->d_st_diag = d_diag;
+    op->st_slots = slots;
+    op->st_bytes = bytes;
+    op->stored = true;
+    return bytes;
+}
+
+void launch_stored(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t st) {
+    if (op->basis->dim == 0) return;
+    uint32_t col = 0;
+    while (col < nrhs) {
+        const int nr = nr_chunk(nrhs - col);
+        if (op->is_complex) launch_spmv_nr<true>(op, nr, nrhs, col, x, y, st);
+        else launch_spmv_nr<false>(op, nr, nrhs, col, x, y, st);
+        LS_HIP_CHECK(hipGetLastError());
+        col += static_cast<uint32_t>(nr);
+    }
+}
+
+}  // namespace ls
