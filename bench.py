@@ -179,6 +179,31 @@ def serving(count: int, rate: float, budget_gb: float, max_iter: int, tol: float
                                  "latency includes queueing"}
 
 
+def push_product(op, x, pull_ms: float, elements: int, steps: int):
+    """The push (transposed, atomic-add) form of the same product on the same
+    input: time per product on the launch stream, and its distance from the
+    pull result."""
+    import torch
+    import paper_2308_16712_amd as ls
+
+    y_pull = ls.ls_matvec(op, x)
+    y = ls.ls_matvec_push(op, x)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        ls.ls_matvec_push(op, x, y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    rel = float(torch.linalg.norm(y - y_pull) / torch.linalg.norm(y_pull))
+    del y, y_pull
+    return {"ms_per_product": ms, "elements_per_s": elements / (ms * 1e-3), "pull_over_push_time": ms / pull_ms,
+            "rel_l2_vs_pull": rel, "form": "transposed: y_j += conj(H_ij) x_i with FP64 atomic adds"}
+
+
 def stored_product(basis, sector, x, y, fly_ms: float, elements: int, steps: int):
     """The same product from stored elements (ls_operator_store): store time
     and size, product time on the launch stream, and bit-identity with the
@@ -310,6 +335,7 @@ def main():
     ap.add_argument("--serve-max-iter", type=int, default=150)
     ap.add_argument("--no-enumeration", action="store_true", help="skip the Table 2 enumeration leg")
     ap.add_argument("--no-stored", action="store_true", help="skip the stored-elements product")
+    ap.add_argument("--no-push", action="store_true", help="skip the push (atomic) product")
     ap.add_argument("--enum-counts", default="40,42", help="chain sizes counted without storage")
     ap.add_argument("--enum-build", type=int, default=40, help="chain size built and stored (0: none)")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -392,6 +418,9 @@ def main():
         "hbm_algorithmic_gbps": alg_bytes / (kernel_ms * 1e-3) / 1e9,
         "basis_build_s": build_s,
     }
+    if not args.no_push:
+        print("[bench] push form", file=sys.stderr, flush=True)
+        out["push"] = push_product(op, x, kernel_ms, elements, args.steps)
     if not args.no_stored:
         print("[bench] stored elements", file=sys.stderr, flush=True)
         out["stored"] = stored_product(basis, sector, x, y, kernel_ms, elements, args.steps)

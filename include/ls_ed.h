@@ -216,6 +216,15 @@ ls_status ls_operator_count(const ls_operator *op, uint64_t *n_offdiag, void *st
  * belongs to an orbit the projector annihilates and contributes zero.     */
 ls_status ls_matvec(const ls_operator *op, uint32_t nrhs, const void *d_x, void *d_y, void *stream);
 
+/* y = H x in the push (transposed) form of Section 5.3's second listing, a
+ * comparison variant of ls_matvec: each row's elements H_ij are generated
+ * as for ls_matvec and conj(H_ij) x_i is added into y_j with device-scope
+ * atomic adds (y is zeroed first, on `stream`).  Arguments, layouts and
+ * errors as ls_matvec.  The order of the adds into one y_j varies between
+ * runs, so results agree with ls_matvec to rounding, not bit for bit.
+ * The elements are always generated (a stored form is not used).          */
+ls_status ls_matvec_push(const ls_operator *op, uint32_t nrhs, const void *d_x, void *d_y, void *stream);
+
 /* ---- batched products ------------------------------------------------------
  * Many products y_k = H_k x_k (k = 0..n-1) over operators of different
  * sectors, couplings and dimensions, each with its own number of right-hand

@@ -21,7 +21,7 @@ _NAMES = {0: "LS_OK", 1: "LS_WNOTCONV", -1: "LS_EINVAL", -2: "LS_ENOMEM", -3: "L
 
 EXPORTS = ["ls_sector_check", "ls_sector_count", "ls_basis_build", "ls_basis_info", "ls_basis_copy", "ls_basis_destroy", "ls_state_info",
            "ls_index_lookup", "ls_operator_create", "ls_operator_destroy", "ls_operator_info",
-           "ls_operator_count", "ls_operator_store", "ls_matvec",
+           "ls_operator_count", "ls_operator_store", "ls_matvec", "ls_matvec_push",
            "ls_batch_create", "ls_batch_matvec", "ls_batch_info", "ls_batch_set_graph", "ls_batch_destroy",
            "ls_lanczos", "ls_solver_footprint", "ls_solver_create", "ls_solver_step", "ls_solver_result",
            "ls_solver_destroy", "ls_last_error", "ls_version"]
@@ -78,6 +78,7 @@ def load(path: str = LIB_PATH):
         "ls_operator_info": ([P, P, P], i32),
         "ls_operator_count": ([P, P, P], i32),
         "ls_matvec": ([P, u32, P, P, P], i32),
+        "ls_matvec_push": ([P, u32, P, P, P], i32),
         "ls_batch_create": ([u32, P, P, P], i32),
         "ls_batch_matvec": ([P, P, P, P], i32),
         "ls_batch_info": ([P, P, P, P], i32),
@@ -279,6 +280,20 @@ class Operator:
         if y is None:
             y = torch.empty_like(x)
         _check(load().ls_matvec(self._h, nrhs, _dptr(x), _dptr(y), _stream_ptr(stream)))
+        return y
+
+    def matvec_push(self, x, y=None, stream=None):
+        """y = H x in the push (transposed, atomic) form (ls_matvec_push)."""
+        import torch
+        want = torch.complex128 if self.is_complex else torch.float64
+        if x.dtype != want:
+            raise TypeError(f"x must be {want}")
+        nrhs = 1 if x.dim() == 1 else x.shape[1]
+        if x.shape[0] != self.dim:
+            raise ValueError("x has the wrong dimension")
+        if y is None:
+            y = torch.empty_like(x)
+        _check(load().ls_matvec_push(self._h, nrhs, _dptr(x), _dptr(y), _stream_ptr(stream)))
         return y
 
     def lanczos(self, max_iter: int, tol: float = 0.0, seed: int = 1, v0=None, reorth: bool = True,

@@ -243,6 +243,21 @@ ls_status ls_matvec(const ls_operator *op, uint32_t nrhs, const void *d_x, void 
     });
 }
 
+ls_status ls_matvec_push(const ls_operator *op, uint32_t nrhs, const void *d_x, void *d_y, void *stream) {
+    return guarded([&] {
+        LS_REQUIRE(op != nullptr, "operator must not be NULL");
+        LS_REQUIRE(nrhs >= 1 && nrhs <= 64, "nrhs must be in 1..64");
+        if (op->basis->dim == 0) return LS_OK;
+        LS_REQUIRE(d_x != nullptr && d_y != nullptr, "x and y must not be NULL");
+        const size_t bytes = op->basis->dim * nrhs * (op->is_complex ? 16u : 8u);
+        const char *xb = static_cast<const char *>(d_x);
+        const char *yb = static_cast<const char *>(d_y);
+        LS_REQUIRE(xb + bytes <= yb || yb + bytes <= xb, "x and y must not overlap");
+        ls::launch_matvec_push(op, nrhs, d_x, d_y, as_stream(stream));
+        return LS_OK;
+    });
+}
+
 ls_status ls_batch_create(uint32_t n, const ls_operator *const *ops, const uint32_t *nrhs, ls_batch **out) {
     return guarded([&] {
         ls::batch_create(n, ops, nrhs, out);

@@ -204,6 +204,8 @@ void compile_terms(const ls_basis *b, uint32_t n_terms, const ls_term *terms, ls
 uint32_t matvec_max_terms();   // the term table is staged in LDS
 uint64_t count_elements(const ls_operator *op, hipStream_t stream);
 void launch_matvec(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t stream);
+// Push (transposed, atomic) form of the product; y is zeroed first.
+void launch_matvec_push(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t stream);
 // Stores the operator's elements (at most max_bytes); returns the bytes held.
 uint64_t store_elements(ls_operator *op, uint64_t max_bytes, hipStream_t stream);
 void launch_stored(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t stream);

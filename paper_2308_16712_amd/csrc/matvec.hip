@@ -32,9 +32,28 @@ k_matvec(MatvecJob a, uint64_t n_lanes, uint32_t rows_per_lane) {
     run_rows<W, KIND, CHI, CPLX, NR, LX, LY, NZ>(a, L, lane, n_lanes, rows_per_lane);
 }
 
+// Push form (comparison variant): same launch shape as k_matvec.
+template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
+__global__ void __launch_bounds__(block_of(KIND)) k_matvec_push(MatvecJob a, uint64_t n_lanes, uint32_t rows_per_lane) {
+    constexpr int BLOCK = block_of(KIND);
+    extern __shared__ __align__(16) unsigned char smem[];
+    const LdsTables L = lds_tables<KIND, LX, BLOCK>(a, smem);
+    stage_tables<KIND, LX, BLOCK>(a, L);
+    __syncthreads();
+    const uint64_t lane = static_cast<uint64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+    push_rows<W, KIND, CHI, CPLX, NR, LX, LY, NZ>(a, L, lane, n_lanes, rows_per_lane);
+}
+
+// y = 0 for the push form (a fill kernel, so the sequence may be captured)
+__global__ void __launch_bounds__(256) k_zero(double *y, uint64_t n) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i < n) y[i] = 0.0;
+}
+
 struct SingleLaunch {
     MatvecJob job;
     hipStream_t st;
+    bool push = false;
     template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
     void run() {
         constexpr int BLOCK = block_of(KIND);
@@ -44,8 +63,16 @@ struct SingleLaunch {
         uint64_t lanes = (job.dim + rpl - 1) / rpl;
         lanes = (lanes + BLOCK - 1) / BLOCK * BLOCK;
         const size_t lds = lds_bytes(KIND, job.n_terms, job.n_terms - job.n_diag, job.plan.lx);
-        hipLaunchKernelGGL((k_matvec<W, KIND, CHI, CPLX, NR, LX, LY, NZ>), dim3(static_cast<uint32_t>(lanes / BLOCK)),
-                           dim3(BLOCK), lds, st, job, lanes, rpl);
+        if (push) {
+            // the push form runs one column per launch
+            if constexpr (NR == 1)
+                hipLaunchKernelGGL((k_matvec_push<W, KIND, CHI, CPLX, 1, LX, LY, NZ>),
+                                   dim3(static_cast<uint32_t>(lanes / BLOCK)), dim3(BLOCK), lds, st, job, lanes, rpl);
+            else
+                throw Error{LS_EINTERNAL, "push products run one column per launch"};
+        } else
+            hipLaunchKernelGGL((k_matvec<W, KIND, CHI, CPLX, NR, LX, LY, NZ>),
+                               dim3(static_cast<uint32_t>(lanes / BLOCK)), dim3(BLOCK), lds, st, job, lanes, rpl);
     }
 };
 
@@ -151,6 +178,21 @@ void launch_matvec(const ls_operator *op, uint32_t nrhs, const void *x, void *y,
         dispatch(v, nr, L);
         LS_HIP_CHECK(hipGetLastError());
         col += static_cast<uint32_t>(nr);
+    }
+}
+
+void launch_matvec_push(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t st) {
+    const uint64_t dim = op->basis->dim;
+    if (dim == 0) return;
+    const uint64_t nd = dim * nrhs * (op->is_complex ? 2 : 1);
+    hipLaunchKernelGGL(k_zero, dim3(static_cast<uint32_t>((nd + 255) / 256)), dim3(256), 0, st, static_cast<double *>(y),
+                       nd);
+    LS_HIP_CHECK(hipGetLastError());
+    const Variant v = variant_of(op);
+    for (uint32_t col = 0; col < nrhs; ++col) {
+        SingleLaunch L{job_of(op, x, y, nrhs, col), st, true};
+        dispatch(v, 1, L);
+        LS_HIP_CHECK(hipGetLastError());
     }
 }
 

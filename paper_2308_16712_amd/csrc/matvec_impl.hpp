@@ -256,6 +256,62 @@ __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L,
     }
 }
 
+// y_j += conj(v) x_i with device-scope atomic adds (push form)
+__device__ __forceinline__ void scatter_add(double *y, double v, double xi) { unsafeAtomicAdd(y, v * xi); }
+__device__ __forceinline__ void scatter_add(double2 *y, double2 v, double2 xi) {
+    // conj(v) * xi
+    unsafeAtomicAdd(&y->x, v.x * xi.x + v.y * xi.y);
+    unsafeAtomicAdd(&y->y, v.x * xi.y - v.y * xi.x);
+}
+
+// Push (transposed) form of the product, the second listing of Section 5.3:
+// row i's elements H_ij are generated as in the pull form, and H_ji x_i =
+// conj(H_ij) x_i is added into y_j (y_i gets the diagonal) with atomic adds,
+// so y must start at zero.  The order of the adds into one y_j varies from
+// run to run.  Rows row0, row0 + step, ... (count of them).
+template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
+__device__ __forceinline__ void push_rows(const MatvecJob &a, const LdsTables &L, uint64_t row0, uint64_t step,
+                                          uint32_t count) {
+    constexpr bool TRACK = CHI != kChiTrivial;
+    using T = typename Val<CPLX>::T;
+    const T *x = static_cast<const T *>(a.x);
+    T *y = static_cast<T *>(a.y);
+    uint64_t row = row0;
+    for (uint32_t k = 0; k < count && row < a.dim; ++k, row += step) {
+        const uint64_t r = a.search.reps[row];
+        const double st_i = static_cast<double>(a.stab[row]);
+        T xi[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) xi[q] = x[row * a.ld + a.col + q];
+        double dre, dim_;
+        diag_sum<CPLX>(L.terms, a.n_diag, r, dre, dim_);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            const T d = diag_times<CPLX>(dre, dim_, xi[q]);
+            if constexpr (CPLX) {
+                unsafeAtomicAdd(&y[row * a.ld + a.col + q].x, d.x);
+                unsafeAtomicAdd(&y[row * a.ld + a.col + q].y, d.y);
+            } else {
+                unsafeAtomicAdd(&y[row * a.ld + a.col + q], d);
+            }
+        }
+        W pr[kTorusCosetSlots] = {};
+        if constexpr (KIND == kOrbitTorus) row_images<W>(a.plan, r, pr);
+        for (uint32_t t = a.n_diag; t < a.n_terms; ++t) {
+            const ls_term_dev &Tm = L.terms[t];
+            if ((r & Tm.sel) != Tm.val) continue;
+            uint32_t code;
+            const W rep = neighbour_rep<W, KIND, TRACK, LX, LY, NZ>(a, L, r, pr, t, code);
+            uint32_t st_j = 0;
+            const int64_t j = lookup_index_stab(a.search, static_cast<uint64_t>(rep), a.stab, st_j);
+            if (j < 0) continue;
+            const T v = element_value<CHI, CPLX>(Tm, r, st_j, st_i, a.plan, code);
+#pragma unroll
+            for (int q = 0; q < NR; ++q) scatter_add(&y[static_cast<uint64_t>(j) * a.ld + a.col + q], v, xi[q]);
+        }
+    }
+}
+
 // Kernel variant of an operator: word size, orbit kind, torus shape.
 struct Variant {
     int word64;      // 0: 32-bit states, 1: 64-bit

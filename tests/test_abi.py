@@ -104,6 +104,7 @@ def test_null_arguments():
     h = ctypes.c_void_p()
     assert L.ls_basis_build(None, None, ctypes.byref(h)) == _lib.LS_EINVAL
     assert L.ls_matvec(None, 1, None, None, None) == _lib.LS_EINVAL
+    assert L.ls_matvec_push(None, 1, None, None, None) == _lib.LS_EINVAL
     assert L.ls_state_info(None, 0, None, None, None, None, None) == _lib.LS_EINVAL
     assert L.ls_index_lookup(None, 0, None, None, None) == _lib.LS_EINVAL
     assert L.ls_lanczos(None, None, None, None, None, None) == _lib.LS_EINVAL
@@ -120,7 +121,7 @@ def test_null_arguments():
 
 def test_binding_names_match_abi():
     for name in ("ls_basis_build", "ls_state_info", "ls_index_lookup", "ls_matvec", "ls_lanczos",
-                 "ls_operator_create", "ls_operator_store", "ls_operator_count", "ls_sector_count",
+                 "ls_operator_create", "ls_operator_store", "ls_operator_count", "ls_matvec_push", "ls_sector_count",
                  "ls_sector_check", "ls_batch_create", "ls_batch_matvec"):
         assert callable(getattr(ls, name))
 
