@@ -242,6 +242,52 @@ def stored_product(basis, sector, x, y, fly_ms: float, elements: int, steps: int
             "layout": "sliced ELLPACK, 64-row slices, uint32 column + value per slot"}
 
 
+def chain_products(ns, steps: int = 3):
+    """The paper's own workload: closed Heisenberg chains (J = 1, nearest
+    neighbours), Sz = 0, fully symmetric sector of D_N x Z2 (Table 2's
+    sectors), one product on the fly per step.  x is drawn on the device
+    (its values do not change the work)."""
+    import torch
+    import paper_2308_16712_amd as ls
+    from workloads import configs
+
+    out = {}
+    for n in ns:
+        sec = configs.ring_symmetric(n, 0, 1, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b = ls.ls_basis_build(sec)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        op = ls.ls_operator_create(b, sec.terms)
+        elements = op.count_elements() + b.dim
+        g = torch.Generator(device="cuda")
+        g.manual_seed(n)
+        x = torch.rand(b.dim, dtype=torch.float64, device="cuda", generator=g) * 2 - 1
+        y = torch.empty_like(x)
+        ls.ls_matvec(op, x, y)
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            ls.ls_matvec(op, x, y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[f"chain_N{n}"] = {"dim": b.dim, "elements_per_product": elements, "basis_build_s": build_s,
+                              "ms_per_product": ms, "elements_per_s": elements / (ms * 1e-3)}
+        print(f"[bench] chain N={n}: {ms:.1f} ms per product", file=sys.stderr, flush=True)
+        del x, y
+        op.close()
+        b.close()
+        torch.cuda.empty_cache()
+    out["paper_context"] = ("40 spins: one product takes at least 40 s on 4 nodes of 2x64-core AMD Rome; "
+                            "42 spins: 424 s per core of element generation on one 128-core node")
+    return out
+
+
 def table2_dims():
     """Closed-chain sector dimensions printed in the paper (Section 6, Table 2)."""
     out = {}
@@ -336,6 +382,7 @@ def main():
     ap.add_argument("--no-enumeration", action="store_true", help="skip the Table 2 enumeration leg")
     ap.add_argument("--no-stored", action="store_true", help="skip the stored-elements product")
     ap.add_argument("--no-push", action="store_true", help="skip the push (atomic) product")
+    ap.add_argument("--chains", default="40,42", help="paper-workload chain sizes to time (empty: none)")
     ap.add_argument("--enum-counts", default="40,42", help="chain sizes counted without storage")
     ap.add_argument("--enum-build", type=int, default=40, help="chain size built and stored (0: none)")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -424,12 +471,16 @@ def main():
     if not args.no_stored:
         print("[bench] stored elements", file=sys.stderr, flush=True)
         out["stored"] = stored_product(basis, sector, x, y, kernel_ms, elements, args.steps)
+    del x, y, op, basis
+    torch.cuda.empty_cache()
     if not args.no_batched:
         print("[bench] batched vs plain", file=sys.stderr, flush=True)
-        del x, y, op, basis
-        torch.cuda.empty_cache()
         out["batched"] = batched_vs_plain(args.batched_count, args.batched_nrhs)
         torch.cuda.empty_cache()
+    chain_ns = [int(v) for v in args.chains.split(",") if v]
+    if chain_ns:
+        print("[bench] paper-workload chains", file=sys.stderr, flush=True)
+        out["paper_chains"] = chain_products(chain_ns)
     if not args.no_enumeration:
         print("[bench] enumeration", file=sys.stderr, flush=True)
         ns = [int(v) for v in args.enum_counts.split(",") if v]

@@ -289,3 +289,34 @@ def test_full_square6x6_j1j2():
     dim = ref.character_dimension(sec.group, 18)
     assert dim == 15804956
     _full_size_checks(sec, dim, n_sample=200, n_rows=60)
+
+
+def test_full_chain40_paper_workload():
+    """The paper's 40-spin chain (Section 6: Heisenberg chain, U(1), spin
+    inversion, translation, reflection; Table 2 dimension): the full product
+    on the GPU, checked on rows the oracle computes one by one, with x keyed
+    by basis state and filled on the device."""
+    sec = configs.ring_symmetric(40, 0, 1, 1)
+    P = oracle.Problem(sec)
+    _say("[gpu] full-size chain40")
+    b = ls.ls_basis_build(sec)
+    try:
+        assert b.dim == 861725794
+        reps_t, _ = b.copy()
+        x = rng.state_values_torch(11, reps_t)
+        op = ls.ls_operator_create(b, sec.terms)
+        y = op.matvec(x)
+        pick = (rng.counter_u64(6, np.arange(60, dtype=np.uint64)) % np.uint64(b.dim)).astype(np.int64)
+        pick = np.unique(np.concatenate([pick, [0, b.dim - 1]]))
+        idx = torch.from_numpy(pick).cuda()
+        reps = reps_t[idx].cpu().numpy().view(np.uint64)
+        ys = y[idx].cpu().numpy()
+        del x, y, reps_t
+        for i, r in enumerate(reps):
+            nb, coef = oracle.get_row(P, int(r))
+            yi = np.sum(coef * rng.state_values(11, nb))
+            assert abs(ys[i] - yi) <= MATVEC_TOL * max(1.0, np.max(np.abs(ys))), (pick[i], ys[i], yi)
+        op.close()
+    finally:
+        b.close()
+        torch.cuda.empty_cache()

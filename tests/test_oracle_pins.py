@@ -355,3 +355,14 @@ def test_counter_generator_matches_published_splitmix64(golden_dir):
     assert [st.u64() for _ in range(5)] == want
     got = rng.counter_u64(1234567, np.arange(5, dtype=np.uint64))
     assert got.tolist() == want
+
+
+def test_state_values_torch_matches_numpy():
+    """The tensor form of the state-keyed generator (used to fill full-size
+    vectors on the device) draws the same numbers as the numpy form."""
+    import torch
+    st = rng.counter_u64(77, np.arange(5000, dtype=np.uint64))
+    st = np.concatenate([st, st >> np.uint64(20), np.array([0, 1, (1 << 63), (1 << 64) - 1], dtype=np.uint64)])
+    want = rng.state_values(11, st)
+    got = rng.state_values_torch(11, torch.from_numpy(st.view(np.int64))).numpy()
+    assert np.array_equal(got, want)

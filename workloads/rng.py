@@ -92,6 +92,30 @@ def state_values(seed: int, states: np.ndarray, complex_: bool = False) -> np.nd
     return re + 1j * im
 
 
+def _s64(v: int) -> int:
+    """A 64-bit pattern as a signed int64 value."""
+    v &= MASK64
+    return v - (1 << 64) if v >> 63 else v
+
+
+def _hash64_01_torch(x):
+    """``hash64_01`` on an int64 tensor holding 64-bit patterns (wrapping
+    multiplies; logical shifts by masking the sign-extended bits)."""
+    x = x ^ ((x >> 30) & ((1 << 34) - 1))
+    x = x * _s64(_M1)
+    x = x ^ ((x >> 27) & ((1 << 37) - 1))
+    x = x * _s64(_M2)
+    return x ^ ((x >> 31) & ((1 << 33) - 1))
+
+
+def state_values_torch(seed: int, states):
+    """``state_values`` (real) on a tensor of states stored as int64 bit
+    patterns, evaluated where the tensor lives (for full-size vectors)."""
+    k = _hash64_01_torch(states ^ _s64(seed))
+    u = (_hash64_01_torch(k) >> 11) & ((1 << 53) - 1)
+    return 2.0 * (u.double() * 2.0 ** -53) - 1.0
+
+
 class Stream:
     """Sequential draws from one counter stream (for workload sampling)."""
 
