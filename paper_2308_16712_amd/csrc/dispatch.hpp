@@ -30,6 +30,8 @@ template <typename W, class F>
 void dispatch_kind(const Variant &v, int nr, F &f) {
     if (v.kind == kOrbitRing32) {
         if constexpr (sizeof(W) == 4) dispatch_chi<W, kOrbitRing32, 0, 0, 0>(v, nr, f);
+    } else if (v.kind == kOrbitRing64) {
+        if constexpr (sizeof(W) == 8) dispatch_chi<W, kOrbitRing64, 0, 0, 0>(v, nr, f);
     } else if (v.kind == kOrbitTorus) {
         if constexpr (sizeof(W) == 8) {
             if (v.lx == 6 && v.ly == 6 && v.nz == 2) return dispatch_chi<W, kOrbitTorus, 6, 6, 2>(v, nr, f);

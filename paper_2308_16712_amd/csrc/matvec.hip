@@ -147,6 +147,8 @@ Variant variant_of(const ls_operator *op) {
                        lds_bytes(kOrbitTorus, op->n_diag + op->n_off, op->n_off, gp.lx) <= kMaxLds;
     if (!v.word64 && gp.ly == 1 && gp.lx == gp.n_sites) {
         v.kind = kOrbitRing32;
+    } else if (v.word64 && gp.ly == 1 && gp.lx == gp.n_sites && gp.n_sites < 64) {
+        v.kind = kOrbitRing64;
     } else if (torus) {
         v.kind = kOrbitTorus;
         const uint32_t nz = gp.pair_flip ? 2 : 1;

@@ -17,6 +17,7 @@ enum OrbitKind : int {
     kOrbitGeneric = 0,   // runtime lx, ly (ring, torus, or no translations)
     kOrbitRing32 = 1,    // N <= 32 ring: all rotations from one funnel shift each
     kOrbitTorus = 2,     // lx <= 6, ly >= 2 torus: pruned by the pair table
+    kOrbitRing64 = 3,    // 32 < N < 64 ring: rotations pruned by the longest zero run
 };
 
 // A value that is the same in every active lane, moved to a scalar register.
@@ -122,12 +123,81 @@ __device__ __forceinline__ void for_each_image(const PlanDev &P, W s, F &&f) {
     }
 }
 
+// Rotations of the low n bits of a 64-bit word (0 <= k < n < 64).
+__device__ __forceinline__ uint64_t rotl_n(uint64_t w, uint32_t k, uint32_t n, uint64_t full) {
+    return ((w << k) | (w >> (n - k))) & full;
+}
+__device__ __forceinline__ uint64_t rotr_n(uint64_t w, uint32_t k, uint32_t n, uint64_t full) {
+    return ((w >> k) | (w << (n - k))) & full;
+}
+
+// Smallest rotation of the n-bit ring word w (32 < n < 64), folded into
+// (best, arg).  A smaller word has more leading zeros, so the smallest
+// rotation puts one of w's longest (cyclic) runs of zeros on top: the runs
+// are found with doubling masks R_k (bit i set when zeros occupy i .. i+k-1)
+// and binary lifting of the run length, and only the rotations that lift one
+// of them to the top are compared in full.  Rotating left by k is the
+// translation with code code0 + k * nz.
+template <bool TRACK>
+__device__ __forceinline__ void ring64_fold(uint64_t w, uint32_t n, uint64_t full, uint32_t code0, uint32_t nz,
+                                            uint64_t &best, uint32_t &arg) {
+    const uint64_t z = ~w & full;
+    if (z == 0 || z == full) {   // every rotation of all-ones / all-zeros is w
+        if (w < best) {
+            best = w;
+            if constexpr (TRACK) arg = code0;
+        }
+        return;
+    }
+    uint64_t R[6];               // runs of 1, 2, 4, 8, 16, 32 zeros (32 < n)
+    R[0] = z;
+#pragma unroll
+    for (uint32_t l = 1; l < 6; ++l) R[l] = R[l - 1] & rotr_n(R[l - 1], 1u << (l - 1), n, full);
+    uint64_t cur = z;            // starts of runs of at least L zeros
+    uint32_t L = 1;
+#pragma unroll
+    for (int l = 5; l >= 0; --l) {
+        const uint32_t k = 1u << l;
+        if (L + k < n) {
+            const uint64_t c = cur & rotr_n(R[l], L, n, full);
+            if (c) {
+                cur = c;
+                L += k;
+            }
+        }
+    }
+    while (cur) {
+        const uint32_t i = static_cast<uint32_t>(__builtin_ctzll(cur));
+        cur &= cur - 1;
+        uint32_t top = i + L - 1;             // the run's highest bit
+        if (top >= n) top -= n;
+        const uint32_t k = n - 1 - top;       // rotate it to bit n-1
+        const uint64_t v = rotl_n(w, k, n, full);
+        if (v < best) {
+            best = v;
+            if constexpr (TRACK) arg = code0 + k * nz;
+        }
+    }
+}
+
 // Orbit minimum; with TRACK also the code of the first element reaching it.
 template <typename W, int KIND, bool TRACK>
 __device__ __forceinline__ W orbit_min(const PlanDev &P, W s, uint32_t &code) {
     W best = s;
     uint32_t arg = 0;
-    if constexpr (!TRACK && KIND == kOrbitRing32) {
+    if constexpr (KIND == kOrbitRing64) {
+        const uint64_t full = P.full;
+        const uint32_t n = P.n_sites;
+        const uint32_t nz = P.pair_flip ? 2u : 1u;
+        uint64_t b64 = static_cast<uint64_t>(s);   // s itself is the identity image (code 0)
+        for (uint32_t p0 = 0; p0 < P.n_cosets; ++p0) {
+            const uint32_t p = uni(p0);
+            const uint64_t u = static_cast<uint64_t>(apply_coset<W>(P.cosets[p], s, P));
+            ring64_fold<TRACK>(u, n, full, p * n * nz, nz, b64, arg);
+            if (P.pair_flip) ring64_fold<TRACK>(u ^ full, n, full, p * n * nz + 1, nz, b64, arg);
+        }
+        best = static_cast<W>(b64);
+    } else if constexpr (!TRACK && KIND == kOrbitRing32) {
         // plain min, two images per rotation with spin inversion
         const W full = static_cast<W>(P.full);
         const uint32_t n = P.n_sites;

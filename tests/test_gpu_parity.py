@@ -71,6 +71,8 @@ def _small_sectors():
     # 64-bit words
     out.append(_sector("ring40_w3_D", 40, 3, lattice.ring_group(40, 0, 1), lattice.ring_bonds(40, 1.0, 0.25)))
     out.append(_sector("ring33_w4_k5", 33, 4, lattice.ring_group(33, 5), lattice.ring_bonds(33, 1.0, 0.0)))
+    out.append(_sector("ring34_w3_kpi_rm", 34, 3, lattice.ring_group(34, 17, -1), lattice.ring_bonds(34, 1.0, 0.4)))
+    out.append(_sector("ring63_w2_k7", 63, 2, lattice.ring_group(63, 7), lattice.ring_bonds(63, 1.0, 0.2)))
     out.append(_sector("torus6x6_w3_full", 36, 3, lattice.torus_group(6, 6), lattice.torus_bonds(6, 6, 1.0, 0.5)))
     out.append(_sector("torus6x6_w4_k10", 36, 4, lattice.torus_group(6, 6, 1, 0, "none"),
                        lattice.torus_bonds(6, 6, 1.0, 0.5)))
