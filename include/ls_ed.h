@@ -118,7 +118,7 @@ ls_status ls_basis_build(const ls_sector_desc *desc, void *stream, ls_basis **ou
  * consecutive ranges add up (callers may split the range to report
  * progress).  Outputs (host): *n_members, and *n_candidates = C(N, w) or
  * 2^N (may be NULL).  Blocks until the count on `stream` has finished;
- * device scratch is 16 KiB plus the compiled group.
+ * device scratch is 8 bytes plus the compiled group.
  * Errors: as ls_basis_build; LS_EINVAL also for rank_begin > rank_end.   */
 ls_status ls_sector_count(const ls_sector_desc *desc, uint64_t rank_begin, uint64_t rank_end,
                           uint64_t *n_members, uint64_t *n_candidates, void *stream);

@@ -211,11 +211,12 @@ __global__ void __launch_bounds__(kBlock) k_enum_mark(EnumArgs a) {
 }
 
 // Count-only pass over candidates [begin, end): each lane takes per_lane
-// consecutive candidates; block totals are added into acc[blockIdx.x], so
-// launches on one stream over consecutive ranges accumulate.
+// consecutive candidates; block totals are added into *acc (integer atomic
+// adds: the total does not depend on their order), so launches on one stream
+// over consecutive ranges accumulate.
 template <typename W, int KIND>
 __global__ void __launch_bounds__(kBlock) k_enum_count(EnumArgs a, uint64_t begin, uint64_t end, uint32_t per_lane,
-                                                       uint64_t *acc) {
+                                                       unsigned long long *acc) {
     __shared__ uint32_t sh[kBlock];
     const uint64_t lane = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
     const uint64_t start = begin + lane * per_lane;
@@ -225,7 +226,7 @@ __global__ void __launch_bounds__(kBlock) k_enum_count(EnumArgs a, uint64_t begi
         walk_members<W, KIND>(a.plan, first_candidate<W>(a, start), cnt, a.weight >= 0, [&](uint32_t) { ++c; });
     }
     const uint32_t t = block_sum(c, sh);
-    if (threadIdx.x == 0) acc[blockIdx.x] += t;
+    if (threadIdx.x == 0 && t != 0) atomicAdd(acc, static_cast<unsigned long long>(t));
 }
 
 template <typename W>
@@ -499,14 +500,15 @@ uint64_t candidate_count(const ls_basis *b) {
 
 template <typename W>
 uint64_t count_impl(ls_basis *b, uint64_t begin, uint64_t end, hipStream_t st) {
-    // 8 workgroups per CU; a launch covers 2^29 candidates, a few ms of work
-    constexpr uint32_t kBlocks = 2048, kPerLane = 1024;
-    constexpr uint64_t kSpan = static_cast<uint64_t>(kBlocks) * kBlock * kPerLane;
-    uint64_t *acc = nullptr;
-    LS_HIP_CHECK(hipMalloc(&acc, kBlocks * sizeof(uint64_t)));
-    uint64_t total = 0;
+    // 64 candidates per lane as in the mark pass; a launch covers up to 2^20
+    // workgroups (1.7e10 candidates, a fraction of a second)
+    constexpr uint32_t kPerLane = kCandPerLane;
+    constexpr uint64_t kSpan = (1ull << 20) * kBlock * kPerLane;
+    unsigned long long *acc = nullptr;
+    LS_HIP_CHECK(hipMalloc(&acc, sizeof(unsigned long long)));
+    unsigned long long total = 0;
     try {
-        LS_HIP_CHECK(hipMemsetAsync(acc, 0, kBlocks * sizeof(uint64_t), st));
+        LS_HIP_CHECK(hipMemsetAsync(acc, 0, sizeof(unsigned long long), st));
         EnumArgs a{};
         a.plan = b->plan_dev;
         a.binom = b->d_binom;
@@ -527,16 +529,14 @@ uint64_t count_impl(ls_basis *b, uint64_t begin, uint64_t end, hipStream_t st) {
             LS_HIP_CHECK(hipGetLastError());
             lo = hi;
         }
-        std::vector<uint64_t> h(kBlocks);
-        LS_HIP_CHECK(hipMemcpyAsync(h.data(), acc, kBlocks * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+        LS_HIP_CHECK(hipMemcpyAsync(&total, acc, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         LS_HIP_CHECK(hipStreamSynchronize(st));
-        for (uint64_t v : h) total += v;
     } catch (...) {
         hipFree(acc);
         throw;
     }
     hipFree(acc);
-    return total;
+    return static_cast<uint64_t>(total);
 }
 
 uint64_t count_members(ls_basis *b, uint64_t begin, uint64_t end, hipStream_t st) {

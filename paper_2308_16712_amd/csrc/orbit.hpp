@@ -131,44 +131,59 @@ __device__ __forceinline__ uint64_t rotr_n(uint64_t w, uint32_t k, uint32_t n, u
     return ((w >> k) | (w << (n - k))) & full;
 }
 
-// Smallest rotation of the n-bit ring word w (32 < n < 64), folded into
-// (best, arg).  A smaller word has more leading zeros, so the smallest
-// rotation puts one of w's longest (cyclic) runs of zeros on top: the runs
-// are found with doubling masks R_k (bit i set when zeros occupy i .. i+k-1)
-// and binary lifting of the run length, and only the rotations that lift one
-// of them to the top are compared in full.  Rotating left by k is the
-// translation with code code0 + k * nz.
-template <bool TRACK>
-__device__ __forceinline__ void ring64_fold(uint64_t w, uint32_t n, uint64_t full, uint32_t code0, uint32_t nz,
-                                            uint64_t &best, uint32_t &arg) {
+// Longest cyclic run of zeros of the n-bit ring word w (32 < n < 64): its
+// length L and the mask of the bits where such a run starts (runs go upward,
+// wrapping from bit n-1 to bit 0).  Doubling masks R_k (bit i set when zeros
+// occupy i .. i+k-1) and binary lifting of the length.  L = 0 when w has no
+// zero; L = n and start mask 1 when w is zero.
+__device__ __forceinline__ uint64_t ring64_runs(uint64_t w, uint32_t n, uint64_t full, uint32_t &L) {
     const uint64_t z = ~w & full;
-    if (z == 0 || z == full) {   // every rotation of all-ones / all-zeros is w
+    if (z == 0) {
+        L = 0;
+        return 0;
+    }
+    if (z == full) {
+        L = n;
+        return 1;
+    }
+    uint64_t R[6];               // runs of 1, 2, 4, 8, 16, 32 zeros (32 < n)
+    R[0] = z;
+#pragma unroll
+    for (uint32_t l = 1; l < 6; ++l) R[l] = R[l - 1] & rotr_n(R[l - 1], 1u << (l - 1), n, full);
+    uint64_t cur = z;
+    uint32_t len = 1;
+#pragma unroll
+    for (int l = 5; l >= 0; --l) {
+        const uint32_t k = 1u << l;
+        if (len + k < n) {
+            const uint64_t c = cur & rotr_n(R[l], len, n, full);
+            if (c) {
+                cur = c;
+                len += k;
+            }
+        }
+    }
+    L = len;
+    return cur;
+}
+
+// The smallest rotation of w puts one of its longest zero runs on top (a
+// smaller word has more leading zeros): compare the rotations that lift each
+// run start in `starts` (runs of length L) to bit n-1, folding into (best,
+// arg).  Rotating left by k is the translation with code code0 + k * nz.
+template <bool TRACK>
+__device__ __forceinline__ void ring64_eval(uint64_t w, uint64_t starts, uint32_t L, uint32_t n, uint64_t full,
+                                            uint32_t code0, uint32_t nz, uint64_t &best, uint32_t &arg) {
+    if (L == 0 || L >= n) {      // all ones / all zeros: every rotation is w
         if (w < best) {
             best = w;
             if constexpr (TRACK) arg = code0;
         }
         return;
     }
-    uint64_t R[6];               // runs of 1, 2, 4, 8, 16, 32 zeros (32 < n)
-    R[0] = z;
-#pragma unroll
-    for (uint32_t l = 1; l < 6; ++l) R[l] = R[l - 1] & rotr_n(R[l - 1], 1u << (l - 1), n, full);
-    uint64_t cur = z;            // starts of runs of at least L zeros
-    uint32_t L = 1;
-#pragma unroll
-    for (int l = 5; l >= 0; --l) {
-        const uint32_t k = 1u << l;
-        if (L + k < n) {
-            const uint64_t c = cur & rotr_n(R[l], L, n, full);
-            if (c) {
-                cur = c;
-                L += k;
-            }
-        }
-    }
-    while (cur) {
-        const uint32_t i = static_cast<uint32_t>(__builtin_ctzll(cur));
-        cur &= cur - 1;
+    while (starts) {
+        const uint32_t i = static_cast<uint32_t>(__builtin_ctzll(starts));
+        starts &= starts - 1;
         uint32_t top = i + L - 1;             // the run's highest bit
         if (top >= n) top -= n;
         const uint32_t k = n - 1 - top;       // rotate it to bit n-1
@@ -180,6 +195,14 @@ __device__ __forceinline__ void ring64_fold(uint64_t w, uint32_t n, uint64_t ful
     }
 }
 
+// Run starts of the reversed word: a run of L zeros starting at i in w
+// starts at n - L - i (mod n) in the bit reversal of w.
+__device__ __forceinline__ uint64_t ring64_mirror(uint64_t starts, uint32_t L, uint32_t n, uint64_t full) {
+    if (L == 0 || L >= n) return starts;
+    const uint64_t r = __builtin_bitreverse64(starts) >> (64u - n);   // i -> n-1-i
+    return rotr_n(r, L - 1, n, full);
+}
+
 // Orbit minimum; with TRACK also the code of the first element reaching it.
 template <typename W, int KIND, bool TRACK>
 __device__ __forceinline__ W orbit_min(const PlanDev &P, W s, uint32_t &code) {
@@ -189,12 +212,38 @@ __device__ __forceinline__ W orbit_min(const PlanDev &P, W s, uint32_t &code) {
         const uint64_t full = P.full;
         const uint32_t n = P.n_sites;
         const uint32_t nz = P.pair_flip ? 2u : 1u;
-        uint64_t b64 = static_cast<uint64_t>(s);   // s itself is the identity image (code 0)
-        for (uint32_t p0 = 0; p0 < P.n_cosets; ++p0) {
-            const uint32_t p = uni(p0);
-            const uint64_t u = static_cast<uint64_t>(apply_coset<W>(P.cosets[p], s, P));
-            ring64_fold<TRACK>(u, n, full, p * n * nz, nz, b64, arg);
-            if (P.pair_flip) ring64_fold<TRACK>(u ^ full, n, full, p * n * nz + 1, nz, b64, arg);
+        const uint64_t w = static_cast<uint64_t>(s);
+        uint64_t b64 = w;        // s itself is the identity image (code 0)
+        if (P.n_cosets == 2 && P.cosets[1].kind == kCosetReverse && P.cosets[1].flip == 0) {
+            // dihedral group (x spin flip): the reversed word's runs mirror
+            // w's, and with the flip only the longer of the zero and one runs
+            // can put the minimum's leading zeros on top
+            uint32_t Lz, Lo = 0;
+            const uint64_t sz = ring64_runs(w, n, full, Lz);
+            uint64_t so = 0;
+            if (P.pair_flip) so = ring64_runs(w ^ full, n, full, Lo);
+            const uint64_t rw = __builtin_bitreverse64(w) >> (64u - n);
+            if (Lz >= Lo) {
+                ring64_eval<TRACK>(w, sz, Lz, n, full, 0, nz, b64, arg);
+                ring64_eval<TRACK>(rw, ring64_mirror(sz, Lz, n, full), Lz, n, full, n * nz, nz, b64, arg);
+            }
+            if (P.pair_flip && Lo >= Lz) {
+                ring64_eval<TRACK>(w ^ full, so, Lo, n, full, 1, nz, b64, arg);
+                ring64_eval<TRACK>(rw ^ full, ring64_mirror(so, Lo, n, full), Lo, n, full, n * nz + 1, nz, b64,
+                                   arg);
+            }
+        } else {
+            for (uint32_t p0 = 0; p0 < P.n_cosets; ++p0) {
+                const uint32_t p = uni(p0);
+                const uint64_t u = static_cast<uint64_t>(apply_coset<W>(P.cosets[p], s, P));
+                uint32_t L;
+                uint64_t st = ring64_runs(u, n, full, L);
+                ring64_eval<TRACK>(u, st, L, n, full, p * n * nz, nz, b64, arg);
+                if (P.pair_flip) {
+                    st = ring64_runs(u ^ full, n, full, L);
+                    ring64_eval<TRACK>(u ^ full, st, L, n, full, p * n * nz + 1, nz, b64, arg);
+                }
+            }
         }
         best = static_cast<W>(b64);
     } else if constexpr (!TRACK && KIND == kOrbitRing32) {
