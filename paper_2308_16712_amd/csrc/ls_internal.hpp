@@ -25,7 +25,8 @@ struct Error {
     do {                                                                              \
         hipError_t e_ = (expr);                                                       \
         if (e_ != hipSuccess)                                                         \
-            throw ::ls::Error{LS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+            throw ::ls::Error{e_ == hipErrorOutOfMemory ? LS_ENOMEM : LS_EDEVICE,      \
+                              std::string(#expr) + ": " + hipGetErrorString(e_)};     \
     } while (0)
 
 #define LS_REQUIRE(cond, msg)                                                         \
