@@ -23,7 +23,9 @@ from typing import List, Optional
 
 import numpy as np
 
-from ._lib import Basis, Operator, Solver
+import threading
+
+from ._lib import Basis, LSError, Operator, Solver
 
 
 def _cycles(perm) -> List[int]:
@@ -127,7 +129,8 @@ class ServeStats:
     steps: int = 0
     max_active: int = 0
     peak_bytes: int = 0
-    build_s: float = 0.0      # basis + operator + solver set-up
+    build_s: float = 0.0      # basis + operator (+ element store) set-up
+    stored_bytes: int = 0     # matrix elements stored over the run
     step_s: float = 0.0       # Lanczos steps (or whole solves, one at a time)
 
     def summary(self) -> dict:
@@ -137,6 +140,7 @@ class ServeStats:
                     p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                     mean_ms=float(lat.mean()), steps=self.steps, max_active=self.max_active,
                     peak_bytes=self.peak_bytes, build_s=self.build_s, step_s=self.step_s,
+                    stored_bytes=self.stored_bytes,
                     converged=int(sum(r.converged for r in self.records)))
 
 
@@ -172,7 +176,7 @@ def _pick(live, policy: str):
 
 
 def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=None,
-          policy: str = "sjf") -> ServeStats:
+          policy: str = "sjf", store_elements: bool = False) -> ServeStats:
     """Continuous batching: admit by footprint, advance the admitted solves
     with fused steps (see _pick), retire converged ones.  Arrivals are
     replayed in real time.
@@ -180,7 +184,12 @@ def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=N
     Bases and operators of admitted requests are built by a worker thread on
     a stream of their own while the loop keeps stepping the live solves on
     another (the library releases the interpreter lock in every call); a
-    request joins the steps once its build has finished."""
+    request joins the steps once its build has finished.
+
+    With store_elements, the builder also stores the operator's matrix
+    elements (ls_operator_store) when they fit the budget left at that
+    moment; the solve then steps with stored products (results identical bit
+    for bit) and the stored bytes count against the budget until it retires."""
     import torch
     from concurrent.futures import FIRST_COMPLETED, ThreadPoolExecutor, wait
 
@@ -188,16 +197,29 @@ def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=N
     queue: List = []
     live: List[_Live] = []
     building = []           # (request, bytes, record, future)
-    used = 0
     stats = ServeStats()
     step_stream = torch.cuda.Stream()
     build_stream = torch.cuda.Stream()
+
+    lock = threading.Lock()
+    budget = {"used": 0}
 
     def build(req):
         t = time.perf_counter()
         b = Basis.from_sector(req.sector, build_stream)
         op = Operator(b, req.sector.terms)
-        return b, op, time.perf_counter() - t
+        stored = 0
+        if store_elements:
+            with lock:      # reserve what is left of the budget for the store
+                room = max(hbm_budget - budget["used"], 0)
+                budget["used"] += room
+            try:
+                stored = op.store(room, build_stream)
+            except LSError:
+                stored = 0
+            with lock:      # keep what the store holds, return the rest
+                budget["used"] -= room - stored
+        return b, op, stored, time.perf_counter() - t
 
     pool = ThreadPoolExecutor(max_workers=1)
     t0 = time.perf_counter()
@@ -214,24 +236,28 @@ def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=N
                     need = footprint_bytes(req.sector, max_iter)
                     if need > hbm_budget:
                         raise ValueError(f"request {req.rid} needs {need} bytes, more than the whole budget")
-                    if used + need > hbm_budget:
-                        continue
+                    with lock:
+                        if budget["used"] + need > hbm_budget:
+                            continue
+                        budget["used"] += need
+                        stats.peak_bytes = max(stats.peak_bytes, budget["used"])
                     queue.remove(req)
                     rec = Record(req.rid, req.sector.name, 0, req.arrival, admitted=time.perf_counter() - t0)
                     building.append((req, need, rec, pool.submit(build, req)))
-                    used += need
-                    stats.peak_bytes = max(stats.peak_bytes, used)
                 # finished builds join the live set
                 for item in list(building):
                     req, need, rec, fut = item
                     if not fut.done():
                         continue
                     building.remove(item)
-                    b, op, dt = fut.result()
+                    b, op, stored, dt = fut.result()
                     stats.build_s += dt
+                    stats.stored_bytes += stored
+                    with lock:
+                        stats.peak_bytes = max(stats.peak_bytes, budget["used"])
                     s = Solver(op, max_iter, tol=tol, seed=req.sector.seed)
                     rec.dim = b.dim
-                    live.append(_Live(rec, b, op, s, need))
+                    live.append(_Live(rec, b, op, s, need + stored))
                     if log:
                         log(f"[serve] t={time.perf_counter() - t0:.3f}s start {req.rid} {req.sector.name} "
                             f"dim={b.dim} active={len(live)}")
@@ -253,7 +279,8 @@ def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=N
                             lv.solver.close()
                             lv.op.close()
                             lv.basis.close()
-                            used -= lv.bytes
+                            with lock:
+                                budget["used"] -= lv.bytes
                         else:
                             keep.append(lv)
                     live = keep

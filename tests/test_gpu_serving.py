@@ -81,3 +81,16 @@ def test_serving_rejects_request_larger_than_budget():
     trace = _small_trace(count=2)
     with pytest.raises(ValueError):
         serve.serve(trace, hbm_budget=1 << 20, max_iter=50)
+
+
+def test_serve_with_stored_elements_matches_alone():
+    """Stored products are bit-identical to generated ones, so a trace served
+    with element storage returns the energies of the plain solves exactly."""
+    trace = configs.serving_trace(count=12, rate=50.0, seed=9)
+    trace = [r for r in trace if serve.sector_dimension(r.sector) < 2_000_000][:4]
+    assert len(trace) == 4
+    a = serve.serve(trace, 64 << 30, max_iter=80, tol=1e-9, store_elements=True)
+    b = serve.serve_one_at_a_time(trace, max_iter=80, tol=1e-9)
+    assert a.stored_bytes > 0
+    for x, y in zip(a.records, b.records):
+        assert x.e0 == y.e0 and x.iters == y.iters
