@@ -131,9 +131,36 @@ __global__ void __launch_bounds__(256) k_spmv(const uint64_t *off, const uint32_
 #pragma unroll
     for (int q = 0; q < NR; ++q) acc[q] = diag_times<CPLX>(dre, dim_, x[row * ld + col0 + q]);
     const uint64_t g = row / kSlice;
-    const uint32_t w = width[g];
+    const uint32_t w = width[g];      // the same for the whole wavefront
     const uint64_t base = off[g] + (row & (kSlice - 1));
-    for (uint32_t k = 0; k < w; ++k) {
+    // U elements per step: their columns, values and x gathers are all issued
+    // before the first add, so U gathers per lane are in flight at once; the
+    // adds keep the element order (same bits as the one-by-one loop).
+    constexpr int U = NR == 1 ? 4 : NR == 2 ? 2 : 1;
+    uint32_t k = 0;
+    for (; k + U <= w; k += U) {
+        uint32_t j[U];
+        T v[U], xv[U][NR];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t slot = base + static_cast<uint64_t>(k + u) * kSlice;
+            j[u] = cols[slot];
+            v[u] = vals[slot];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j[u] != kNoCol) {
+#pragma unroll
+                for (int q = 0; q < NR; ++q) xv[u][q] = x[static_cast<uint64_t>(j[u]) * ld + col0 + q];
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (j[u] != kNoCol) {
+#pragma unroll
+                for (int q = 0; q < NR; ++q) accumulate(acc[q], v[u], xv[u][q]);
+            }
+    }
+    for (; k < w; ++k) {
         const uint64_t slot = base + static_cast<uint64_t>(k) * kSlice;
         const uint32_t j = cols[slot];
         if (j == kNoCol) continue;
