@@ -17,7 +17,7 @@ namespace {
 // 12% faster on the 6x6 product than the compiler's 71-register choice).
 // Other variants would spill at 64 registers and keep the launch bound.
 constexpr int waves_per_simd(int kind, bool cplx, int nr, uint32_t lx) {
-    return (kind == kOrbitTorus && !cplx && nr == 1 && lx != 0) ? 8 : 1;
+    return ((kind == kOrbitTorus && !cplx && nr == 1 && lx != 0) || (kind == kOrbitRing64 && nr <= 2)) ? 8 : 1;
 }
 
 template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
