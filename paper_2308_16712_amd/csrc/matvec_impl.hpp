@@ -200,10 +200,128 @@ __device__ __forceinline__ W neighbour_rep(const MatvecJob &a, const LdsTables &
     }
 }
 
+// Rows as run_rows, for the searches that are cheap next to the memory
+// latency of the lookup (rings and the generic walk): the element loop is
+// software-pipelined one element deep.  An iteration searches element e+1 and
+// issues the load of its home hash slot, then finishes element e, whose slot
+// load was issued one search earlier.  Elements are still accumulated one by
+// one in term order, so the sums (and their bits) are those of run_rows.
+template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
+__device__ __forceinline__ void run_rows_ahead(const MatvecJob &a, const LdsTables &L, uint64_t row0,
+                                               uint64_t step, uint32_t count) {
+    constexpr bool TRACK = CHI != kChiTrivial;
+    using T = typename Val<CPLX>::T;
+    const T *x = static_cast<const T *>(a.x);
+    T *y = static_cast<T *>(a.y);
+    const ls_term_dev *sterm = L.terms;
+    const SearchDev &S = a.search;
+    const bool hash = S.mode == kLookupHash;
+
+    uint64_t row = row0;
+    uint32_t k = 0;
+    if (count == 0 || row >= a.dim) return;
+
+    uint64_t r = 0;
+    double st_i = 1.0;
+    T acc[NR];
+    uint32_t t = a.n_diag;
+    W pr[kTorusCosetSlots] = {};   // unused by these searches
+
+    auto begin_row = [&]() {
+        r = a.search.reps[row];
+        st_i = static_cast<double>(a.stab[row]);
+        double dre, dim_;
+        diag_sum<CPLX>(sterm, a.n_diag, r, dre, dim_);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) acc[q] = diag_times<CPLX>(dre, dim_, x[row * a.ld + a.col + q]);
+        t = a.n_diag;
+    };
+    begin_row();
+
+    // the element whose home-slot load is in flight
+    bool pend = false;
+    uint64_t p_rep = 0, p_slot = 0;
+    uint32_t p_code = 0, p_t = 0;
+    uint4 p_e = make_uint4(0u, 0u, 0u, 0u);
+
+    for (;;) {
+        while (t < a.n_terms && (r & sterm[t].sel) != sterm[t].val) ++t;
+        const bool more = t < a.n_terms;
+        // stage 1: search the next element, issue its home-slot load
+        uint64_t n_rep = 0, n_slot = 0;
+        uint32_t n_code = 0;
+        uint4 n_e = make_uint4(0u, 0u, 0u, 0u);
+        bool n_live = false;
+        if (more) {
+            n_rep = static_cast<uint64_t>(neighbour_rep<W, KIND, TRACK, LX, LY, NZ>(a, L, r, pr, t, n_code));
+            if (hash) {
+                n_live = n_rep >= S.kmin && n_rep <= S.kmax;   // outside: not in the basis
+                if (n_live) {
+                    n_slot = slot_of(n_rep, S.hash_shift);
+                    n_e = *reinterpret_cast<const uint4 *>(S.table + n_slot);
+                }
+            } else {
+                n_live = true;
+            }
+        }
+        // stage 2: finish the pending element of this row
+        if (pend) {
+            int64_t j;
+            uint32_t st_j = 0;
+            if (hash) {
+                uint64_t sl = p_slot;
+                uint4 e = p_e;
+                for (;;) {
+                    const uint64_t key = static_cast<uint64_t>(e.x) | (static_cast<uint64_t>(e.y) << 32);
+                    if (key == p_rep) {
+                        j = static_cast<int64_t>(e.z);
+                        st_j = e.w;
+                        break;
+                    }
+                    if (key == kEmptyKey) {
+                        j = -1;
+                        break;
+                    }
+                    sl = (sl + 1) & S.hash_mask;
+                    e = *reinterpret_cast<const uint4 *>(S.table + sl);
+                }
+            } else {
+                j = lookup_index_stab(S, p_rep, a.stab, st_j);
+            }
+            if (j >= 0) {
+                const T c = element_value<CHI, CPLX>(sterm[p_t], r, st_j, st_i, a.plan, p_code);
+#pragma unroll
+                for (int q = 0; q < NR; ++q) accumulate(acc[q], c, x[j * a.ld + a.col + q]);
+            }
+        }
+        if (!more) {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) y[row * a.ld + a.col + q] = acc[q];
+            ++k;
+            row += step;
+            if (k >= count || row >= a.dim) break;
+            begin_row();
+            pend = false;
+            continue;
+        }
+        pend = n_live;
+        p_rep = n_rep;
+        p_slot = n_slot;
+        p_code = n_code;
+        p_t = t;
+        p_e = n_e;
+        ++t;
+    }
+}
+
 // Rows row0, row0 + step, ... (count of them, below dim) of one job.
 template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
 __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L, uint64_t row0, uint64_t step,
                                          uint32_t count) {
+    if constexpr (KIND != kOrbitTorus) {
+        run_rows_ahead<W, KIND, CHI, CPLX, NR, LX, LY, NZ>(a, L, row0, step, count);
+        return;
+    }
     constexpr bool TRACK = CHI != kChiTrivial;
     using T = typename Val<CPLX>::T;
     const T *x = static_cast<const T *>(a.x);
