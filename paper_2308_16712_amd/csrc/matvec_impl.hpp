@@ -318,7 +318,9 @@ __device__ __forceinline__ void run_rows_ahead(const MatvecJob &a, const LdsTabl
 template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
 __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L, uint64_t row0, uint64_t step,
                                          uint32_t count) {
-    if constexpr (KIND != kOrbitTorus) {
+    // the pipelined loop pays off where one or two columns leave registers
+    // for the element in flight; wider products keep the plain loop
+    if constexpr (KIND != kOrbitTorus && NR <= 2) {
         run_rows_ahead<W, KIND, CHI, CPLX, NR, LX, LY, NZ>(a, L, row0, step, count);
         return;
     }
