@@ -235,9 +235,11 @@ ls_status ls_matvec_push(const ls_operator *op, uint32_t nrhs, const void *d_x, 
  * the launch sequence is captured in a HIP graph and replayed.
  * On the first ls_batch_matvec the library tunes, per variant, the tile size
  * and grid size (timing candidates on the caller's buffers; y is written
- * during tuning) and, per basis, the bucket bits of a batch-owned search
- * layout; the choices are cached per process.  The batch borrows the
- * operators, which must outlive it.                                         */
+ * during tuning) and, for a basis that uses the bucket search layout, the
+ * bucket bits of a batch-owned copy of it (hash layouts are used as built);
+ * the choices are cached per process.  Elements are always generated (a
+ * stored form is not used); results equal ls_matvec's bit for bit.  The
+ * batch borrows the operators, which must outlive it.                       */
 typedef struct ls_batch ls_batch;
 
 /*   ops   host array of n operator handles (may repeat);
@@ -295,10 +297,11 @@ ls_status ls_lanczos(const ls_operator *op, const ls_lanczos_opts *opts, void *s
  * A solver holds one Lanczos solve (the recurrence, start vector, stop rule
  * and arithmetic of ls_lanczos) with its Krylov vectors resident in HBM.
  * ls_solver_step advances every listed solver that is not done by one
- * iteration: the products of all of them run as one fused launch (the
- * batched kernel), alpha and beta stay on the device, and the step ends with
- * one synchronisation.  A solve stepped alone or among others produces the
- * same numbers.  Calls to ls_solver_step are serialised inside the library. */
+ * iteration: the products of several solves run as one fused launch (the
+ * batched kernel; a single solve takes ls_matvec's launch, or its stored
+ * elements), alpha and beta stay on the device, and the step ends with one
+ * synchronisation.  A solve stepped alone or among others produces the same
+ * numbers.  Calls to ls_solver_step are serialised inside the library.     */
 typedef struct ls_solver ls_solver;
 
 /* Device bytes a solver for `op` with `max_iter` steps allocates.          */
