@@ -27,8 +27,9 @@
  * device) owned by the caller; work is enqueued on `stream` (a hipStream_t
  * passed as void*; NULL = the default stream) and is complete when the
  * stream is.  Descriptors and term tables are host memory, read during the
- * call only.  Handles are owned by the library, immutable after creation,
- * and freed with the matching *_destroy.  Calls on different streams may
+ * call only.  Handles are owned by the library, immutable after creation
+ * (ls_operator_store excepted: it adds the stored form to an operator), and
+ * freed with the matching *_destroy.  Calls on different streams may
  * overlap; a handle may be shared by concurrent calls.
  *
  * Errors: every call returns ls_status.  No exception crosses this boundary.
@@ -103,7 +104,9 @@ typedef struct {
  * environment variable LS_ED_SEARCH is "buckets" at build time, a bucket
  * table over the keys' high bits with binary search in reps.  A group of
  * one element needs neither (colex rank, or the state itself).
- * Blocks until the build on `stream` has finished.
+ * Blocks until the build on `stream` has finished.  Indices are 32-bit:
+ * sectors of 2^32 - 1 or more representatives are refused (count them with
+ * ls_sector_count).
  * Errors: LS_EINVAL (invalid descriptor: see ls_sector_desc), LS_ENOMEM,
  * LS_EDEVICE, LS_EINTERNAL (a group-compiler self-check failed).          */
 ls_status ls_basis_build(const ls_sector_desc *desc, void *stream, ls_basis **out);
