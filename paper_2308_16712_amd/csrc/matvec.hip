@@ -112,7 +112,7 @@ uint64_t count_elements(const ls_operator *op, hipStream_t st) {
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    hipFree(d);
+    (void)hipFree(d);
     LS_HIP_CHECK(e);
     return h;
 }

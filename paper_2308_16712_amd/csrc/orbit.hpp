@@ -312,8 +312,10 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, cons
         if (ty >= 1) return static_cast<uint32_t>(u >> (L * (ty - 1))) & m2;
         return ((static_cast<uint32_t>(u) & rm) << L) | (static_cast<uint32_t>(u >> (L * (Ly - 1))) & rm);
     };
-    // pass 1a: the smallest key (entries compare by key first)
-    uint32_t best = 0xFFFFu;
+    // pass 1a: the smallest key (entries compare by key first); both 16-bit
+    // entries of a table word are folded at once with one packed minimum
+    using u16x2 = unsigned short __attribute__((ext_vector_type(2)));
+    u16x2 bestv = {0xFFFFu, 0xFFFFu};
 #pragma unroll
     for (uint32_t p = 0; p < kTorusMaxCosets; ++p) {
         if (p >= ncos) break;
@@ -322,11 +324,12 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, cons
             for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
                 const uint32_t b = LY ? b0 : uni(b1);
                 const uint32_t e = lut[pair_of(us[p], b)];
-                best = min(best, e & 0xFFFFu);
-                if (nz == 2) best = min(best, e >> 16);
+                bestv = __builtin_elementwise_min(bestv, __builtin_bit_cast(u16x2, e));
             }
         }
     }
+    uint32_t best = bestv.x;
+    if (nz == 2) best = min(best, static_cast<uint32_t>(bestv.y));
     best >>= 4;
     // pass 1b: which (p, b, f) reach it (bit (p*ly + b)*nz + f)
     uint64_t M0 = 0, M1 = 0;
