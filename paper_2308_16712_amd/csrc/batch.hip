@@ -87,10 +87,8 @@ __global__ void k_buckets_tuned(const uint64_t *reps, uint64_t d, uint64_t kmin,
 // (128 VGPRs at most) the wider torus variants would spill to scratch; the
 // cap keeps every instantiated variant in registers.  Columns are computed
 // independently, so the cap changes no result bit.
-constexpr int nr_cap(bool word64, int kind, int chi) {
-    return kind != kOrbitTorus ? 8 : (word64 && chi == kChiComplex) ? 1 : 2;
-}
-int batch_nr_cap(const Variant &v) { return nr_cap(v.word64 != 0, v.kind, v.chi); }
+constexpr int nr_cap(bool word64, int kind) { return kind != kOrbitTorus ? 8 : word64 ? 1 : 2; }
+int batch_nr_cap(const Variant &v) { return nr_cap(v.word64 != 0, v.kind); }
 
 // Lookup sweep used to time a search layout: keys are representatives taken
 // in a scattered order; the sum of indices defeats dead-code elimination.
@@ -126,7 +124,7 @@ struct BatchLaunch {
     template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
     void run() {
         // variants above the cap are never grouped (batch_nr_cap) and never built
-        if constexpr (NR > nr_cap(sizeof(W) == 8, KIND, CHI)) {
+        if constexpr (NR > nr_cap(sizeof(W) == 8, KIND)) {
             throw Error{LS_EINTERNAL, "batched job wider than its variant's cap"};
         } else {
             constexpr int BLOCK = batch_block(KIND, CPLX);

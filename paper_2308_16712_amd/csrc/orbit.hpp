@@ -331,58 +331,124 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, cons
     uint32_t best = bestv.x;
     if (nz == 2) best = min(best, static_cast<uint32_t>(bestv.y));
     best >>= 4;
-    // pass 1b: which (p, b, f) reach it (bit (p*ly + b)*nz + f)
-    uint64_t M0 = 0, M1 = 0;
-#pragma unroll
-    for (uint32_t p = 0; p < kTorusMaxCosets; ++p) {
-        if (p >= ncos) break;
-#pragma unroll
-        for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
-            for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
-                const uint32_t b = LY ? b0 : uni(b1);
-                const uint32_t e = lut[pair_of(us[p], b)];
-                const uint32_t idx = LY ? (p * Ly + b) * nz : uni((p * Ly + b) * nz);
-                const uint64_t hit = (((e >> 4) & 0xFFFu) == best ? 1ull : 0ull) |
-                                     ((nz == 2 && (e >> 20) == best) ? 2ull : 0ull);
-                if (idx < 63) M0 |= hit << idx;
-                else if (idx == 63) { M0 |= hit << 63; M1 |= hit >> 1; }
-                else M1 |= hit << (idx - 64);
-            }
-        }
-    }
     W rmin = static_cast<W>(~static_cast<W>(0));
     uint32_t arg = 0;
-    while (M0 | M1) {
-        uint32_t idx;
-        if (M0) {
-            idx = static_cast<uint32_t>(__builtin_ctzll(M0));
-            M0 &= M0 - 1;
-        } else {
-            idx = 64u + static_cast<uint32_t>(__builtin_ctzll(M1));
-            M1 &= M1 - 1;
+    if constexpr (!TRACK) {
+        // one mask bit per (coset, y-shift): fewer instructions; the kernels
+        // that also track g* do not have the registers for it and keep one
+        // bit per (coset, y-shift, flip)
+        // pass 1b: which (p, b) reach it with either entry (bit p*ly + b); the
+        // key fields of both entries are compared at once against the pattern
+        const uint32_t pat = (best << 4) | (best << 20);
+        const uint32_t keys = nz == 2 ? 0xFFF0FFF0u : 0x0000FFF0u;
+        uint64_t M0 = 0, M1 = 0;
+    #pragma unroll
+        for (uint32_t p = 0; p < kTorusMaxCosets; ++p) {
+            if (p >= ncos) break;
+    #pragma unroll
+            for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
+                for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
+                    const uint32_t b = LY ? b0 : uni(b1);
+                    const uint32_t d = (lut[pair_of(us[p], b)] ^ pat) & keys;
+                    const uint64_t hit = ((d & 0xFFFFu) == 0 || (nz == 2 && (d >> 16) == 0)) ? 1ull : 0ull;
+                    const uint32_t idx = LY ? p * Ly + b : uni(p * Ly + b);
+                    if (idx < 64) M0 |= hit << idx;
+                    else M1 |= hit << (idx - 64);
+                }
+            }
         }
-        const uint32_t f = idx % nz, pb = idx / nz;
-        const uint32_t b = pb % Ly, p = pb / Ly;
-        W v = us[0];
+        // pass 2: full evaluation of the images those (p, b) give
+        while (M0 | M1) {
+            uint32_t idx;
+            if (M0) {
+                idx = static_cast<uint32_t>(__builtin_ctzll(M0));
+                M0 &= M0 - 1;
+            } else {
+                idx = 64u + static_cast<uint32_t>(__builtin_ctzll(M1));
+                M1 &= M1 - 1;
+            }
+            const uint32_t b = idx % Ly, p = idx / Ly;
+            W v0 = us[0];
+    #pragma unroll
+            for (uint32_t q = 1; q < kTorusMaxCosets; ++q) v0 = (q < ncos && p == q) ? us[q] : v0;
+            if (b) v0 = ((v0 << (L * b)) | (v0 >> (P.n_sites - L * b))) & full;
+            // low entry: v0's top two rows; high entry: those of v0 ^ full
+            const uint32_t e2 = lut[static_cast<uint32_t>(v0 >> (L * (Ly - 2))) & m2];
 #pragma unroll
-        for (uint32_t q = 1; q < kTorusMaxCosets; ++q) v = (q < ncos && p == q) ? us[q] : v;
-        if (b) v = ((v << (L * b)) | (v >> (P.n_sites - L * b))) & full;
-        if (f) v ^= full;
-        const uint32_t e = lut[static_cast<uint32_t>(v >> (L * (Ly - 2))) & m2] & 0xFFFFu;
-        const uint32_t base = (p * P.n_trans + L * b) * nz + f;
-        if (e & 8u) {
-            for (uint32_t a = 0; a < L; ++a) {
-                if (v < rmin) { rmin = v; arg = base + a * nz; }
-                if (a + 1 < L) v = xrot<W>(v, P);
+            for (uint32_t f = 0; f < 2; ++f) {
+                if (f >= nz) break;
+                const uint32_t e = f ? (e2 >> 16) : (e2 & 0xFFFFu);
+                if ((e >> 4) != best) continue;
+                W v = f ? static_cast<W>(v0 ^ full) : v0;
+                const uint32_t base = (p * P.n_trans + L * b) * nz + f;
+                if (e & 8u) {
+                    for (uint32_t a = 0; a < L; ++a) {
+                        if (v < rmin) { rmin = v; arg = base + a * nz; }
+                        if (a + 1 < L) v = xrot<W>(v, P);
+                    }
+                } else {
+                    const uint32_t a = e & 7u;
+                    W c = v;
+                    if (a) {
+                        const W ma = static_cast<W>(lcol[a]);
+                        c = ((v << a) & ma) | ((v >> (L - a)) & ~ma & full);
+                    }
+                    if (c < rmin) { rmin = c; arg = base + a * nz; }
+                }
             }
-        } else {
-            const uint32_t a = e & 7u;
-            W c = v;
-            if (a) {
-                const W ma = static_cast<W>(lcol[a]);
-                c = ((v << a) & ma) | ((v >> (L - a)) & ~ma & full);
+        }
+    } else {
+        // pass 1b: which (p, b, f) reach it (bit (p*ly + b)*nz + f)
+        uint64_t M0 = 0, M1 = 0;
+    #pragma unroll
+        for (uint32_t p = 0; p < kTorusMaxCosets; ++p) {
+            if (p >= ncos) break;
+    #pragma unroll
+            for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
+                for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
+                    const uint32_t b = LY ? b0 : uni(b1);
+                    const uint32_t e = lut[pair_of(us[p], b)];
+                    const uint32_t idx = LY ? (p * Ly + b) * nz : uni((p * Ly + b) * nz);
+                    const uint64_t hit = (((e >> 4) & 0xFFFu) == best ? 1ull : 0ull) |
+                                         ((nz == 2 && (e >> 20) == best) ? 2ull : 0ull);
+                    if (idx < 63) M0 |= hit << idx;
+                    else if (idx == 63) { M0 |= hit << 63; M1 |= hit >> 1; }
+                    else M1 |= hit << (idx - 64);
+                }
             }
-            if (c < rmin) { rmin = c; arg = base + a * nz; }
+        }
+        while (M0 | M1) {
+            uint32_t idx;
+            if (M0) {
+                idx = static_cast<uint32_t>(__builtin_ctzll(M0));
+                M0 &= M0 - 1;
+            } else {
+                idx = 64u + static_cast<uint32_t>(__builtin_ctzll(M1));
+                M1 &= M1 - 1;
+            }
+            const uint32_t f = idx % nz, pb = idx / nz;
+            const uint32_t b = pb % Ly, p = pb / Ly;
+            W v = us[0];
+    #pragma unroll
+            for (uint32_t q = 1; q < kTorusMaxCosets; ++q) v = (q < ncos && p == q) ? us[q] : v;
+            if (b) v = ((v << (L * b)) | (v >> (P.n_sites - L * b))) & full;
+            if (f) v ^= full;
+            const uint32_t e = lut[static_cast<uint32_t>(v >> (L * (Ly - 2))) & m2] & 0xFFFFu;
+            const uint32_t base = (p * P.n_trans + L * b) * nz + f;
+            if (e & 8u) {
+                for (uint32_t a = 0; a < L; ++a) {
+                    if (v < rmin) { rmin = v; arg = base + a * nz; }
+                    if (a + 1 < L) v = xrot<W>(v, P);
+                }
+            } else {
+                const uint32_t a = e & 7u;
+                W c = v;
+                if (a) {
+                    const W ma = static_cast<W>(lcol[a]);
+                    c = ((v << a) & ma) | ((v >> (L - a)) & ~ma & full);
+                }
+                if (c < rmin) { rmin = c; arg = base + a * nz; }
+            }
         }
     }
     if constexpr (TRACK) code = arg;
