@@ -10,8 +10,9 @@
 //
 // An autotuner picks, per variant group, the rows per lane of a tile and the
 // number of resident workgroups by timing the candidates on first use, and,
-// per basis, the number of bucket bits of the search layout by timing a
-// lookup sweep (the batch owns these tables; the basis is not modified).
+// per basis that uses the bucket search layout (hash layouts are used as
+// built), the number of bucket bits by timing a lookup sweep (the batch owns
+// these tables; the basis is not modified).
 // Results are cached per process.
 
 #include <algorithm>
