@@ -215,6 +215,50 @@ def push_product(op, x, pull_ms: float, elements: int, steps: int):
             "rel_l2_vs_pull": rel, "form": "transposed: y_j += conj(H_ij) x_i with FP64 atomic adds"}
 
 
+def lanczos_leg(steps: int = 100):
+    """Heisenberg ring N=32 (Sz=0, k=0, R=+1, Z=+1; 4,707,969 states): a
+    100-step Lanczos solve (full CGS2, tol 0), with generated and with stored
+    elements; time per step and the share spent in the products."""
+    import torch
+    import paper_2308_16712_amd as ls
+    from workloads import configs
+
+    sec = configs.ring32_symmetric()
+    b = ls.ls_basis_build(sec)
+    out = {"workload": "Heisenberg ring N=32, Sz=0, k=0, R=+1, Z=+1 (128)", "dim": b.dim, "steps": steps}
+    for form in ("generated", "stored"):
+        op = ls.ls_operator_create(b, sec.terms)
+        if form == "stored":
+            op.store()
+        x = torch.empty(b.dim, dtype=torch.float64, device="cuda").uniform_(-1, 1)
+        y = torch.empty_like(x)
+        ls.ls_matvec(op, x, y)
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(10):
+            ls.ls_matvec(op, x, y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        product_ms = e0.elapsed_time(e1) / 10
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = op.lanczos(steps, tol=0.0, seed=1)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[form] = {"e0": r["e0"], "iters": r["iters"], "s": wall, "ms_per_step": wall * 1e3 / r["iters"],
+                     "product_ms": product_ms, "product_share": product_ms * r["iters"] / (wall * 1e3)}
+        print(f"[bench] lanczos ring32 {form}: {wall:.2f}s, e0={r['e0']:.12f}", file=sys.stderr, flush=True)
+        op.close()
+        del x, y
+    out["e0_identical"] = out["generated"]["e0"] == out["stored"]["e0"]
+    b.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def stored_product(basis, sector, x, y, fly_ms: float, elements: int, steps: int):
     """The same product from stored elements (ls_operator_store): store time
     and size, product time on the launch stream, and bit-identity with the
@@ -393,6 +437,7 @@ def main():
     ap.add_argument("--no-enumeration", action="store_true", help="skip the Table 2 enumeration leg")
     ap.add_argument("--no-stored", action="store_true", help="skip the stored-elements product")
     ap.add_argument("--no-push", action="store_true", help="skip the push (atomic) product")
+    ap.add_argument("--no-lanczos", action="store_true", help="skip the 100-step Lanczos leg (ring N=32)")
     ap.add_argument("--chains", default="40,42", help="paper-workload chain sizes to time (empty: none)")
     ap.add_argument("--enum-counts", default="40,42", help="chain sizes counted without storage")
     ap.add_argument("--enum-build", type=int, default=40, help="chain size built and stored (0: none)")
@@ -493,6 +538,9 @@ def main():
         print("[bench] batched vs plain", file=sys.stderr, flush=True)
         out["batched"] = batched_vs_plain(args.batched_count, args.batched_nrhs)
         torch.cuda.empty_cache()
+    if not args.no_lanczos:
+        print("[bench] lanczos", file=sys.stderr, flush=True)
+        out["lanczos"] = lanczos_leg()
     chain_ns = [int(v) for v in args.chains.split(",") if v]
     if chain_ns:
         print("[bench] paper-workload chains", file=sys.stderr, flush=True)

@@ -24,7 +24,7 @@ namespace ls {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kDotBlocks = 1024;
+constexpr int kDotBlocks = 2048;   // 8 workgroups per CU: enough loads in flight to stream V
 constexpr int kTile = 8;    // Krylov vectors per pass of the multi-dot
 
 template <bool CPLX>

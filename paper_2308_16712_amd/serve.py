@@ -93,7 +93,7 @@ def footprint_bytes(sector, max_iter: int) -> int:
     es = 16 if complex_ else 8
     m = min(max_iter, max(dim, 1))
     cand = comb(sector.n_sites, sector.weight) if sector.weight >= 0 else 2 ** sector.n_sites
-    return dim * 10 + _search_bytes(dim) + (m + 1) * dim * es + 1024 * m * 16 + cand // 8 + (64 << 20)
+    return dim * 10 + _search_bytes(dim) + (m + 1) * dim * es + 2048 * m * 16 + cand // 8 + (64 << 20)
 
 
 @dataclass
