@@ -312,49 +312,66 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, cons
         if (ty >= 1) return static_cast<uint32_t>(u >> (L * (ty - 1))) & m2;
         return ((static_cast<uint32_t>(u) & rm) << L) | (static_cast<uint32_t>(u >> (L * (Ly - 1))) & rm);
     };
-    // pass 1a: the smallest key (entries compare by key first); both 16-bit
-    // entries of a table word are folded at once with one packed minimum
     using u16x2 = unsigned short __attribute__((ext_vector_type(2)));
-    u16x2 bestv = {0xFFFFu, 0xFFFFu};
-#pragma unroll
-    for (uint32_t p = 0; p < kTorusMaxCosets; ++p) {
-        if (p >= ncos) break;
-#pragma unroll
-        for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
-            for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
-                const uint32_t b = LY ? b0 : uni(b1);
-                const uint32_t e = lut[pair_of(us[p], b)];
-                bestv = __builtin_elementwise_min(bestv, __builtin_bit_cast(u16x2, e));
-            }
-        }
-    }
-    uint32_t best = bestv.x;
-    if (nz == 2) best = min(best, static_cast<uint32_t>(bestv.y));
-    best >>= 4;
     W rmin = static_cast<W>(~static_cast<W>(0));
     uint32_t arg = 0;
     if constexpr (!TRACK) {
-        // one mask bit per (coset, y-shift): fewer instructions; the kernels
-        // that also track g* do not have the registers for it and keep one
-        // bit per (coset, y-shift, flip)
-        // pass 1b: which (p, b) reach it with either entry (bit p*ly + b); the
-        // key fields of both entries are compared at once against the pattern
-        const uint32_t pat = (best << 4) | (best << 20);
-        const uint32_t keys = nz == 2 ? 0xFFF0FFF0u : 0x0000FFF0u;
-        uint64_t M0 = 0, M1 = 0;
-    #pragma unroll
+        // one mask bit per (coset, y-shift), and only the cosets that reach
+        // the smallest key are scanned twice; the kernels that also track g*
+        // do not have the registers for it and keep one bit per (coset,
+        // y-shift, flip) over every coset
+        // pass 1a: the smallest entry of every coset (both flip entries of a
+        // table word folded with one packed minimum), then the smallest key
+        uint32_t cmin[kTorusMaxCosets];
+        uint32_t ball = 0xFFFFu;
+#pragma unroll
         for (uint32_t p = 0; p < kTorusMaxCosets; ++p) {
-            if (p >= ncos) break;
-    #pragma unroll
+            cmin[p] = 0xFFFFu;
+            if (p >= ncos) continue;
+            u16x2 m = {0xFFFFu, 0xFFFFu};
+#pragma unroll
             for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
                 for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
                     const uint32_t b = LY ? b0 : uni(b1);
-                    const uint32_t d = (lut[pair_of(us[p], b)] ^ pat) & keys;
-                    const uint64_t hit = ((d & 0xFFFFu) == 0 || (nz == 2 && (d >> 16) == 0)) ? 1ull : 0ull;
-                    const uint32_t idx = LY ? p * Ly + b : uni(p * Ly + b);
-                    if (idx < 64) M0 |= hit << idx;
-                    else M1 |= hit << (idx - 64);
+                    m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, lut[pair_of(us[p], b)]));
                 }
+            }
+            cmin[p] = nz == 2 ? min(static_cast<uint32_t>(m.x), static_cast<uint32_t>(m.y))
+                              : static_cast<uint32_t>(m.x);
+            ball = min(ball, cmin[p]);
+        }
+        const uint32_t best = ball >> 4;
+        // the cosets that reach the smallest key
+        uint32_t cm = 0;
+#pragma unroll
+        for (uint32_t p = 0; p < kTorusMaxCosets; ++p) cm |= ((cmin[p] >> 4) == best ? 1u : 0u) << p;
+        // pass 1b: in those cosets only (a loop per lane), the y-shifts that
+        // reach it with either entry (bit p*ly + b); the key fields of both
+        // entries are compared at once against the pattern
+        const uint32_t pat = (best << 4) | (best << 20);
+        const uint32_t keys = nz == 2 ? 0xFFF0FFF0u : 0x0000FFF0u;
+        uint64_t M0 = 0, M1 = 0;
+        while (cm) {
+            const uint32_t p = static_cast<uint32_t>(__builtin_ctz(cm));
+            cm &= cm - 1;
+            W u = us[0];
+#pragma unroll
+            for (uint32_t q = 1; q < kTorusMaxCosets; ++q) u = (q < ncos && p == q) ? us[q] : u;
+            uint64_t mb = 0;
+#pragma unroll
+            for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
+                for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
+                    const uint32_t b = LY ? b0 : uni(b1);
+                    const uint32_t d = (lut[pair_of(u, b)] ^ pat) & keys;
+                    mb |= ((d & 0xFFFFu) == 0 || (nz == 2 && (d >> 16) == 0)) ? (1ull << b) : 0ull;
+                }
+            }
+            const uint32_t i0 = p * Ly;
+            if (i0 < 64) {
+                M0 |= mb << i0;
+                if (i0 + Ly > 64) M1 |= mb >> (64 - i0);
+            } else {
+                M1 |= mb << (i0 - 64);
             }
         }
         // pass 2: full evaluation of the images those (p, b) give
@@ -398,6 +415,24 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, cons
             }
         }
     } else {
+        // pass 1a: the smallest key (entries compare by key first); both 16-bit
+        // entries of a table word are folded at once with one packed minimum
+        u16x2 bestv = {0xFFFFu, 0xFFFFu};
+#pragma unroll
+        for (uint32_t p = 0; p < kTorusMaxCosets; ++p) {
+            if (p >= ncos) break;
+#pragma unroll
+            for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
+                for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
+                    const uint32_t b = LY ? b0 : uni(b1);
+                    const uint32_t e = lut[pair_of(us[p], b)];
+                    bestv = __builtin_elementwise_min(bestv, __builtin_bit_cast(u16x2, e));
+                }
+            }
+        }
+        uint32_t best = bestv.x;
+        if (nz == 2) best = min(best, static_cast<uint32_t>(bestv.y));
+        best >>= 4;
         // pass 1b: which (p, b, f) reach it (bit (p*ly + b)*nz + f)
         uint64_t M0 = 0, M1 = 0;
     #pragma unroll
