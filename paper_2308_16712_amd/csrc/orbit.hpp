@@ -319,7 +319,7 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, cons
         // one mask bit per (coset, y-shift), and only the cosets that reach
         // the smallest key are scanned twice; the kernels that also track g*
         // do not have the registers for it and keep one bit per (coset,
-        // y-shift, flip) over every coset
+        // y-shift, flip)
         // pass 1a: the smallest entry of every coset (both flip entries of a
         // table word folded with one packed minimum), then the smallest key
         uint32_t cmin[kTorusMaxCosets];
@@ -415,35 +415,44 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, cons
             }
         }
     } else {
-        // pass 1a: the smallest key (entries compare by key first); both 16-bit
-        // entries of a table word are folded at once with one packed minimum
-        u16x2 bestv = {0xFFFFu, 0xFFFFu};
+        // pass 1a: the smallest entry of every coset, then the smallest key
+        uint32_t cmin[kTorusMaxCosets];
+        uint32_t ball = 0xFFFFu;
 #pragma unroll
         for (uint32_t p = 0; p < kTorusMaxCosets; ++p) {
-            if (p >= ncos) break;
+            cmin[p] = 0xFFFFu;
+            if (p >= ncos) continue;
+            u16x2 m = {0xFFFFu, 0xFFFFu};
 #pragma unroll
             for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
                 for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
                     const uint32_t b = LY ? b0 : uni(b1);
-                    const uint32_t e = lut[pair_of(us[p], b)];
-                    bestv = __builtin_elementwise_min(bestv, __builtin_bit_cast(u16x2, e));
+                    m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, lut[pair_of(us[p], b)]));
                 }
             }
+            cmin[p] = nz == 2 ? min(static_cast<uint32_t>(m.x), static_cast<uint32_t>(m.y))
+                              : static_cast<uint32_t>(m.x);
+            ball = min(ball, cmin[p]);
         }
-        uint32_t best = bestv.x;
-        if (nz == 2) best = min(best, static_cast<uint32_t>(bestv.y));
-        best >>= 4;
-        // pass 1b: which (p, b, f) reach it (bit (p*ly + b)*nz + f)
+        const uint32_t best = ball >> 4;
+        uint32_t cm = 0;
+#pragma unroll
+        for (uint32_t p = 0; p < kTorusMaxCosets; ++p) cm |= ((cmin[p] >> 4) == best ? 1u : 0u) << p;
+        // pass 1b: in those cosets only, which (p, b, f) reach it
+        // (bit (p*ly + b)*nz + f)
         uint64_t M0 = 0, M1 = 0;
-    #pragma unroll
-        for (uint32_t p = 0; p < kTorusMaxCosets; ++p) {
-            if (p >= ncos) break;
-    #pragma unroll
+        while (cm) {
+            const uint32_t p = static_cast<uint32_t>(__builtin_ctz(cm));
+            cm &= cm - 1;
+            W u = us[0];
+#pragma unroll
+            for (uint32_t q = 1; q < kTorusMaxCosets; ++q) u = (q < ncos && p == q) ? us[q] : u;
+#pragma unroll
             for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
                 for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
                     const uint32_t b = LY ? b0 : uni(b1);
-                    const uint32_t e = lut[pair_of(us[p], b)];
-                    const uint32_t idx = LY ? (p * Ly + b) * nz : uni((p * Ly + b) * nz);
+                    const uint32_t e = lut[pair_of(u, b)];
+                    const uint32_t idx = (p * Ly + b) * nz;
                     const uint64_t hit = (((e >> 4) & 0xFFFu) == best ? 1ull : 0ull) |
                                          ((nz == 2 && (e >> 20) == best) ? 2ull : 0ull);
                     if (idx < 63) M0 |= hit << idx;
