@@ -189,11 +189,7 @@ __device__ __forceinline__ W neighbour_rep(const MatvecJob &a, const LdsTables &
     if constexpr (KIND == kOrbitTorus) {
         const uint32_t n_off = a.n_terms - a.n_diag;
         const uint32_t ko = t - a.n_diag;
-        W us[kTorusCosetSlots];
-#pragma unroll
-        for (uint32_t p = 0; p < kTorusCosetSlots; ++p)
-            us[p] = p < a.plan.n_cosets ? (pr[p] ^ static_cast<W>(L.cflip[p * n_off + ko])) : W(0);
-        return torus_orbit_min<W, TRACK, LX, LY, NZ>(a.plan, us, L.lut, L.col, code);
+        return torus_orbit_min<W, TRACK, LX, LY, NZ>(a.plan, pr, L.cflip + ko, n_off, L.lut, L.col, code);
     } else {
         (void)pr;
         return orbit_min<W, KIND, TRACK>(a.plan, static_cast<W>(r ^ L.terms[t].flip), code);

@@ -283,7 +283,8 @@ __device__ __forceinline__ W orbit_min(const PlanDev &P, W s, uint32_t &code) {
 
 // Pruned orbit minimum on an lx-by-ly torus (lx <= 6, ly >= 2).
 //
-// The images p(s) of the coset representatives come in precomputed (us[]).
+// The images p(s) = p(r) ^ pi_p(f) of the coset representatives are formed
+// from the row's images p(r) (pr[]) and the flip images pi_p(f) (cf[p * cstride]).
 // Pass 1a walks every coset p and y-shift b: the top two rows of
 // tau_{0,b}(p(s)) index the pair table, whose entry holds, for the pair and
 // for its spin-flipped partner, the smallest value the two rows take over
@@ -299,8 +300,8 @@ __device__ __forceinline__ W orbit_min(const PlanDev &P, W s, uint32_t &code) {
 constexpr uint32_t kTorusMaxCosets = kTorusCosetSlots;
 
 template <typename W, bool TRACK, uint32_t LX, uint32_t LY, uint32_t NZ>
-__device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, const uint32_t *lut,
-                                             const uint64_t *lcol, uint32_t &code) {
+__device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *pr, const uint64_t *cf, uint32_t cstride,
+                                             const uint32_t *lut, const uint64_t *lcol, uint32_t &code) {
     const uint32_t L = LX ? LX : P.lx, Ly = LY ? LY : P.ly;
     const uint32_t nz = NZ ? NZ : (P.pair_flip ? 2u : 1u);
     const uint32_t rm = (1u << L) - 1u, m2 = (1u << (2 * L)) - 1u;
@@ -312,6 +313,9 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, cons
         if (ty >= 1) return static_cast<uint32_t>(u >> (L * (ty - 1))) & m2;
         return ((static_cast<uint32_t>(u) & rm) << L) | (static_cast<uint32_t>(u >> (L * (Ly - 1))) & rm);
     };
+    // image p(s) = p(r) ^ pi_p(f) of coset p: fixed p (unrolled loops), or a
+    // p that differs between lanes
+#define LS_IMG(p) (pr[p] ^ static_cast<W>(cf[(p) * cstride]))
     using u16x2 = unsigned short __attribute__((ext_vector_type(2)));
     W rmin = static_cast<W>(~static_cast<W>(0));
     uint32_t arg = 0;
@@ -333,7 +337,7 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, cons
             for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
                 for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
                     const uint32_t b = LY ? b0 : uni(b1);
-                    m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, lut[pair_of(us[p], b)]));
+                    m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, lut[pair_of(LS_IMG(p), b)]));
                 }
             }
             cmin[p] = nz == 2 ? min(static_cast<uint32_t>(m.x), static_cast<uint32_t>(m.y))
@@ -345,18 +349,19 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, cons
         uint32_t cm = 0;
 #pragma unroll
         for (uint32_t p = 0; p < kTorusMaxCosets; ++p) cm |= ((cmin[p] >> 4) == best ? 1u : 0u) << p;
-        // pass 1b: in those cosets only (a loop per lane), the y-shifts that
-        // reach it with either entry (bit p*ly + b); the key fields of both
-        // entries are compared at once against the pattern
+        // pass 1b and 2: in those cosets only (a loop per lane), the y-shifts
+        // that reach it with either entry (the key fields of both entries are
+        // compared at once against the pattern), and a full evaluation of the
+        // images they give, with the coset image already at hand
         const uint32_t pat = (best << 4) | (best << 20);
         const uint32_t keys = nz == 2 ? 0xFFF0FFF0u : 0x0000FFF0u;
-        uint64_t M0 = 0, M1 = 0;
         while (cm) {
             const uint32_t p = static_cast<uint32_t>(__builtin_ctz(cm));
             cm &= cm - 1;
-            W u = us[0];
+            W u = pr[0];
 #pragma unroll
-            for (uint32_t q = 1; q < kTorusMaxCosets; ++q) u = (q < ncos && p == q) ? us[q] : u;
+            for (uint32_t q = 1; q < kTorusMaxCosets; ++q) u = (q < ncos && p == q) ? pr[q] : u;
+            u ^= static_cast<W>(cf[p * cstride]);
             uint64_t mb = 0;
 #pragma unroll
             for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
@@ -366,51 +371,34 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, cons
                     mb |= ((d & 0xFFFFu) == 0 || (nz == 2 && (d >> 16) == 0)) ? (1ull << b) : 0ull;
                 }
             }
-            const uint32_t i0 = p * Ly;
-            if (i0 < 64) {
-                M0 |= mb << i0;
-                if (i0 + Ly > 64) M1 |= mb >> (64 - i0);
-            } else {
-                M1 |= mb << (i0 - 64);
-            }
-        }
-        // pass 2: full evaluation of the images those (p, b) give
-        while (M0 | M1) {
-            uint32_t idx;
-            if (M0) {
-                idx = static_cast<uint32_t>(__builtin_ctzll(M0));
-                M0 &= M0 - 1;
-            } else {
-                idx = 64u + static_cast<uint32_t>(__builtin_ctzll(M1));
-                M1 &= M1 - 1;
-            }
-            const uint32_t b = idx % Ly, p = idx / Ly;
-            W v0 = us[0];
-    #pragma unroll
-            for (uint32_t q = 1; q < kTorusMaxCosets; ++q) v0 = (q < ncos && p == q) ? us[q] : v0;
-            if (b) v0 = ((v0 << (L * b)) | (v0 >> (P.n_sites - L * b))) & full;
-            // low entry: v0's top two rows; high entry: those of v0 ^ full
-            const uint32_t e2 = lut[static_cast<uint32_t>(v0 >> (L * (Ly - 2))) & m2];
+            while (mb) {
+                const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(mb));
+                mb &= mb - 1;
+                W v0 = u;
+                if (b) v0 = ((v0 << (L * b)) | (v0 >> (P.n_sites - L * b))) & full;
+                // low entry: v0's top two rows; high entry: those of v0 ^ full
+                const uint32_t e2 = lut[static_cast<uint32_t>(v0 >> (L * (Ly - 2))) & m2];
 #pragma unroll
-            for (uint32_t f = 0; f < 2; ++f) {
-                if (f >= nz) break;
-                const uint32_t e = f ? (e2 >> 16) : (e2 & 0xFFFFu);
-                if ((e >> 4) != best) continue;
-                W v = f ? static_cast<W>(v0 ^ full) : v0;
-                const uint32_t base = (p * P.n_trans + L * b) * nz + f;
-                if (e & 8u) {
-                    for (uint32_t a = 0; a < L; ++a) {
-                        if (v < rmin) { rmin = v; arg = base + a * nz; }
-                        if (a + 1 < L) v = xrot<W>(v, P);
+                for (uint32_t f = 0; f < 2; ++f) {
+                    if (f >= nz) break;
+                    const uint32_t e = f ? (e2 >> 16) : (e2 & 0xFFFFu);
+                    if ((e >> 4) != best) continue;
+                    W v = f ? static_cast<W>(v0 ^ full) : v0;
+                    const uint32_t base = (p * P.n_trans + L * b) * nz + f;
+                    if (e & 8u) {
+                        for (uint32_t a = 0; a < L; ++a) {
+                            if (v < rmin) { rmin = v; arg = base + a * nz; }
+                            if (a + 1 < L) v = xrot<W>(v, P);
+                        }
+                    } else {
+                        const uint32_t a = e & 7u;
+                        W c = v;
+                        if (a) {
+                            const W ma = static_cast<W>(lcol[a]);
+                            c = ((v << a) & ma) | ((v >> (L - a)) & ~ma & full);
+                        }
+                        if (c < rmin) { rmin = c; arg = base + a * nz; }
                     }
-                } else {
-                    const uint32_t a = e & 7u;
-                    W c = v;
-                    if (a) {
-                        const W ma = static_cast<W>(lcol[a]);
-                        c = ((v << a) & ma) | ((v >> (L - a)) & ~ma & full);
-                    }
-                    if (c < rmin) { rmin = c; arg = base + a * nz; }
                 }
             }
         }
@@ -427,7 +415,7 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, cons
             for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
                 for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
                     const uint32_t b = LY ? b0 : uni(b1);
-                    m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, lut[pair_of(us[p], b)]));
+                    m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, lut[pair_of(LS_IMG(p), b)]));
                 }
             }
             cmin[p] = nz == 2 ? min(static_cast<uint32_t>(m.x), static_cast<uint32_t>(m.y))
@@ -444,9 +432,10 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, cons
         while (cm) {
             const uint32_t p = static_cast<uint32_t>(__builtin_ctz(cm));
             cm &= cm - 1;
-            W u = us[0];
+            W u = pr[0];
 #pragma unroll
-            for (uint32_t q = 1; q < kTorusMaxCosets; ++q) u = (q < ncos && p == q) ? us[q] : u;
+            for (uint32_t q = 1; q < kTorusMaxCosets; ++q) u = (q < ncos && p == q) ? pr[q] : u;
+            u ^= static_cast<W>(cf[p * cstride]);
 #pragma unroll
             for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
                 for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
@@ -472,9 +461,10 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, cons
             }
             const uint32_t f = idx % nz, pb = idx / nz;
             const uint32_t b = pb % Ly, p = pb / Ly;
-            W v = us[0];
-    #pragma unroll
-            for (uint32_t q = 1; q < kTorusMaxCosets; ++q) v = (q < ncos && p == q) ? us[q] : v;
+            W v = pr[0];
+#pragma unroll
+            for (uint32_t q = 1; q < kTorusMaxCosets; ++q) v = (q < ncos && p == q) ? pr[q] : v;
+            v ^= static_cast<W>(cf[p * cstride]);
             if (b) v = ((v << (L * b)) | (v >> (P.n_sites - L * b))) & full;
             if (f) v ^= full;
             const uint32_t e = lut[static_cast<uint32_t>(v >> (L * (Ly - 2))) & m2] & 0xFFFFu;
@@ -498,6 +488,7 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *us, cons
     if constexpr (TRACK) code = arg;
     else code = 0;
     return rmin;
+#undef LS_IMG
 }
 
 // Binomial coefficient table [65][65] in device memory.
