@@ -218,7 +218,8 @@ def push_product(op, x, pull_ms: float, elements: int, steps: int):
 def lanczos_leg(steps: int = 100):
     """Heisenberg ring N=32 (Sz=0, k=0, R=+1, Z=+1; 4,707,969 states): a
     100-step Lanczos solve (full CGS2, tol 0), with generated and with stored
-    elements; time per step and the share spent in the products."""
+    elements; time per step and the share spent in the products; and the
+    same solves with the second Gram-Schmidt pass only where needed."""
     import torch
     import paper_2308_16712_amd as ls
     from workloads import configs
@@ -251,6 +252,16 @@ def lanczos_leg(steps: int = 100):
         out[form] = {"e0": r["e0"], "iters": r["iters"], "s": wall, "ms_per_step": wall * 1e3 / r["iters"],
                      "product_ms": product_ms, "product_share": product_ms * r["iters"] / (wall * 1e3)}
         print(f"[bench] lanczos ring32 {form}: {wall:.2f}s, e0={r['e0']:.12f}", file=sys.stderr, flush=True)
+        # the same solve with the second Gram-Schmidt pass only where needed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = op.lanczos(steps, tol=0.0, seed=1, reorth="selective")
+        torch.cuda.synchronize()
+        wall_s = time.perf_counter() - t0
+        out[form]["selective_reorth"] = {"e0": rs["e0"], "ms_per_step": wall_s * 1e3 / rs["iters"],
+                                         "e0_diff_vs_full": abs(rs["e0"] - r["e0"])}
+        print(f"[bench] lanczos ring32 {form} selective: {wall_s:.2f}s, e0={rs['e0']:.12f}", file=sys.stderr,
+              flush=True)
         op.close()
         del x, y
     out["e0_identical"] = out["generated"]["e0"] == out["stored"]["e0"]

@@ -267,9 +267,14 @@ ls_status ls_batch_set_graph(ls_batch *batch, int enabled);
 void ls_batch_destroy(ls_batch *batch);
 
 /* Lanczos ground-state solve on top of ls_matvec.  FP64 throughout, Krylov
- * vectors resident in HBM, full CGS2 reorthogonalization when reorth = 1,
- * dot products reduced in a fixed order (deterministic).
+ * vectors resident in HBM, dot products reduced in a fixed order
+ * (deterministic).
  *   max_iter  Krylov dimension cap (>= 1; clipped to dim).
+ *   reorth    0: none.  1: full CGS2, two classical Gram-Schmidt passes
+ *             against every stored Krylov vector at every step.  2: the
+ *             second pass only when the first removed more than half of
+ *             ||w||^2 (the criterion of Daniel, Gragg, Kaufman and Stewart,
+ *             1976), decided on the device.  Other values: LS_EINVAL.
  *   tol       0: run exactly max_iter steps.  > 0: stop when successive
  *             lowest Ritz values differ by < tol*max(1,|E0|) and the residual
  *             bound beta |s_last| < sqrt(tol)*max(1,|E0|).

@@ -174,9 +174,23 @@ def dense(prob: Problem, reps, stab) -> np.ndarray:
     return matvec(prob, reps, stab, np.eye(d, dtype=np.complex128))
 
 
-def lanczos(apply_h, v0: np.ndarray, m: int, reorth: bool = True, tol: float = 0.0):
+def cgs_selective(Vm: np.ndarray, w: np.ndarray):
+    """One classical Gram-Schmidt pass of w against the rows of Vm, and a
+    second one only when the first removed more than half of ||w||^2 (the
+    criterion of Daniel, Gragg, Kaufman and Stewart, Math. Comp. 30 (1976),
+    with eta^2 = 1/2).  Returns (w, passes run)."""
+    n0 = np.vdot(w, w).real
+    w = w - Vm.T @ (Vm.conj() @ w)
+    if np.vdot(w, w).real < 0.5 * n0:
+        return w - Vm.T @ (Vm.conj() @ w), 2
+    return w, 1
+
+
+def lanczos(apply_h, v0: np.ndarray, m: int, reorth=True, tol: float = 0.0):
     """Lanczos three-term recurrence in FP64 with optional full CGS2
-    reorthogonalization; the tridiagonal eigenproblem by SciPy.
+    reorthogonalization (reorth True), or a second Gram-Schmidt pass only when
+    the first needs it (reorth "selective", cgs_selective); the tridiagonal
+    eigenproblem by SciPy.
 
     Step k: w = H v_k; alpha_k = Re <v_k, w>; w -= alpha_k v_k + beta_k v_{k-1};
     (CGS2: twice w -= V (V^H w)); beta_{k+1} = ||w||; v_{k+1} = w / beta_{k+1}.
@@ -201,7 +215,9 @@ def lanczos(apply_h, v0: np.ndarray, m: int, reorth: bool = True, tol: float = 0
         w = w - a * V[k]
         if k > 0:
             w = w - beta[k - 1] * V[k - 1]
-        if reorth:
+        if reorth == "selective":
+            w, _ = cgs_selective(np.stack(V, axis=0), w)
+        elif reorth:
             Vm = np.stack(V, axis=0)
             for _ in range(2):
                 h = Vm.conj() @ w

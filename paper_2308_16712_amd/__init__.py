@@ -76,6 +76,6 @@ def ls_matvec_push(op: Operator, x, y=None, stream=None):
     return op.matvec_push(x, y, stream)
 
 
-def ls_lanczos(op: Operator, max_iter: int, tol: float = 0.0, seed: int = 1, v0=None, reorth: bool = True,
+def ls_lanczos(op: Operator, max_iter: int, tol: float = 0.0, seed: int = 1, v0=None, reorth=True,
                stream=None):
     return op.lanczos(max_iter, tol, seed, v0, reorth, stream)

@@ -236,6 +236,24 @@ def terms_to_ctypes(term_table) -> ctypes.Array:
     return arr
 
 
+
+REORTH_CODES = {"none": 0, "full": 1, "selective": 2}
+
+
+def reorth_code(reorth) -> int:
+    """ls_lanczos_opts.reorth from True/False, "none"/"full"/"selective" or 0/1/2:
+    none, full CGS2 (two Gram-Schmidt passes every step), or a second pass only
+    when the first removed more than half of ||w||^2."""
+    if isinstance(reorth, str):
+        return REORTH_CODES[reorth]
+    if isinstance(reorth, bool):
+        return 1 if reorth else 0
+    code = int(reorth)
+    if code not in (0, 1, 2):
+        raise ValueError("reorth must be 0, 1 or 2")
+    return code
+
+
 class Operator:
     """Handle of a compiled Hamiltonian (ls_operator_create)."""
 
@@ -296,12 +314,12 @@ class Operator:
         _check(load().ls_matvec_push(self._h, nrhs, _dptr(x), _dptr(y), _stream_ptr(stream)))
         return y
 
-    def lanczos(self, max_iter: int, tol: float = 0.0, seed: int = 1, v0=None, reorth: bool = True,
+    def lanczos(self, max_iter: int, tol: float = 0.0, seed: int = 1, v0=None, reorth=True,
                 stream=None):
         m = int(max_iter)
         alpha = np.zeros(m)
         beta = np.zeros(m)
-        opts = LanczosOpts(m, 1 if reorth else 0, float(tol), int(seed),
+        opts = LanczosOpts(m, reorth_code(reorth), float(tol), int(seed),
                            _dptr(v0) if v0 is not None else None, alpha.ctypes.data, beta.ctypes.data)
         e0 = ctypes.c_double()
         it = ctypes.c_uint32()
@@ -329,9 +347,9 @@ class Solver:
     solvers advance together with Solver.step_all (one fused product)."""
 
     def __init__(self, op: "Operator", max_iter: int, tol: float = 0.0, seed: int = 1, v0=None,
-                 reorth: bool = True, stream=None):
+                 reorth=True, stream=None):
         self.op = op
-        opts = LanczosOpts(int(max_iter), 1 if reorth else 0, float(tol), int(seed),
+        opts = LanczosOpts(int(max_iter), reorth_code(reorth), float(tol), int(seed),
                            _dptr(v0) if v0 is not None else None, None, None)
         h = ctypes.c_void_p()
         _check(load().ls_solver_create(op.handle, ctypes.byref(opts), _stream_ptr(stream), ctypes.byref(h)))

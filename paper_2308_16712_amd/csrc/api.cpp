@@ -305,7 +305,7 @@ ls_status ls_solver_create(const ls_operator *op, const ls_lanczos_opts *opts, v
     return guarded([&] {
         LS_REQUIRE(op != nullptr && opts != nullptr && out != nullptr, "operator, opts and out must not be NULL");
         LS_REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
-        LS_REQUIRE(opts->reorth <= 1, "reorth must be 0 or 1");
+        LS_REQUIRE(opts->reorth <= 2, "reorth must be 0, 1 or 2");
         LS_REQUIRE(std::isfinite(opts->tol) && opts->tol >= 0, "tol must be >= 0");
         LS_REQUIRE(op->basis->dim > 0, "the basis is empty");
         *out = ls::solver_create(op, opts, as_stream(stream));
@@ -339,7 +339,7 @@ ls_status ls_lanczos(const ls_operator *op, const ls_lanczos_opts *opts, void *s
     return guarded([&] {
         LS_REQUIRE(op != nullptr && opts != nullptr, "operator and opts must not be NULL");
         LS_REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
-        LS_REQUIRE(opts->reorth <= 1, "reorth must be 0 or 1");
+        LS_REQUIRE(opts->reorth <= 2, "reorth must be 0, 1 or 2");
         LS_REQUIRE(std::isfinite(opts->tol) && opts->tol >= 0, "tol must be >= 0");
         LS_REQUIRE(op->basis->dim > 0, "the basis is empty");
         return ls::run_lanczos(op, opts, as_stream(stream), e0, iters, resid_bound);

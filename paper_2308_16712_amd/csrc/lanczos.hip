@@ -7,6 +7,10 @@
 //   w = H v_k;  alpha_k = Re<v_k, w>;  w -= alpha_k v_k + beta_k v_{k-1};
 //   CGS2 (twice: h = V^H w; w -= V h);  beta_{k+1} = ||w||;
 //   v_{k+1} = w / beta_{k+1}.
+// The second Gram-Schmidt pass is either always run (full CGS2) or run only
+// when the first pass removed more than half of ||w||^2 (the test of Daniel,
+// Gragg, Kaufman and Stewart, 1976, with eta^2 = 1/2); the decision is taken
+// on the device, so the stepper below needs no extra synchronisation.
 // Dot products use a fixed grid and a fixed reduction tree, so results do
 // not depend on scheduling.  The m x m tridiagonal eigenproblem is solved on
 // the host (Sturm-sequence bisection for the lowest eigenvalue, inverse
@@ -86,18 +90,24 @@ __global__ void __launch_bounds__(kBlock) k_reduce_partials(const double2 *parti
     if (threadIdx.x == 0) out[j] = make_double2(re, im);
 }
 
-// partial[b][j0 + q] = sum over the block's rows of conj(V_{j0+q}) w, q < tile
+// partial[b][j0 + q] = sum over the block's rows of conj(V_{j0+q}) w, q < tile.
+// With wn != null also wn[b] = the block's part of ||w||^2 (accumulated as
+// k_dot_partial does).  Does nothing when gate is set and *gate == 0.
 template <bool CPLX>
 __global__ void __launch_bounds__(kBlock) k_multidot_partial(const void *pV, uint64_t n, int j0, int tile,
-                                                             const void *pw, double2 *partial, int stride) {
+                                                             const void *pw, double2 *partial, int stride,
+                                                             const int *gate, double2 *wn) {
+    if (gate && *gate == 0) return;
     __shared__ double sh[kBlock];
     double re[kTile], im[kTile];
+    double nre = 0.0;
 #pragma unroll
     for (int q = 0; q < kTile; ++q) re[q] = im[q] = 0.0;
     const uint64_t gstride = static_cast<uint64_t>(kDotBlocks) * kBlock;
     for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += gstride) {
         if constexpr (CPLX) {
             const double2 w = static_cast<const double2 *>(pw)[i];
+            if (wn) nre = fma(w.x, w.x, fma(w.y, w.y, nre));
             const double2 *Vb = static_cast<const double2 *>(pV);
 #pragma unroll
             for (int q = 0; q < kTile; ++q) {
@@ -109,6 +119,7 @@ __global__ void __launch_bounds__(kBlock) k_multidot_partial(const void *pV, uin
             }
         } else {
             const double w = static_cast<const double *>(pw)[i];
+            if (wn) nre = fma(w, w, nre);
             const double *Vb = static_cast<const double *>(pV);
 #pragma unroll
             for (int q = 0; q < kTile; ++q)
@@ -121,32 +132,62 @@ __global__ void __launch_bounds__(kBlock) k_multidot_partial(const void *pV, uin
         if constexpr (CPLX) m = block_reduce(im[q], sh);
         if (threadIdx.x == 0) partial[static_cast<size_t>(blockIdx.x) * stride + j0 + q] = make_double2(r, m);
     }
+    if (wn) {
+        const double r = block_reduce(nre, sh);
+        if (threadIdx.x == 0) wn[blockIdx.x] = make_double2(r, 0.0);
+    }
 }
 
-// w -= sum_j V_j h_j
+// w -= sum_j V_j h_j over the rows of the fixed grid of the dot products;
+// with wn != null also wn[b] = the block's part of ||w||^2 of the new w (the
+// same rows and order as k_dot_partial, so the same value as a separate dot).
+// Does nothing when gate is set and *gate == 0.
 template <bool CPLX>
-__global__ void __launch_bounds__(kBlock) k_gemv_sub(const void *pV, uint64_t n, int nv, const double2 *h, void *pw) {
-    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
-    if constexpr (CPLX) {
-        const double2 *Vb = static_cast<const double2 *>(pV);
-        double2 w = static_cast<double2 *>(pw)[i];
-        double sre = 0.0, sim = 0.0;
-        for (int j = 0; j < nv; ++j) {
-            const double2 v = Vb[static_cast<uint64_t>(j) * n + i];
-            const double2 c = h[j];
-            sre = fma(v.x, c.x, fma(-v.y, c.y, sre));
-            sim = fma(v.x, c.y, fma(v.y, c.x, sim));
+__global__ void __launch_bounds__(kBlock) k_gemv_sub(const void *pV, uint64_t n, int nv, const double2 *h, void *pw,
+                                                     const int *gate, double2 *wn) {
+    if (gate && *gate == 0) return;
+    __shared__ double sh[kBlock];
+    double nre = 0.0;
+    const uint64_t gstride = static_cast<uint64_t>(kDotBlocks) * kBlock;
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n; i += gstride) {
+        if constexpr (CPLX) {
+            const double2 *Vb = static_cast<const double2 *>(pV);
+            double2 w = static_cast<double2 *>(pw)[i];
+            double sre = 0.0, sim = 0.0;
+            for (int j = 0; j < nv; ++j) {
+                const double2 v = Vb[static_cast<uint64_t>(j) * n + i];
+                const double2 c = h[j];
+                sre = fma(v.x, c.x, fma(-v.y, c.y, sre));
+                sim = fma(v.x, c.y, fma(v.y, c.x, sim));
+            }
+            w.x -= sre;
+            w.y -= sim;
+            static_cast<double2 *>(pw)[i] = w;
+            nre = fma(w.x, w.x, fma(w.y, w.y, nre));
+        } else {
+            const double *Vb = static_cast<const double *>(pV);
+            double s = 0.0;
+            for (int j = 0; j < nv; ++j) s = fma(Vb[static_cast<uint64_t>(j) * n + i], h[j].x, s);
+            const double w = static_cast<double *>(pw)[i] - s;
+            static_cast<double *>(pw)[i] = w;
+            nre = fma(w, w, nre);
         }
-        w.x -= sre;
-        w.y -= sim;
-        static_cast<double2 *>(pw)[i] = w;
-    } else {
-        const double *Vb = static_cast<const double *>(pV);
-        double s = 0.0;
-        for (int j = 0; j < nv; ++j) s = fma(Vb[static_cast<uint64_t>(j) * n + i], h[j].x, s);
-        static_cast<double *>(pw)[i] -= s;
     }
+    if (wn) {
+        const double r = block_reduce(nre, sh);
+        if (threadIdx.x == 0) wn[blockIdx.x] = make_double2(r, 0.0);
+    }
+}
+
+// Second pass needed (DGKS): ||w1||^2 < ||w||^2 / 2.  nrm = ||w1||^2.
+__global__ void k_reorth_decide(const double2 *wn, const double2 *w1n, int *gate, double2 *nrm) {
+    *gate = w1n[0].x < 0.5 * wn[0].x ? 1 : 0;
+    nrm[0] = w1n[0];
+}
+
+// nrm = ||w2||^2 when the second pass ran
+__global__ void k_reorth_pick(const int *gate, const double2 *w2n, double2 *nrm) {
+    if (*gate) nrm[0] = w2n[0];
 }
 
 // w -= alpha v + beta vp   (vp may be null)
@@ -195,6 +236,67 @@ __global__ void __launch_bounds__(kBlock) k_fill_uniform(double *out, uint64_t c
 }
 
 uint32_t grid(uint64_t n) { return static_cast<uint32_t>((n + kBlock - 1) / kBlock); }
+
+// Device work buffers of the reorthogonalisation.
+struct ReorthBufs {
+    double2 *partial;   // [kDotBlocks][m] multi-dot parts (stride m)
+    double2 *npart;     // [2][kDotBlocks] block parts of ||w||^2 before / after a pass
+    double2 *hs;        // [m] coefficients h = V^H w
+    double2 *nrm;       // [4] reduced ||w||^2, ||w1||^2, ||w2||^2; [3] free for the caller
+    int *gate;          // second pass needed
+    int m;
+};
+
+enum { kReorthNone = 0, kReorthFull = 1, kReorthSelective = 2 };
+
+// aux: npart [2][kDotBlocks] | nrm [4] | gate
+constexpr size_t kAuxBytes = (2 * kDotBlocks + 4) * sizeof(double2) + 16;
+ReorthBufs reorth_bufs(double2 *partial, double2 *hs, void *aux, int m) {
+    ReorthBufs b;
+    b.partial = partial;
+    b.hs = hs;
+    b.npart = static_cast<double2 *>(aux);
+    b.nrm = b.npart + 2 * kDotBlocks;
+    b.gate = reinterpret_cast<int *>(b.nrm + 4);
+    b.m = m;
+    return b;
+}
+
+// Orthogonalises w against V_0 .. V_{nv-1} (mode: none, two passes, or a
+// second pass only when the first removed more than half of ||w||^2) and
+// leaves ||w||^2 of the result in out[0].x.
+template <bool CPLX>
+void enqueue_reorth(const void *Vb, uint64_t n, int nv, int mode, void *w, const ReorthBufs &b, double2 *out,
+                    hipStream_t st) {
+    if (mode == kReorthNone) {
+        hipLaunchKernelGGL(k_dot_partial<CPLX>, dim3(kDotBlocks), dim3(kBlock), 0, st, w, w, n, b.partial);
+        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, b.partial, kDotBlocks, 1, out);
+        return;
+    }
+    const bool sel = mode == kReorthSelective;
+    double2 *before = b.npart, *after = b.npart + kDotBlocks;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int *g = (sel && pass == 1) ? b.gate : nullptr;
+        for (int j0 = 0; j0 < nv; j0 += kTile)
+            hipLaunchKernelGGL(k_multidot_partial<CPLX>, dim3(kDotBlocks), dim3(kBlock), 0, st, Vb, n, j0,
+                               std::min(kTile, nv - j0), w, b.partial, b.m, g,
+                               (sel && pass == 0 && j0 == 0) ? before : nullptr);
+        hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(kBlock), 0, st, b.partial, kDotBlocks, b.m, b.hs);
+        hipLaunchKernelGGL(k_gemv_sub<CPLX>, dim3(kDotBlocks), dim3(kBlock), 0, st, Vb, n, nv, b.hs, w, g,
+                           (sel || pass == 1) ? after : nullptr);
+        if (sel && pass == 0) {
+            hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, before, kDotBlocks, 1, b.nrm);
+            hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, after, kDotBlocks, 1, b.nrm + 1);
+            hipLaunchKernelGGL(k_reorth_decide, dim3(1), dim3(1), 0, st, b.nrm, b.nrm + 1, b.gate, out);
+        }
+    }
+    if (sel) {
+        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, after, kDotBlocks, 1, b.nrm + 2);
+        hipLaunchKernelGGL(k_reorth_pick, dim3(1), dim3(1), 0, st, b.gate, b.nrm + 2, out);
+    } else {
+        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, after, kDotBlocks, 1, out);
+    }
+}
 
 // Lowest eigenvalue of the symmetric tridiagonal (a, b) by Sturm bisection.
 double tridiag_lowest(const std::vector<double> &a, const std::vector<double> &b) {
@@ -267,17 +369,19 @@ ls_status lanczos_impl(const ls_operator *op, const ls_lanczos_opts *o, hipStrea
     const uint64_t n = op->basis->dim;
     const uint32_t m = static_cast<uint32_t>(std::min<uint64_t>(o->max_iter, n));
     const size_t es = sizeof(T);
-    DevMem Vm, wm, part, scal;
+    DevMem Vm, wm, part, scal, aux;
     hipError_t err = hipMalloc(&Vm.p, static_cast<size_t>(m) * n * es);
     if (err != hipSuccess) throw Error{LS_ENOMEM, "cannot allocate the Krylov vectors"};
     LS_HIP_CHECK(hipMalloc(&wm.p, n * es));
     LS_HIP_CHECK(hipMalloc(&part.p, static_cast<size_t>(kDotBlocks) * std::max<uint32_t>(m, 1) * sizeof(double2)));
     LS_HIP_CHECK(hipMalloc(&scal.p, std::max<uint32_t>(m, 1) * sizeof(double2)));
+    LS_HIP_CHECK(hipMalloc(&aux.p, kAuxBytes));
     T *Vb = static_cast<T *>(Vm.p);
     T *w = static_cast<T *>(wm.p);
     double2 *partial = static_cast<double2 *>(part.p);
     double2 *hs = static_cast<double2 *>(scal.p);
     const uint64_t nd = n * (CPLX ? 2 : 1);    // doubles per vector
+    const ReorthBufs rb = reorth_bufs(partial, hs, aux.p, static_cast<int>(m));
 
     auto dot = [&](const T *x, const T *y) {
         hipLaunchKernelGGL(k_dot_partial<CPLX>, dim3(kDotBlocks), dim3(kBlock), 0, st, x, y, n, partial);
@@ -311,19 +415,12 @@ ls_status lanczos_impl(const ls_operator *op, const ls_lanczos_opts *o, hipStrea
         hipLaunchKernelGGL(k_three_term<CPLX>, dim3(grid(n)), dim3(kBlock), 0, st, w, vk,
                            k > 0 ? Vb + static_cast<uint64_t>(k - 1) * n : nullptr, n, a,
                            k > 0 ? beta[k - 1] : 0.0);
-        if (o->reorth) {
-            const int nv = static_cast<int>(k) + 1;
-            for (int pass = 0; pass < 2; ++pass) {
-                for (int j0 = 0; j0 < nv; j0 += kTile)
-                    hipLaunchKernelGGL(k_multidot_partial<CPLX>, dim3(kDotBlocks), dim3(kBlock), 0, st, Vb, n, j0,
-                                       std::min(kTile, nv - j0), w, partial, static_cast<int>(m));
-                hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(kBlock), 0, st, partial, kDotBlocks,
-                                   static_cast<int>(m), hs);
-                hipLaunchKernelGGL(k_gemv_sub<CPLX>, dim3(grid(n)), dim3(kBlock), 0, st, Vb, n, nv, hs, w);
-            }
-        }
+        enqueue_reorth<CPLX>(Vb, n, static_cast<int>(k) + 1, static_cast<int>(o->reorth), w, rb, rb.nrm + 3, st);
         LS_HIP_CHECK(hipGetLastError());
-        const double bnext = std::sqrt(dot(w, w).x);
+        double2 wn;
+        LS_HIP_CHECK(hipMemcpyAsync(&wn, rb.nrm + 3, sizeof(double2), hipMemcpyDeviceToHost, st));
+        LS_HIP_CHECK(hipStreamSynchronize(st));
+        const double bnext = std::sqrt(wn.x);
         alpha.push_back(a);
         e0 = tridiag_lowest(alpha, beta);
         resid = bnext * tridiag_last_component(alpha, beta, e0);
@@ -418,11 +515,12 @@ struct ls_solver {
     uint64_t n = 0;
     uint32_t m = 0;
     double tol = 0.0;
-    bool reorth = true;
+    int reorth = 1;               // none, full CGS2, selective second pass
     void *V = nullptr;            // [m][n]
     void *w = nullptr;            // [n]
     double2 *partial = nullptr;   // [kDotBlocks][m]
     double2 *hs = nullptr;        // [m] reorthogonalisation coefficients
+    void *aux = nullptr;          // norms and gate of the reorthogonalisation
     double2 *dots = nullptr;      // [2]: <v_k, w>, <w, w>
     double *scal = nullptr;       // [2]: alpha_k, beta_{k+1}
     double *bprev = nullptr;      // beta_k (device copy)
@@ -445,6 +543,7 @@ void free_solver(ls_solver *s) {
     hipFree(s->w);
     hipFree(s->partial);
     hipFree(s->hs);
+    hipFree(s->aux);
     hipFree(s->dots);
     hipFree(s->scal);
     hipFree(s->bprev);
@@ -470,18 +569,8 @@ void enqueue_after_product(ls_solver *s, hipStream_t st) {
     enqueue_dot<CPLX>(s, vk, w, s->dots, st);
     hipLaunchKernelGGL(k_three_term_dev<CPLX>, dim3(grid(n)), dim3(kBlock), 0, st, w, vk,
                        k > 0 ? Vb + static_cast<uint64_t>(k - 1) * n : nullptr, n, s->dots, s->bprev);
-    if (s->reorth) {
-        const int nv = static_cast<int>(k) + 1;
-        for (int pass = 0; pass < 2; ++pass) {
-            for (int j0 = 0; j0 < nv; j0 += kTile)
-                hipLaunchKernelGGL(k_multidot_partial<CPLX>, dim3(kDotBlocks), dim3(kBlock), 0, st, Vb, n, j0,
-                                   std::min(kTile, nv - j0), w, s->partial, static_cast<int>(s->m));
-            hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(kBlock), 0, st, s->partial, kDotBlocks,
-                               static_cast<int>(s->m), s->hs);
-            hipLaunchKernelGGL(k_gemv_sub<CPLX>, dim3(grid(n)), dim3(kBlock), 0, st, Vb, n, nv, s->hs, w);
-        }
-    }
-    enqueue_dot<CPLX>(s, w, w, s->dots + 1, st);
+    const ReorthBufs rb = reorth_bufs(s->partial, s->hs, s->aux, static_cast<int>(s->m));
+    enqueue_reorth<CPLX>(Vb, n, static_cast<int>(k) + 1, s->reorth, w, rb, s->dots + 1, st);
     hipLaunchKernelGGL(k_alpha_beta, dim3(1), dim3(1), 0, st, s->dots, s->dots + 1, s->scal);
     if (k + 1 < s->m) {
         const uint64_t nd = n * (CPLX ? 2 : 1);
@@ -523,7 +612,7 @@ uint64_t solver_footprint(const ls_operator *op, uint32_t max_iter) {
     const uint64_t n = op->basis->dim;
     const uint64_t m = std::min<uint64_t>(max_iter, n);
     const uint64_t es = op->is_complex ? 16 : 8;
-    return (m + 1) * n * es + static_cast<uint64_t>(kDotBlocks) * std::max<uint64_t>(m, 1) * 16 + 4096;
+    return (m + 1) * n * es + static_cast<uint64_t>(kDotBlocks) * std::max<uint64_t>(m, 1) * 16 + kAuxBytes + 4096;
 }
 
 ls_solver *solver_create(const ls_operator *op, const ls_lanczos_opts *o, hipStream_t st) {
@@ -534,7 +623,7 @@ ls_solver *solver_create(const ls_operator *op, const ls_lanczos_opts *o, hipStr
         s->n = op->basis->dim;
         s->m = static_cast<uint32_t>(std::min<uint64_t>(o->max_iter, s->n));
         s->tol = o->tol;
-        s->reorth = o->reorth != 0;
+        s->reorth = static_cast<int>(o->reorth);
         const size_t es = s->cplx ? 16 : 8;
         if (hipMalloc(&s->V, static_cast<size_t>(s->m) * s->n * es) != hipSuccess)
             throw Error{LS_ENOMEM, "cannot allocate the Krylov vectors"};
@@ -542,6 +631,7 @@ ls_solver *solver_create(const ls_operator *op, const ls_lanczos_opts *o, hipStr
         LS_HIP_CHECK(hipMalloc(&s->partial, static_cast<size_t>(kDotBlocks) * std::max<uint32_t>(s->m, 1) *
                                                 sizeof(double2)));
         LS_HIP_CHECK(hipMalloc(&s->hs, std::max<uint32_t>(s->m, 1) * sizeof(double2)));
+        LS_HIP_CHECK(hipMalloc(&s->aux, kAuxBytes));
         LS_HIP_CHECK(hipMalloc(&s->dots, 2 * sizeof(double2)));
         LS_HIP_CHECK(hipMalloc(&s->scal, 2 * sizeof(double)));
         LS_HIP_CHECK(hipMalloc(&s->bprev, sizeof(double)));

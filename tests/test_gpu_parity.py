@@ -208,6 +208,35 @@ def test_lanczos_parity(sec):
     assert abs(got2["e0"] - want["e0"]) <= LANCZOS_TOL * max(1.0, abs(want["e0"]))
 
 
+
+@pytest.mark.parametrize("sec", [SMALL[0], SMALL[6], SMALL[3]], ids=lambda s: s.name)
+def test_lanczos_selective_parity(sec):
+    """reorth = 2 (second Gram-Schmidt pass only when needed) against the
+    oracle's selective variant: same steps, coefficients and ground energy."""
+    P, reps, stab, b, op = _built(sec)
+    m = 30
+    v0 = rng.vector(1, len(reps), complex_=op.is_complex)
+    want = oracle.lanczos(lambda v: oracle.matvec(P, reps, stab, v), v0, m, reorth="selective")
+    got = op.lanczos(m, seed=1, reorth="selective")
+    assert got["iters"] == want["iters"]
+    assert abs(got["e0"] - want["e0"]) <= LANCZOS_TOL * max(1.0, abs(want["e0"]))
+    assert np.allclose(got["alpha"], want["alpha"], atol=1e-10)
+    assert np.allclose(got["beta"], want["beta"], atol=1e-10)
+
+
+def test_lanczos_selective_through_exhaustion():
+    """Running the selective variant up to the full sector dimension, where w
+    falls back into the Krylov space and the second pass is taken, still
+    gives the dense ground energy."""
+    sec = next(s for s in SMALL if s.name == "ringD16_0pp")
+    P, reps, stab, b, op = _built(sec)
+    d = len(reps)
+    e_dense = np.linalg.eigvalsh(oracle.dense(P, reps, stab))[0]
+    got = op.lanczos(d, seed=5, reorth="selective")
+    assert abs(got["e0"] - e_dense) <= 1e-10 * max(1.0, abs(e_dense))
+    full = op.lanczos(d, seed=5)
+    assert abs(full["e0"] - e_dense) <= 1e-10 * max(1.0, abs(e_dense))
+
 @pytest.mark.parametrize("sec", [s for s in SMALL if s.name in
                                  ("ringD20_0pp", "torus4x6_full", "ring40_w3_D", "torus6x6_w4_k10",
                                   "ringT10_noU1_k1", "scrambled4x4_full", "ringTZ18_k5")],

@@ -51,6 +51,20 @@ def test_stepper_matches_lanczos_alone_and_in_a_mix():
     assert one.result()["e0"] == solvers[1].result()["e0"]
 
 
+
+def test_stepper_selective_matches_lanczos_alone():
+    secs = [configs.ring_symmetric(20, 0, 1, 1, 0.3, seed=7),
+            configs.ring_symmetric(18, 3, 0, 0, 0.2, seed=8)]          # complex sector
+    ops = [ls.ls_operator_create(ls.ls_basis_build(s), s.terms) for s in secs]
+    alone = [op.lanczos(40, seed=s.seed, reorth="selective") for op, s in zip(ops, secs)]
+    solvers = [ls.Solver(op, 40, seed=s.seed, reorth="selective") for op, s in zip(ops, secs)]
+    while not all(s.result()["done"] for s in solvers):
+        ls.Solver.step_all(solvers)
+    for a, s in zip(alone, solvers):
+        r = s.result()
+        assert r["iters"] == a["iters"]
+        assert r["e0"] == a["e0"]
+
 def test_stepper_against_oracle_lanczos():
     sec = configs.ring_symmetric(16, 0, 1, 1, 0.4, seed=3)
     P = oracle.Problem(sec)

@@ -347,6 +347,38 @@ def test_lanczos_ring16_against_full_space_sparse():
     assert abs(res["e0"] - e_full) < 1e-10
 
 
+
+def test_cgs_selective_decision_and_result():
+    """The selective pass (DGKS, eta^2 = 1/2): a vector far from span(V) gets
+    one pass and is orthogonal to V afterwards; a vector almost inside span(V)
+    loses most of its norm in the first pass and gets the second one."""
+    g = np.random.default_rng(11)
+    Vm = np.linalg.qr(g.standard_normal((40, 6)))[0].T          # 6 orthonormal rows
+    far = g.standard_normal(40)
+    w, passes = oracle.cgs_selective(Vm, far)
+    assert passes == 1 and np.abs(Vm @ w).max() < 1e-13
+    near = Vm.T @ g.standard_normal(6) + 1e-3 * g.standard_normal(40)
+    w, passes = oracle.cgs_selective(Vm, near)
+    assert passes == 2 and np.abs(Vm @ w).max() < 1e-16 * 40
+    # the result is the component of w outside span(V), as projecting by hand gives
+    ref = near - Vm.T @ (Vm @ near)
+    assert np.allclose(w, ref, rtol=0, atol=1e-15)
+
+
+def test_lanczos_selective_matches_dense_and_full_cgs2():
+    n = 12
+    sec = _sector(n, n // 2, lattice.ring_group(n, 0, 1, 1), lattice.ring_bonds(n, 1.0, 0.3))
+    P = oracle.Problem(sec)
+    reps, stab = oracle.enumerate_basis(P)
+    e_dense = np.linalg.eigvalsh(oracle.dense(P, reps, stab))[0]
+    v0 = rng.vector(7, len(reps))
+    apply_h = lambda v: oracle.matvec(P, reps, stab, v)
+    sel = oracle.lanczos(apply_h, v0, min(60, len(reps)), reorth="selective")
+    full = oracle.lanczos(apply_h, v0, min(60, len(reps)))
+    assert abs(sel["e0"] - e_dense) < 1e-10
+    k = min(len(sel["alpha"]), 20)
+    assert np.allclose(sel["alpha"][:k], full["alpha"][:k], rtol=0, atol=1e-11)
+
 # ---------------------------------------------------------------- generator
 
 def test_counter_generator_matches_published_splitmix64(golden_dir):
