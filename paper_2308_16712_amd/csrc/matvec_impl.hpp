@@ -114,14 +114,21 @@ constexpr int block_of(int kind) { return kind == kOrbitTorus ? 1024 : 256; }
 
 __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
 
-// LDS layout: terms | pair table | col_ge | flip images (torus only)
+// LDS: the torus search's pair table is a static array (its address is then
+// a compile-time constant that folds into the lookups); the dynamic part is
+// col_ge | flip images (torus only) | terms.
+constexpr uint32_t kPairTableEntries = 1u << 12;   // 4^lx for lx <= 6
+
+// Dynamic LDS bytes of a launch.
 inline size_t lds_bytes(int kind, uint32_t n_terms, uint32_t n_off, uint32_t lx) {
+    (void)lx;
     size_t b = align16((n_terms > 0 ? n_terms : 1) * sizeof(ls_term_dev));
-    if (kind == kOrbitTorus)
-        b += align16((size_t(1) << (2 * lx)) * sizeof(uint32_t)) + 64 +
-             static_cast<size_t>(n_off) * kTorusCosetSlots * sizeof(uint64_t);
+    if (kind == kOrbitTorus) b += 64 + static_cast<size_t>(n_off) * kTorusCosetSlots * sizeof(uint64_t);
     return b;
 }
+
+// Static LDS of the torus kernels.
+constexpr size_t kPairTableBytes = kPairTableEntries * sizeof(uint32_t);
 
 struct LdsTables {
     ls_term_dev *terms;
@@ -133,12 +140,19 @@ struct LdsTables {
 template <int KIND, uint32_t LX, int BLOCK>
 __device__ __forceinline__ LdsTables lds_tables(const MatvecJob &a, unsigned char *smem) {
     LdsTables L;
-    L.terms = reinterpret_cast<ls_term_dev *>(smem);
-    const size_t terms_bytes = align16(static_cast<size_t>(a.n_terms > 0 ? a.n_terms : 1) * sizeof(ls_term_dev));
-    L.lut = reinterpret_cast<uint32_t *>(smem + terms_bytes);
-    const uint32_t lut_n = KIND == kOrbitTorus ? (1u << (2 * (LX ? LX : a.plan.lx))) : 0u;
-    L.col = reinterpret_cast<uint64_t *>(smem + terms_bytes + align16(lut_n * sizeof(uint32_t)));
-    L.cflip = L.col + 8;
+    if constexpr (KIND == kOrbitTorus) {
+        __shared__ uint32_t pair_table[kPairTableEntries];
+        L.lut = pair_table;
+        L.col = reinterpret_cast<uint64_t *>(smem);
+        L.cflip = L.col + 8;
+        L.terms = reinterpret_cast<ls_term_dev *>(
+            smem + 64 + static_cast<size_t>(a.n_terms - a.n_diag) * kTorusCosetSlots * sizeof(uint64_t));
+    } else {
+        L.lut = nullptr;
+        L.col = nullptr;
+        L.cflip = nullptr;
+        L.terms = reinterpret_cast<ls_term_dev *>(smem);
+    }
     return L;
 }
 

@@ -307,11 +307,20 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *pr, cons
     const uint32_t rm = (1u << L) - 1u, m2 = (1u << (2 * L)) - 1u;
     const uint32_t ncos = P.n_cosets;
     const W full = static_cast<W>(P.full);
-    // top two rows of tau_{0,b}(u): rows ly-1-b and ly-2-b (mod ly)
+    // bits [sh, sh + 32) of u shifted up by 2: an index times 4 is the byte
+    // offset of its 4-byte entry
+    auto x4 = [&](W u, uint32_t sh) -> uint32_t {
+        return sh >= 2 ? static_cast<uint32_t>(u >> (sh - 2)) : static_cast<uint32_t>(u) << (2 - sh);
+    };
+    // byte offset of the entry of the top two rows of tau_{0,b}(u): rows
+    // ly-1-b and ly-2-b (mod ly)
     auto pair_of = [&](W u, uint32_t b) -> uint32_t {
         const uint32_t ty = Ly - 1 - b;
-        if (ty >= 1) return static_cast<uint32_t>(u >> (L * (ty - 1))) & m2;
-        return ((static_cast<uint32_t>(u) & rm) << L) | (static_cast<uint32_t>(u >> (L * (Ly - 1))) & rm);
+        if (ty >= 1) return x4(u, L * (ty - 1)) & (m2 << 2);
+        return ((static_cast<uint32_t>(u) & rm) << (L + 2)) | (x4(u, L * (Ly - 1)) & (rm << 2));
+    };
+    auto entry = [&](uint32_t off) -> uint32_t {
+        return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const unsigned char *>(lut) + off);
     };
     // image p(s) = p(r) ^ pi_p(f) of coset p: fixed p (unrolled loops), or a
     // p that differs between lanes
@@ -337,7 +346,7 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *pr, cons
             for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
                 for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
                     const uint32_t b = LY ? b0 : uni(b1);
-                    m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, lut[pair_of(LS_IMG(p), b)]));
+                    m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, entry(pair_of(LS_IMG(p), b))));
                 }
             }
             cmin[p] = nz == 2 ? min(static_cast<uint32_t>(m.x), static_cast<uint32_t>(m.y))
@@ -367,7 +376,7 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *pr, cons
             for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
                 for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
                     const uint32_t b = LY ? b0 : uni(b1);
-                    const uint32_t d = (lut[pair_of(u, b)] ^ pat) & keys;
+                    const uint32_t d = (entry(pair_of(u, b)) ^ pat) & keys;
                     mb |= ((d & 0xFFFFu) == 0 || (nz == 2 && (d >> 16) == 0)) ? (1ull << b) : 0ull;
                 }
             }
@@ -377,7 +386,7 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *pr, cons
                 W v0 = u;
                 if (b) v0 = ((v0 << (L * b)) | (v0 >> (P.n_sites - L * b))) & full;
                 // low entry: v0's top two rows; high entry: those of v0 ^ full
-                const uint32_t e2 = lut[static_cast<uint32_t>(v0 >> (L * (Ly - 2))) & m2];
+                const uint32_t e2 = entry(x4(v0, L * (Ly - 2)) & (m2 << 2));
 #pragma unroll
                 for (uint32_t f = 0; f < 2; ++f) {
                     if (f >= nz) break;
@@ -415,7 +424,7 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *pr, cons
             for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
                 for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
                     const uint32_t b = LY ? b0 : uni(b1);
-                    m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, lut[pair_of(LS_IMG(p), b)]));
+                    m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, entry(pair_of(LS_IMG(p), b))));
                 }
             }
             cmin[p] = nz == 2 ? min(static_cast<uint32_t>(m.x), static_cast<uint32_t>(m.y))
@@ -440,7 +449,7 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *pr, cons
             for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
                 for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
                     const uint32_t b = LY ? b0 : uni(b1);
-                    const uint32_t e = lut[pair_of(u, b)];
+                    const uint32_t e = entry(pair_of(u, b));
                     const uint32_t idx = (p * Ly + b) * nz;
                     const uint64_t hit = (((e >> 4) & 0xFFFu) == best ? 1ull : 0ull) |
                                          ((nz == 2 && (e >> 20) == best) ? 2ull : 0ull);
@@ -467,7 +476,7 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *pr, cons
             v ^= static_cast<W>(cf[p * cstride]);
             if (b) v = ((v << (L * b)) | (v >> (P.n_sites - L * b))) & full;
             if (f) v ^= full;
-            const uint32_t e = lut[static_cast<uint32_t>(v >> (L * (Ly - 2))) & m2] & 0xFFFFu;
+            const uint32_t e = entry(x4(v, L * (Ly - 2)) & (m2 << 2)) & 0xFFFFu;
             const uint32_t base = (p * P.n_trans + L * b) * nz + f;
             if (e & 8u) {
                 for (uint32_t a = 0; a < L; ++a) {
