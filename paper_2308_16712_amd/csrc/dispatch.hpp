@@ -36,7 +36,6 @@ void dispatch_kind(const Variant &v, int nr, F &f) {
         if constexpr (sizeof(W) == 8) {
             if (v.lx == 6 && v.ly == 6 && v.nz == 2) return dispatch_chi<W, kOrbitTorus, 6, 6, 2>(v, nr, f);
         } else {
-            if (v.lx == 6 && v.ly == 4 && v.nz == 2) return dispatch_chi<W, kOrbitTorus, 6, 4, 2>(v, nr, f);
             if (v.lx == 4 && v.ly == 4 && v.nz == 2) return dispatch_chi<W, kOrbitTorus, 4, 4, 2>(v, nr, f);
         }
         dispatch_chi<W, kOrbitTorus, 0, 0, 0>(v, nr, f);

@@ -152,8 +152,10 @@ Variant variant_of(const ls_operator *op) {
     } else if (torus) {
         v.kind = kOrbitTorus;
         const uint32_t nz = gp.pair_flip ? 2 : 1;
-        if ((gp.lx == 6 && gp.ly == 6 && nz == 2) || (gp.lx == 6 && gp.ly == 4 && nz == 2) ||
-            (gp.lx == 4 && gp.ly == 4 && nz == 2)) {
+        // compile-time shapes: square tori with the full point group (eight
+        // coset representatives) and spin inversion
+        if (gp.cosets.size() == kTorusCosetSlots && nz == 2 &&
+            ((gp.lx == 6 && gp.ly == 6) || (gp.lx == 4 && gp.ly == 4))) {
             v.lx = gp.lx;
             v.ly = gp.ly;
             v.nz = nz;

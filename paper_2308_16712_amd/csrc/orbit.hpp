@@ -305,7 +305,8 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *pr, cons
     const uint32_t L = LX ? LX : P.lx, Ly = LY ? LY : P.ly;
     const uint32_t nz = NZ ? NZ : (P.pair_flip ? 2u : 1u);
     const uint32_t rm = (1u << L) - 1u, m2 = (1u << (2 * L)) - 1u;
-    const uint32_t ncos = P.n_cosets;
+    // the compile-time shapes are built for the full point group only
+    const uint32_t ncos = LX ? kTorusMaxCosets : P.n_cosets;
     const W full = static_cast<W>(P.full);
     // bits [sh, sh + 32) of u shifted up by 2: an index times 4 is the byte
     // offset of its 4-byte entry
@@ -342,12 +343,17 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *pr, cons
             cmin[p] = 0xFFFFu;
             if (p >= ncos) continue;
             u16x2 m = {0xFFFFu, 0xFFFFu};
+            if constexpr (LY != 0) {
+                // all of the coset's table reads in flight before the first minimum
+                const W u = LS_IMG(p);
+                uint32_t e[LY];
 #pragma unroll
-            for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
-                for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
-                    const uint32_t b = LY ? b0 : uni(b1);
-                    m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, entry(pair_of(LS_IMG(p), b))));
-                }
+                for (uint32_t b = 0; b < LY; ++b) e[b] = entry(pair_of(u, b));
+#pragma unroll
+                for (uint32_t b = 0; b < LY; ++b) m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, e[b]));
+            } else {
+                for (uint32_t b1 = 0; b1 < Ly; ++b1)
+                    m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, entry(pair_of(LS_IMG(p), uni(b1)))));
             }
             cmin[p] = nz == 2 ? min(static_cast<uint32_t>(m.x), static_cast<uint32_t>(m.y))
                               : static_cast<uint32_t>(m.x);
