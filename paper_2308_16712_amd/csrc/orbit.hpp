@@ -338,14 +338,17 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *pr, cons
         // table word folded with one packed minimum), then the smallest key
         uint32_t cmin[kTorusMaxCosets];
         uint32_t ball = 0xFFFFu;
+        uint64_t cf_next = cf[0];
 #pragma unroll
         for (uint32_t p = 0; p < kTorusMaxCosets; ++p) {
             cmin[p] = 0xFFFFu;
             if (p >= ncos) continue;
             u16x2 m = {0xFFFFu, 0xFFFFu};
             if constexpr (LY != 0) {
-                // all of the coset's table reads in flight before the first minimum
-                const W u = LS_IMG(p);
+                // the next coset's flip image and all of this coset's table
+                // reads in flight before the first minimum
+                const W u = pr[p] ^ static_cast<W>(cf_next);
+                if (p + 1 < kTorusMaxCosets) cf_next = cf[(p + 1) * cstride];
                 uint32_t e[LY];
 #pragma unroll
                 for (uint32_t b = 0; b < LY; ++b) e[b] = entry(pair_of(u, b));
@@ -378,10 +381,18 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *pr, cons
             for (uint32_t q = 1; q < kTorusMaxCosets; ++q) u = (q < ncos && p == q) ? pr[q] : u;
             u ^= static_cast<W>(cf[p * cstride]);
             uint64_t mb = 0;
+            if constexpr (LY != 0) {
+                uint32_t e[LY];
 #pragma unroll
-            for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
-                for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
-                    const uint32_t b = LY ? b0 : uni(b1);
+                for (uint32_t b = 0; b < LY; ++b) e[b] = entry(pair_of(u, b));
+#pragma unroll
+                for (uint32_t b = 0; b < LY; ++b) {
+                    const uint32_t d = (e[b] ^ pat) & keys;
+                    mb |= ((d & 0xFFFFu) == 0 || (nz == 2 && (d >> 16) == 0)) ? (1ull << b) : 0ull;
+                }
+            } else {
+                for (uint32_t b1 = 0; b1 < Ly; ++b1) {
+                    const uint32_t b = uni(b1);
                     const uint32_t d = (entry(pair_of(u, b)) ^ pat) & keys;
                     mb |= ((d & 0xFFFFu) == 0 || (nz == 2 && (d >> 16) == 0)) ? (1ull << b) : 0ull;
                 }
