@@ -329,44 +329,44 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *pr, cons
     using u16x2 = unsigned short __attribute__((ext_vector_type(2)));
     W rmin = static_cast<W>(~static_cast<W>(0));
     uint32_t arg = 0;
+    // pass 1a: the smallest entry of every coset (both flip entries of a
+    // table word folded with one packed minimum), then the smallest key
+    uint32_t cmin[kTorusMaxCosets];
+    uint32_t ball = 0xFFFFu;
+    uint64_t cf_next = cf[0];
+#pragma unroll
+    for (uint32_t p = 0; p < kTorusMaxCosets; ++p) {
+        cmin[p] = 0xFFFFu;
+        if (p >= ncos) continue;
+        u16x2 m = {0xFFFFu, 0xFFFFu};
+        if constexpr (LY != 0) {
+            // the next coset's flip image and all of this coset's table
+            // reads in flight before the first minimum
+            const W u = pr[p] ^ static_cast<W>(cf_next);
+            if (p + 1 < kTorusMaxCosets) cf_next = cf[(p + 1) * cstride];
+            uint32_t e[LY];
+#pragma unroll
+            for (uint32_t b = 0; b < LY; ++b) e[b] = entry(pair_of(u, b));
+#pragma unroll
+            for (uint32_t b = 0; b < LY; ++b) m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, e[b]));
+        } else {
+            for (uint32_t b1 = 0; b1 < Ly; ++b1)
+                m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, entry(pair_of(LS_IMG(p), uni(b1)))));
+        }
+        cmin[p] = nz == 2 ? min(static_cast<uint32_t>(m.x), static_cast<uint32_t>(m.y))
+                          : static_cast<uint32_t>(m.x);
+        ball = min(ball, cmin[p]);
+    }
+    const uint32_t best = ball >> 4;
+    // the cosets that reach the smallest key
+    uint32_t cm = 0;
+#pragma unroll
+    for (uint32_t p = 0; p < kTorusMaxCosets; ++p) cm |= ((cmin[p] >> 4) == best ? 1u : 0u) << p;
     if constexpr (!TRACK) {
         // one mask bit per (coset, y-shift), and only the cosets that reach
         // the smallest key are scanned twice; the kernels that also track g*
         // do not have the registers for it and keep one bit per (coset,
         // y-shift, flip)
-        // pass 1a: the smallest entry of every coset (both flip entries of a
-        // table word folded with one packed minimum), then the smallest key
-        uint32_t cmin[kTorusMaxCosets];
-        uint32_t ball = 0xFFFFu;
-        uint64_t cf_next = cf[0];
-#pragma unroll
-        for (uint32_t p = 0; p < kTorusMaxCosets; ++p) {
-            cmin[p] = 0xFFFFu;
-            if (p >= ncos) continue;
-            u16x2 m = {0xFFFFu, 0xFFFFu};
-            if constexpr (LY != 0) {
-                // the next coset's flip image and all of this coset's table
-                // reads in flight before the first minimum
-                const W u = pr[p] ^ static_cast<W>(cf_next);
-                if (p + 1 < kTorusMaxCosets) cf_next = cf[(p + 1) * cstride];
-                uint32_t e[LY];
-#pragma unroll
-                for (uint32_t b = 0; b < LY; ++b) e[b] = entry(pair_of(u, b));
-#pragma unroll
-                for (uint32_t b = 0; b < LY; ++b) m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, e[b]));
-            } else {
-                for (uint32_t b1 = 0; b1 < Ly; ++b1)
-                    m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, entry(pair_of(LS_IMG(p), uni(b1)))));
-            }
-            cmin[p] = nz == 2 ? min(static_cast<uint32_t>(m.x), static_cast<uint32_t>(m.y))
-                              : static_cast<uint32_t>(m.x);
-            ball = min(ball, cmin[p]);
-        }
-        const uint32_t best = ball >> 4;
-        // the cosets that reach the smallest key
-        uint32_t cm = 0;
-#pragma unroll
-        for (uint32_t p = 0; p < kTorusMaxCosets; ++p) cm |= ((cmin[p] >> 4) == best ? 1u : 0u) << p;
         // pass 1b and 2: in those cosets only (a loop per lane), the y-shifts
         // that reach it with either entry (the key fields of both entries are
         // compared at once against the pattern), and a full evaluation of the
@@ -429,29 +429,6 @@ __device__ __forceinline__ W torus_orbit_min(const PlanDev &P, const W *pr, cons
             }
         }
     } else {
-        // pass 1a: the smallest entry of every coset, then the smallest key
-        uint32_t cmin[kTorusMaxCosets];
-        uint32_t ball = 0xFFFFu;
-#pragma unroll
-        for (uint32_t p = 0; p < kTorusMaxCosets; ++p) {
-            cmin[p] = 0xFFFFu;
-            if (p >= ncos) continue;
-            u16x2 m = {0xFFFFu, 0xFFFFu};
-#pragma unroll
-            for (uint32_t b0 = 0; b0 < (LY ? LY : 1u); ++b0) {
-                for (uint32_t b1 = 0; b1 < (LY ? 1u : Ly); ++b1) {
-                    const uint32_t b = LY ? b0 : uni(b1);
-                    m = __builtin_elementwise_min(m, __builtin_bit_cast(u16x2, entry(pair_of(LS_IMG(p), b))));
-                }
-            }
-            cmin[p] = nz == 2 ? min(static_cast<uint32_t>(m.x), static_cast<uint32_t>(m.y))
-                              : static_cast<uint32_t>(m.x);
-            ball = min(ball, cmin[p]);
-        }
-        const uint32_t best = ball >> 4;
-        uint32_t cm = 0;
-#pragma unroll
-        for (uint32_t p = 0; p < kTorusMaxCosets; ++p) cm |= ((cmin[p] >> 4) == best ? 1u : 0u) << p;
         // pass 1b: in those cosets only, which (p, b, f) reach it
         // (bit (p*ly + b)*nz + f)
         uint64_t M0 = 0, M1 = 0;
