@@ -72,16 +72,17 @@ def sector_dimension(sector) -> int:
 
 
 def _search_bytes(dim: int) -> int:
-    """Hash index of the basis build: 16-byte slots, a power of two at least
-    twice the dimension (three quarters full above 32 GiB)."""
-    cap = 1024
-    while cap < 2 * dim:
-        cap *= 2
-    if cap * 16 > 32 << 30:
+    """Hash index of the basis build: 16-byte slots, a power of two with load
+    factor at most 1/8 while the table fits 8 GiB, 1/4 within 16 GiB, 1/2
+    within 32 GiB, 3/4 within 64 GiB (the library's hash_capacity); above
+    that the bucket table (at most 2^22 + 1 four-byte offsets)."""
+    for num, den, limit in ((8, 1, 8 << 30), (4, 1, 16 << 30), (2, 1, 32 << 30), (4, 3, 64 << 30)):
         cap = 1024
-        while cap * 3 < 4 * dim:
+        while cap * den < num * dim:
             cap *= 2
-    return cap * 16
+        if cap * 16 <= limit:
+            return cap * 16
+    return ((1 << 22) + 1) * 4
 
 
 def footprint_bytes(sector, max_iter: int) -> int:
