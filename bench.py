@@ -536,6 +536,7 @@ def main():
         "roofline": roof,
         "hbm_algorithmic_gbps": alg_bytes / (kernel_ms * 1e-3) / 1e9,
         "basis_build_s": build_s,
+        "orbit_search": dict(zip(("kind", "compile_time_shape"), op.search_kind())),
     }
     if not args.no_push:
         print("[bench] push form", file=sys.stderr, flush=True)

@@ -208,6 +208,16 @@ ls_status ls_operator_store(ls_operator *op, uint64_t max_bytes, void *stream, u
  * per row.  Runs on `stream` and blocks until the count is known.          */
 ls_status ls_operator_count(const ls_operator *op, uint64_t *n_offdiag, void *stream);
 
+/* The orbit search (the representative of each generated state, Section
+ * 5.2's condition applied to a neighbour) that the products of op run:
+ * kind 0 the general walk over coset representatives, 1 rings of at most 32
+ * sites (rotations of a doubled word), 2 tori (pair-table pruned search),
+ * 3 rings of 33 to 63 sites (longest-zero-run candidates); fixed_shape 1
+ * when a torus search runs with a compile-time layout (6x6 or 4x4 with the
+ * full point group and spin inversion).  Either output may be NULL.  A
+ * query only: it launches nothing.  Errors: LS_EINVAL (NULL operator).     */
+ls_status ls_operator_search_kind(const ls_operator *op, uint32_t *kind, uint32_t *fixed_shape);
+
 /* y = H x (Section 5.3, the first listing's row-by-row ("pull") form: each
  * row's elements are generated from its representative, looked up, and
  * accumulated; no atomics, since H is Hermitian).

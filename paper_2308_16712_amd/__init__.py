@@ -67,6 +67,12 @@ def ls_operator_count(op: Operator, stream=None) -> int:
     return op.count_elements(stream)
 
 
+def ls_operator_search_kind(op: Operator):
+    """The orbit search the products run and whether a compile-time torus
+    shape is used: ("generic" | "ring32" | "torus" | "ring64", bool)."""
+    return op.search_kind()
+
+
 def ls_matvec(op: Operator, x, y=None, stream=None):
     return op.matvec(x, y, stream)
 

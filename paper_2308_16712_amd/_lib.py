@@ -21,7 +21,7 @@ _NAMES = {0: "LS_OK", 1: "LS_WNOTCONV", -1: "LS_EINVAL", -2: "LS_ENOMEM", -3: "L
 
 EXPORTS = ["ls_sector_check", "ls_sector_count", "ls_basis_build", "ls_basis_info", "ls_basis_copy", "ls_basis_destroy", "ls_state_info",
            "ls_index_lookup", "ls_operator_create", "ls_operator_destroy", "ls_operator_info",
-           "ls_operator_count", "ls_operator_store", "ls_matvec", "ls_matvec_push",
+           "ls_operator_count", "ls_operator_store", "ls_operator_search_kind", "ls_matvec", "ls_matvec_push",
            "ls_batch_create", "ls_batch_matvec", "ls_batch_info", "ls_batch_set_graph", "ls_batch_destroy",
            "ls_lanczos", "ls_solver_footprint", "ls_solver_create", "ls_solver_step", "ls_solver_result",
            "ls_solver_destroy", "ls_last_error", "ls_version"]
@@ -77,6 +77,7 @@ def load(path: str = LIB_PATH):
         "ls_operator_destroy": ([P], None),
         "ls_operator_info": ([P, P, P], i32),
         "ls_operator_count": ([P, P, P], i32),
+        "ls_operator_search_kind": ([P, P, P], i32),
         "ls_matvec": ([P, u32, P, P, P], i32),
         "ls_matvec_push": ([P, u32, P, P, P], i32),
         "ls_batch_create": ([u32, P, P, P], i32),
@@ -278,6 +279,16 @@ class Operator:
         n = ctypes.c_uint64()
         _check(load().ls_operator_count(self._h, ctypes.byref(n), _stream_ptr(stream)))
         return int(n.value)
+
+    SEARCH_KINDS = ("generic", "ring32", "torus", "ring64")
+
+    def search_kind(self):
+        """(orbit search of the products, compile-time torus shape) as
+        ("generic" | "ring32" | "torus" | "ring64", bool) (ls_operator_search_kind)."""
+        k = ctypes.c_uint32()
+        f = ctypes.c_uint32()
+        _check(load().ls_operator_search_kind(self._h, ctypes.byref(k), ctypes.byref(f)))
+        return self.SEARCH_KINDS[k.value], bool(f.value)
 
     def store(self, max_bytes: int = 2**64 - 1, stream=None) -> int:
         """Keep the matrix elements in device memory for later products

@@ -228,6 +228,17 @@ ls_status ls_operator_count(const ls_operator *op, uint64_t *n_offdiag, void *st
     });
 }
 
+ls_status ls_operator_search_kind(const ls_operator *op, uint32_t *kind, uint32_t *fixed_shape) {
+    return guarded([&] {
+        LS_REQUIRE(op != nullptr, "operator must not be NULL");
+        uint32_t k = 0, f = 0;
+        ls::search_kind(op, &k, &f);
+        if (kind) *kind = k;
+        if (fixed_shape) *fixed_shape = f;
+        return LS_OK;
+    });
+}
+
 ls_status ls_matvec(const ls_operator *op, uint32_t nrhs, const void *d_x, void *d_y, void *stream) {
     return guarded([&] {
         LS_REQUIRE(op != nullptr, "operator must not be NULL");

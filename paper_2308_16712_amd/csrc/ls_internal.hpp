@@ -204,6 +204,9 @@ void compile_terms(const ls_basis *b, uint32_t n_terms, const ls_term *terms, ls
 // matvec.hip
 uint32_t matvec_max_terms();   // the term table is staged in LDS
 uint64_t count_elements(const ls_operator *op, hipStream_t stream);
+// Orbit search the products of op use (OrbitKind) and whether a torus
+// search runs with a compile-time shape.
+void search_kind(const ls_operator *op, uint32_t *kind, uint32_t *fixed_shape);
 void launch_matvec(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t stream);
 // Push (transposed, atomic) form of the product; y is zeroed first.
 void launch_matvec_push(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t stream);

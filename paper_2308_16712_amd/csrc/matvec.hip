@@ -119,6 +119,12 @@ uint64_t count_elements(const ls_operator *op, hipStream_t st) {
 
 uint32_t matvec_max_terms() { return kMaxLdsTerms; }
 
+void search_kind(const ls_operator *op, uint32_t *kind, uint32_t *fixed_shape) {
+    const Variant v = variant_of(op);
+    *kind = static_cast<uint32_t>(v.kind);
+    *fixed_shape = v.lx != 0 ? 1u : 0u;
+}
+
 MatvecJob job_of(const ls_operator *op, const void *x, void *y, uint32_t ld, uint32_t col) {
     const ls_basis *b = op->basis;
     MatvecJob a{};

@@ -111,6 +111,7 @@ def test_null_arguments():
     m = ctypes.c_uint64()
     assert L.ls_sector_count(None, 0, 1, ctypes.byref(m), None, None) == _lib.LS_EINVAL
     assert L.ls_operator_store(None, 0, None, None) == _lib.LS_EINVAL
+    assert L.ls_operator_search_kind(None, None, None) == _lib.LS_EINVAL
     g = lattice.ring_group(6, 0)
     with pytest.raises(_lib.LSError) as e:     # rank_begin > rank_end
         _lib.sector_count(6, 3, g.perm, g.flip, g.chi, 5, 4)
@@ -121,7 +122,8 @@ def test_null_arguments():
 
 def test_binding_names_match_abi():
     for name in ("ls_basis_build", "ls_state_info", "ls_index_lookup", "ls_matvec", "ls_lanczos",
-                 "ls_operator_create", "ls_operator_store", "ls_operator_count", "ls_matvec_push", "ls_sector_count",
+                 "ls_operator_create", "ls_operator_store", "ls_operator_count", "ls_operator_search_kind", "ls_matvec_push",
+                 "ls_sector_count",
                  "ls_sector_check", "ls_batch_create", "ls_batch_matvec"):
         assert callable(getattr(ls, name))
 

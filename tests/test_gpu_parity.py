@@ -312,14 +312,28 @@ def test_full_ring32_symmetric():
     sec = configs.ring32_symmetric()
     dim = ref.character_dimension(sec.group, 16)
     assert dim == 4707969
-    _full_size_checks(sec, dim)
+    b, op = _full_size_checks(sec, dim)
+    assert op.search_kind() == ("ring32", False)
 
 
 def test_full_square6x6_j1j2():
     sec = configs.square_j1j2()
     dim = ref.character_dimension(sec.group, 18)
     assert dim == 15804956
-    _full_size_checks(sec, dim, n_sample=200, n_rows=60)
+    b, op = _full_size_checks(sec, dim, n_sample=200, n_rows=60)
+    # the timed configuration runs the pruned torus search with its
+    # compile-time layout (a fallback would still pass the checks above)
+    assert op.search_kind() == ("torus", True)
+
+
+@pytest.mark.parametrize("name,want", [("ringD16_0pp", ("ring32", False)), ("ring40_w3_D", ("ring64", False)),
+                                       ("torus4x4_full", ("torus", True)), ("torus6x6_w4_k10", ("torus", False)),
+                                       ("trivial11_noU1", ("generic", False))])
+def test_search_kind(name, want):
+    sec = next(s for s in SMALL if s.name == name)
+    P, reps, stab, b, op = _built(sec)
+    assert op.search_kind() == want
+    assert ls.ls_operator_search_kind(op) == want
 
 
 def test_full_chain40_paper_workload():
