@@ -377,17 +377,36 @@ int orbit_kind(const GroupPlan &p) {
 
 uint64_t grid_for(uint64_t n) { return (n + kBlock - 1) / kBlock; }
 
+// Device scratch of a build, allocated and released in order on the build's
+// stream: unlike hipFree, hipFreeAsync does not wait for the whole device,
+// so a build beside running products (the serving loop) is not held up by
+// them.
+struct StreamBuf {
+    void *p = nullptr;
+    hipStream_t st;
+    StreamBuf(size_t bytes, hipStream_t s) : st(s) { LS_HIP_CHECK(hipMallocAsync(&p, bytes, s)); }
+    ~StreamBuf() {
+        if (p) (void)hipFreeAsync(p, st);
+    }
+    StreamBuf(const StreamBuf &) = delete;
+    StreamBuf &operator=(const StreamBuf &) = delete;
+    template <class T>
+    T *as() const {
+        return static_cast<T *>(p);
+    }
+};
+
 template <typename W>
 void enumerate_impl(ls_basis *b, hipStream_t st, uint64_t total, uint64_t **out_reps, uint64_t *out_dim) {
     const GroupPlan &gp = b->plan;
     const uint64_t lanes = (total + kCandPerLane - 1) / kCandPerLane;
     const uint64_t blocks = grid_for(lanes);
-    uint64_t *marks = nullptr, *offsets = nullptr, *d_total = nullptr;
-    uint32_t *counts = nullptr;
-    LS_HIP_CHECK(hipMalloc(&marks, std::max<uint64_t>(lanes, 1) * sizeof(uint64_t)));
-    LS_HIP_CHECK(hipMalloc(&counts, std::max<uint64_t>(blocks, 1) * sizeof(uint32_t)));
-    LS_HIP_CHECK(hipMalloc(&offsets, std::max<uint64_t>(blocks, 1) * sizeof(uint64_t)));
-    LS_HIP_CHECK(hipMalloc(&d_total, sizeof(uint64_t)));
+    StreamBuf marks_b(std::max<uint64_t>(lanes, 1) * sizeof(uint64_t), st);
+    StreamBuf counts_b(std::max<uint64_t>(blocks, 1) * sizeof(uint32_t), st);
+    StreamBuf offsets_b(std::max<uint64_t>(blocks, 1) * sizeof(uint64_t), st);
+    StreamBuf total_b(sizeof(uint64_t), st);
+    uint64_t *marks = marks_b.as<uint64_t>(), *offsets = offsets_b.as<uint64_t>(), *d_total = total_b.as<uint64_t>();
+    uint32_t *counts = counts_b.as<uint32_t>();
     EnumArgs a{};
     a.plan = b->plan_dev;
     a.binom = b->d_binom;
@@ -419,11 +438,11 @@ void enumerate_impl(ls_basis *b, hipStream_t st, uint64_t total, uint64_t **out_
         hipLaunchKernelGGL((k_enum_write<W>), dim3(blocks), dim3(kBlock), 0, st, a);
         LS_HIP_CHECK(hipGetLastError());
     }
-    LS_HIP_CHECK(hipStreamSynchronize(st));
-    hipFree(marks);
-    hipFree(counts);
-    hipFree(offsets);
-    hipFree(d_total);
+    const hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        (void)hipFree(reps);
+        LS_HIP_CHECK(e);
+    }
     *out_reps = reps;
     *out_dim = dim;
 }
@@ -522,10 +541,10 @@ uint64_t count_impl(ls_basis *b, uint64_t begin, uint64_t end, hipStream_t st) {
     // workgroups (1.7e10 candidates, a fraction of a second)
     constexpr uint32_t kPerLane = kCandPerLane;
     constexpr uint64_t kSpan = (1ull << 20) * kBlock * kPerLane;
-    unsigned long long *acc = nullptr;
-    LS_HIP_CHECK(hipMalloc(&acc, sizeof(unsigned long long)));
+    StreamBuf acc_b(sizeof(unsigned long long), st);
+    unsigned long long *acc = acc_b.as<unsigned long long>();
     unsigned long long total = 0;
-    try {
+    {
         LS_HIP_CHECK(hipMemsetAsync(acc, 0, sizeof(unsigned long long), st));
         EnumArgs a{};
         a.plan = b->plan_dev;
@@ -549,11 +568,7 @@ uint64_t count_impl(ls_basis *b, uint64_t begin, uint64_t end, hipStream_t st) {
         }
         LS_HIP_CHECK(hipMemcpyAsync(&total, acc, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         LS_HIP_CHECK(hipStreamSynchronize(st));
-    } catch (...) {
-        hipFree(acc);
-        throw;
     }
-    hipFree(acc);
     return static_cast<uint64_t>(total);
 }
 
