@@ -198,6 +198,7 @@ def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=N
     queue: List = []
     live: List[_Live] = []
     building = []           # (request, bytes, record, future)
+    needs = {}              # request id -> footprint bytes
     stats = ServeStats()
     step_stream = torch.cuda.Stream()
     build_stream = torch.cuda.Stream()
@@ -234,7 +235,9 @@ def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=N
                     i += 1
                 # first-fit admission in arrival order; the build starts now
                 for req in list(queue):
-                    need = footprint_bytes(req.sector, max_iter)
+                    if req.rid not in needs:     # the character formula runs once per request
+                        needs[req.rid] = footprint_bytes(req.sector, max_iter)
+                    need = needs[req.rid]
                     if need > hbm_budget:
                         raise ValueError(f"request {req.rid} needs {need} bytes, more than the whole budget")
                     with lock:
