@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(256) k_spmv(const uint64_t *off, const uint32_
     // U elements per step: their columns, values and x gathers are all issued
     // before the first add, so U gathers per lane are in flight at once; the
     // adds keep the element order (same bits as the one-by-one loop).
-    constexpr int U = NR == 1 ? 4 : NR == 2 ? 2 : 1;
+    constexpr int U = NR == 1 ? (CPLX ? 8 : 16) : NR == 2 ? 4 : 1;
     uint32_t k = 0;
     for (; k + U <= w; k += U) {
         uint32_t j[U];
