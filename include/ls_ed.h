@@ -214,8 +214,10 @@ ls_status ls_operator_count(const ls_operator *op, uint64_t *n_offdiag, void *st
  * sites (rotations of a doubled word), 2 tori (pair-table pruned search),
  * 3 rings of 33 to 63 sites (longest-zero-run candidates); fixed_shape 1
  * when a torus search runs with a compile-time layout (6x6 or 4x4 with the
- * full point group and spin inversion).  Either output may be NULL.  A
- * query only: it launches nothing.  Errors: LS_EINVAL (NULL operator).     */
+ * full point group and spin inversion).  For an operator with stored
+ * elements (ls_operator_store) it is the search the store ran; its products
+ * read the stored elements.  Either output may be NULL.  A query only: it
+ * launches nothing.  Errors: LS_EINVAL (NULL operator).                    */
 ls_status ls_operator_search_kind(const ls_operator *op, uint32_t *kind, uint32_t *fixed_shape);
 
 /* y = H x (Section 5.3, the first listing's row-by-row ("pull") form: each
