@@ -434,11 +434,12 @@ void enumerate_impl(ls_basis *b, hipStream_t st, uint64_t total, uint64_t **out_
     uint64_t *reps = nullptr;
     LS_HIP_CHECK(hipMalloc(&reps, std::max<uint64_t>(dim, 1) * sizeof(uint64_t)));
     a.reps = reps;
+    hipError_t e = hipSuccess;
     if (dim > 0) {
         hipLaunchKernelGGL((k_enum_write<W>), dim3(blocks), dim3(kBlock), 0, st, a);
-        LS_HIP_CHECK(hipGetLastError());
+        e = hipGetLastError();
     }
-    const hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         (void)hipFree(reps);
         LS_HIP_CHECK(e);
