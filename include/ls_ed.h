@@ -151,6 +151,16 @@ ls_status ls_basis_copy(const ls_basis *basis, uint64_t *d_reps_out, uint16_t *d
 /* Frees the handle and its device memory (after synchronizing the device). */
 void ls_basis_destroy(ls_basis *basis);
 
+/* Test hook for the lookup-miss error path (host-forced fault injection):
+ * takes the representative at position `index` out of the basis's hash
+ * index, so ls_index_lookup returns -1 for it and every product that meets
+ * it raises its operator's error flag (ls_operator_check).  The basis is
+ * changed for good: use it on a basis built for the purpose.  Blocks until
+ * done on `stream`.
+ * Errors: LS_EINVAL (NULL basis, index >= dim, a search layout other than
+ * the hash index, or no unused key value above the representatives).      */
+ls_status ls_basis_test_drop_key(ls_basis *basis, uint64_t index, void *stream);
+
 /* Per state: its representative (orbit minimum), the character chi(g*) of
  * an element g* with g*.s = rep, and norm = sqrt(stab/|G|) with stab the
  * stabilizer size (the norm of P|rep>).  A state of the wrong Hamming
@@ -199,7 +209,9 @@ ls_status ls_operator_info(const ls_operator *op, int *is_complex, uint64_t *dim
  * results bit for bit.  Storing again is a no-op.  This call changes the
  * operator: make it before the handle is shared by concurrent calls.
  * Blocks until the store on `stream` has finished; costs about one product.
- * Errors: LS_EINVAL (NULL operator), LS_ENOMEM, LS_EDEVICE.                 */
+ * Errors: LS_EINVAL (NULL operator), LS_ENOMEM, LS_EDEVICE, LS_EINTERNAL
+ * (the store met a lookup miss of an in-sector representative; nothing is
+ * kept).                                                                   */
 ls_status ls_operator_store(ls_operator *op, uint64_t max_bytes, void *stream, uint64_t *bytes);
 
 /* Number of off-diagonal element applications of one product: the sum over
@@ -229,8 +241,24 @@ ls_status ls_operator_search_kind(const ls_operator *op, uint32_t *kind, uint32_
  *   d_y    same shape, must not overlap d_x.  (out)
  * Errors: LS_EINVAL (NULL handle or vector, nrhs out of range, x and y
  * overlapping).  A neighbour whose representative is not in the basis
- * belongs to an orbit the projector annihilates and contributes zero.     */
+ * contributes zero when its orbit is annihilated by the projector (an
+ * element fixing it has a character other than 1).  Any other miss -- a
+ * representative of the sector that stateToIndex does not find, which
+ * Section 5.3's lookup presumes cannot happen -- raises the operator's
+ * device error flag; the call itself returns before the product has run,
+ * and the flag is reported by the next ls_operator_check (or ls_lanczos,
+ * ls_solver_step, ls_operator_store) on the operator.                      */
 ls_status ls_matvec(const ls_operator *op, uint32_t nrhs, const void *d_x, void *d_y, void *stream);
+
+/* Waits for `stream`, then reports whether a product of op (ls_matvec,
+ * ls_matvec_push, batched or fused products) since the last check met a
+ * neighbour whose representative lies in the sector but is missing from
+ * the basis (an inconsistent basis or search layout: Section 5.3's
+ * stateToIndex presumes every such state is present).  Clears the flag.
+ * The flag belongs to the operator: calls on several streams that share an
+ * operator share it.  Returns LS_OK, or LS_EINTERNAL when the flag was set
+ * (the products' outputs are then not valid).                              */
+ls_status ls_operator_check(const ls_operator *op, void *stream);
 
 /* y = H x in the push (transposed) form of Section 5.3's second listing, a
  * comparison variant of ls_matvec: each row's elements H_ij are generated
@@ -313,6 +341,8 @@ typedef struct {
 
 ls_status ls_lanczos(const ls_operator *op, const ls_lanczos_opts *opts, void *stream,
                      double *e0, uint32_t *iters, double *resid_bound);
+/* (ls_lanczos also returns LS_EINTERNAL, at the step where it happens, when
+ * a product met a lookup miss of an in-sector representative.)             */
 
 /* ---- Lanczos stepper for serving ------------------------------------------
  * A solver holds one Lanczos solve (the recurrence, start vector, stop rule
@@ -333,12 +363,18 @@ ls_status ls_solver_footprint(const ls_operator *op, uint32_t max_iter, uint64_t
  * Errors: LS_EINVAL, LS_ENOMEM when the Krylov space does not fit.         */
 ls_status ls_solver_create(const ls_operator *op, const ls_lanczos_opts *opts, void *stream, ls_solver **out);
 
-/* One iteration for each of the n solvers (host array; done ones skipped). */
+/* One iteration for each of the n solvers (host array; done ones skipped).
+ * A solve whose product met a lookup miss of an in-sector representative
+ * (see ls_operator_check) is stopped without taking the step; the other
+ * solves complete theirs, and the call returns LS_EINTERNAL naming how many
+ * were stopped (ls_solver_result tells which).                             */
 ls_status ls_solver_step(ls_solver *const *solvers, uint32_t n, void *stream);
 
 /* Current lowest Ritz value, steps taken, residual bound, whether the solve
- * is finished (converged, max_iter reached or Krylov space exhausted) and
- * whether the tolerance was met.  Any output may be NULL.                  */
+ * is finished (converged, max_iter reached, Krylov space exhausted, or
+ * stopped) and whether the tolerance was met.  Any output may be NULL.
+ * Returns LS_EINTERNAL (outputs filled as they stand) for a solve that
+ * ls_solver_step stopped because its product met a lookup miss.           */
 ls_status ls_solver_result(const ls_solver *solver, double *e0, uint32_t *iters, double *resid_bound, int *done,
                            int *converged);
 

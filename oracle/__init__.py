@@ -8,8 +8,10 @@ no code with the GPU library; the only module both use is ``workloads``
 Contents:
   * C core (``oracle.c``): brute-force orbit search, Gosper enumeration,
     hash-map index, column-by-column product, getRow.
-  * Here: ctypes marshalling, and the Lanczos recurrence in FP64 numpy with
-    the tridiagonal eigenproblem solved by SciPy (a library primitive).
+  * Here: ctypes marshalling (optionally split over host threads), the
+    sector Hamiltonian assembled from getRow as a SciPy sparse matrix, and
+    the Lanczos recurrence in FP64 numpy with the tridiagonal eigenproblem
+    solved by SciPy (library primitives).
 
 Parity pins of every function live in ``tests/test_oracle_*.py``.
 """
@@ -102,14 +104,35 @@ def count_basis(prob: Problem) -> int:
     return int(lib().orc_enumerate(prob.ptr, None, None, 0))
 
 
-def state_info(prob: Problem, states) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+def _workers(workers) -> int:
+    if workers is None or workers <= 0:
+        return max(1, min(16, os.cpu_count() or 1))
+    return int(workers)
+
+
+def state_info(prob: Problem, states, workers: int = 1) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """(representative, chi(g*), norm) per state.  With workers > 1 the
+    states are split into contiguous chunks handled by host threads (the C
+    core releases the interpreter lock); each state's result is the same."""
     s = np.ascontiguousarray(states, dtype=np.uint64)
     n = s.shape[0]
     reps = np.zeros(n, np.uint64)
     chi = np.zeros((n, 2), np.float64)
     norm = np.zeros(n, np.float64)
-    lib().orc_state_info(prob.ptr, n, s.ctypes.data, reps.ctypes.data, chi.ctypes.data,
-                         norm.ctypes.data)
+    nw = _workers(workers)
+
+    def run(lo, hi):
+        if hi > lo:
+            lib().orc_state_info(prob.ptr, hi - lo, s[lo:].ctypes.data, reps[lo:].ctypes.data,
+                                 chi[lo:].ctypes.data, norm[lo:].ctypes.data)
+
+    if nw == 1 or n < 4096:
+        run(0, n)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        step = max(4096, -(-n // (nw * 8)))
+        with ThreadPoolExecutor(max_workers=nw) as ex:
+            list(ex.map(lambda lo: run(lo, min(n, lo + step)), range(0, n, step)))
     return reps, chi[:, 0] + 1j * chi[:, 1], norm
 
 
@@ -172,6 +195,39 @@ def dense(prob: Problem, reps, stab) -> np.ndarray:
     """The sector Hamiltonian as a dense matrix, one column per unit vector."""
     d = len(reps)
     return matvec(prob, reps, stab, np.eye(d, dtype=np.complex128))
+
+
+def get_rows(prob: Problem, rs, workers: int = 1):
+    """get_row for every representative in rs (host threads when workers > 1)."""
+    rs = [int(r) for r in rs]
+    nw = _workers(workers)
+    if nw == 1 or len(rs) < 64:
+        return [get_row(prob, r) for r in rs]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=nw) as ex:
+        return list(ex.map(lambda r: get_row(prob, r), rs, chunksize=64))
+
+
+def sparse_matrix(prob: Problem, reps, workers: int = 1):
+    """The sector Hamiltonian as a SciPy CSR matrix assembled row by row from
+    getRow (Section 5.3): row i holds <r~_i|H|r~_j> at the index j of each
+    neighbour's representative (entries of one (i, j) summed).  Same elements
+    as the column-by-column product, in a form a library sparse product can
+    apply many times (Lanczos parity at sizes where the column loop is slow)."""
+    import scipy.sparse as sp
+    reps = np.ascontiguousarray(reps, dtype=np.uint64)
+    d = reps.shape[0]
+    rows = get_rows(prob, reps, workers)
+    cnt = np.array([len(nb) for nb, _ in rows], dtype=np.int64)
+    nb = np.concatenate([r[0] for r in rows]) if d else np.zeros(0, np.uint64)
+    coef = np.concatenate([r[1] for r in rows]) if d else np.zeros(0, np.complex128)
+    cols = index_lookup(reps, nb)
+    if np.any(cols < 0):
+        raise RuntimeError("oracle: a neighbour representative in the sector is missing")
+    ri = np.repeat(np.arange(d, dtype=np.int64), cnt)
+    if prob.is_real:
+        coef = coef.real.copy()
+    return sp.csr_matrix((coef, (ri, cols)), shape=(d, d))
 
 
 def cgs_selective(Vm: np.ndarray, w: np.ndarray):

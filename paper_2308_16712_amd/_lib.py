@@ -21,7 +21,8 @@ _NAMES = {0: "LS_OK", 1: "LS_WNOTCONV", -1: "LS_EINVAL", -2: "LS_ENOMEM", -3: "L
 
 EXPORTS = ["ls_sector_check", "ls_sector_count", "ls_basis_build", "ls_basis_info", "ls_basis_copy", "ls_basis_destroy", "ls_state_info",
            "ls_index_lookup", "ls_operator_create", "ls_operator_destroy", "ls_operator_info",
-           "ls_operator_count", "ls_operator_store", "ls_operator_search_kind", "ls_matvec", "ls_matvec_push",
+           "ls_operator_count", "ls_operator_store", "ls_operator_search_kind", "ls_operator_check",
+           "ls_basis_test_drop_key", "ls_matvec", "ls_matvec_push",
            "ls_batch_create", "ls_batch_matvec", "ls_batch_info", "ls_batch_set_graph", "ls_batch_destroy",
            "ls_lanczos", "ls_solver_footprint", "ls_solver_create", "ls_solver_step", "ls_solver_result",
            "ls_solver_destroy", "ls_last_error", "ls_version"]
@@ -78,6 +79,8 @@ def load(path: str = LIB_PATH):
         "ls_operator_info": ([P, P, P], i32),
         "ls_operator_count": ([P, P, P], i32),
         "ls_operator_search_kind": ([P, P, P], i32),
+        "ls_operator_check": ([P, P], i32),
+        "ls_basis_test_drop_key": ([P, u64, P], i32),
         "ls_matvec": ([P, u32, P, P, P], i32),
         "ls_matvec_push": ([P, u32, P, P, P], i32),
         "ls_batch_create": ([u32, P, P, P], i32),
@@ -123,6 +126,48 @@ def _dptr(t) -> ctypes.c_void_p:
     if not t.is_contiguous():
         raise ValueError("device buffers must be contiguous")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _vector(t, dim: int, cplx: bool, name: str, max_rhs: int = 64) -> int:
+    """Checks a device vector [dim] or [dim][nrhs] of the operator's element
+    type before its pointer reaches the library (a wrong dtype or a short
+    buffer would make the kernels read or write past the allocation).
+    Returns nrhs."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    want = torch.complex128 if cplx else torch.float64
+    if t.dtype != want:
+        raise TypeError(f"{name} must be {want}, got {t.dtype}")
+    if t.dim() not in (1, 2) or t.shape[0] != dim:
+        raise ValueError(f"{name} must have shape [{dim}] or [{dim}][nrhs], got {tuple(t.shape)}")
+    nrhs = 1 if t.dim() == 1 else int(t.shape[1])
+    if not 1 <= nrhs <= max_rhs:
+        raise ValueError(f"{name}: nrhs must be in 1..{max_rhs}")
+    _dptr(t)   # on the GPU, contiguous
+    return nrhs
+
+
+def _same_as(y, x, name: str = "y"):
+    import torch
+    if not isinstance(y, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if y.dtype != x.dtype or tuple(y.shape) != tuple(x.shape) or y.device != x.device:
+        raise ValueError(f"{name} must match x in dtype, shape and device "
+                         f"({y.dtype}, {tuple(y.shape)}, {y.device} vs {x.dtype}, {tuple(x.shape)}, {x.device})")
+    _dptr(y)
+
+
+def _states(t, name: str):
+    """A device array of basis states / keys: 1-D int64 (uint64 bit patterns)."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype not in (torch.int64, getattr(torch, "uint64", torch.int64)):
+        raise TypeError(f"{name} must hold 64-bit states (int64 or uint64), got {t.dtype}")
+    if t.dim() != 1:
+        raise ValueError(f"{name} must be one-dimensional")
+    _dptr(t)
 
 
 def sector_check(n_sites: int, hamming_weight: int, perm, flip, chi) -> dict:
@@ -198,6 +243,7 @@ class Basis:
 
     def state_info(self, states, stream=None):
         import torch
+        _states(states, "states")
         n = states.numel()
         reps = torch.empty(n, dtype=torch.int64, device=states.device)
         chi = torch.empty((n, 2), dtype=torch.float64, device=states.device)
@@ -209,11 +255,18 @@ class Basis:
 
     def index_lookup(self, keys, stream=None):
         import torch
+        _states(keys, "keys")
         n = keys.numel()
         out = torch.empty(n, dtype=torch.int64, device=keys.device)
         if n:
             _check(load().ls_index_lookup(self._h, n, _dptr(keys), _dptr(out), _stream_ptr(stream)))
         return out
+
+    def test_drop_key(self, index: int, stream=None):
+        """Fault injection for tests: take representative `index` out of the
+        hash index so that products meeting it raise the lookup-miss flag
+        (ls_basis_test_drop_key)."""
+        _check(load().ls_basis_test_drop_key(self._h, int(index), _stream_ptr(stream)))
 
     def close(self):
         if getattr(self, "_h", None):
@@ -290,6 +343,11 @@ class Operator:
         _check(load().ls_operator_search_kind(self._h, ctypes.byref(k), ctypes.byref(f)))
         return self.SEARCH_KINDS[k.value], bool(f.value)
 
+    def check(self, stream=None):
+        """Raise LSError(LS_EINTERNAL) when a product since the last check met a
+        lookup miss of an in-sector representative (ls_operator_check)."""
+        _check(load().ls_operator_check(self._h, _stream_ptr(stream)))
+
     def store(self, max_bytes: int = 2**64 - 1, stream=None) -> int:
         """Keep the matrix elements in device memory for later products
         (ls_operator_store); returns the bytes held."""
@@ -300,34 +358,30 @@ class Operator:
     def matvec(self, x, y=None, stream=None):
         """y = H x for x of shape [dim] or [dim][nrhs] (float64 / complex128)."""
         import torch
-        want = torch.complex128 if self.is_complex else torch.float64
-        if x.dtype != want:
-            raise TypeError(f"x must be {want}")
-        nrhs = 1 if x.dim() == 1 else x.shape[1]
-        if x.shape[0] != self.dim:
-            raise ValueError("x has the wrong dimension")
+        nrhs = _vector(x, self.dim, self.is_complex, "x")
         if y is None:
             y = torch.empty_like(x)
+        _same_as(y, x)
         _check(load().ls_matvec(self._h, nrhs, _dptr(x), _dptr(y), _stream_ptr(stream)))
         return y
 
     def matvec_push(self, x, y=None, stream=None):
         """y = H x in the push (transposed, atomic) form (ls_matvec_push)."""
         import torch
-        want = torch.complex128 if self.is_complex else torch.float64
-        if x.dtype != want:
-            raise TypeError(f"x must be {want}")
-        nrhs = 1 if x.dim() == 1 else x.shape[1]
-        if x.shape[0] != self.dim:
-            raise ValueError("x has the wrong dimension")
+        nrhs = _vector(x, self.dim, self.is_complex, "x")
         if y is None:
             y = torch.empty_like(x)
+        _same_as(y, x)
         _check(load().ls_matvec_push(self._h, nrhs, _dptr(x), _dptr(y), _stream_ptr(stream)))
         return y
 
     def lanczos(self, max_iter: int, tol: float = 0.0, seed: int = 1, v0=None, reorth=True,
                 stream=None):
         m = int(max_iter)
+        if m < 1:
+            raise ValueError("max_iter must be >= 1")
+        if v0 is not None:
+            _vector(v0, self.dim, self.is_complex, "v0", max_rhs=1)
         alpha = np.zeros(m)
         beta = np.zeros(m)
         opts = LanczosOpts(m, reorth_code(reorth), float(tol), int(seed),
@@ -360,6 +414,10 @@ class Solver:
     def __init__(self, op: "Operator", max_iter: int, tol: float = 0.0, seed: int = 1, v0=None,
                  reorth=True, stream=None):
         self.op = op
+        if int(max_iter) < 1:
+            raise ValueError("max_iter must be >= 1")
+        if v0 is not None:
+            _vector(v0, op.dim, op.is_complex, "v0", max_rhs=1)
         opts = LanczosOpts(int(max_iter), reorth_code(reorth), float(tol), int(seed),
                            _dptr(v0) if v0 is not None else None, None, None)
         h = ctypes.c_void_p()
@@ -426,10 +484,10 @@ class Batch:
         n = len(self.ops)
         if len(xs) != n or len(ys) != n:
             raise ValueError("one x and one y per operator")
-        for op, x, y, r in zip(self.ops, xs, ys, self.nrhs):
-            want = (op.dim, r) if r > 1 else (op.dim,)
-            if tuple(x.shape) not in (want, (op.dim, r)) or tuple(y.shape) != tuple(x.shape):
-                raise ValueError("x/y shape does not match the operator and nrhs")
+        for k, (op, x, y, r) in enumerate(zip(self.ops, xs, ys, self.nrhs)):
+            if _vector(x, op.dim, op.is_complex, f"xs[{k}]") != r:
+                raise ValueError(f"xs[{k}] does not have nrhs = {r} columns")
+            _same_as(y, x, f"ys[{k}]")
         px = (ctypes.c_void_p * n)(*[_dptr(x).value for x in xs])
         py = (ctypes.c_void_p * n)(*[_dptr(y).value for y in ys])
         _check(load().ls_batch_matvec(self._h, px, py, _stream_ptr(stream)))

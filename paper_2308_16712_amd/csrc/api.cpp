@@ -178,12 +178,16 @@ ls_status ls_operator_create(const ls_basis *b, uint32_t n_terms, const ls_term 
             LS_HIP_CHECK(hipMemcpy(op->d_cflip, op->host_cflip.data(), op->host_cflip.size() * sizeof(uint64_t),
                                    hipMemcpyHostToDevice));
         }
+        LS_HIP_CHECK(hipMalloc(&op->d_err, sizeof(uint32_t)));
+        const uint32_t zero = 0;
+        LS_HIP_CHECK(hipMemcpy(op->d_err, &zero, sizeof(uint32_t), hipMemcpyHostToDevice));
         *out = op;
         return LS_OK;
     });
     if (st != LS_OK && op) {
         hipFree(op->d_terms);
         hipFree(op->d_cflip);
+        hipFree(op->d_err);
         delete op;
     }
     return st;
@@ -194,6 +198,7 @@ void ls_operator_destroy(ls_operator *op) {
     hipDeviceSynchronize();
     hipFree(op->d_terms);
     hipFree(op->d_cflip);
+    hipFree(op->d_err);
     hipFree(op->d_st_off);
     hipFree(op->d_st_width);
     hipFree(op->d_st_cols);
@@ -224,6 +229,23 @@ ls_status ls_operator_count(const ls_operator *op, uint64_t *n_offdiag, void *st
     return guarded([&] {
         LS_REQUIRE(op != nullptr && n_offdiag != nullptr, "operator and output must not be NULL");
         *n_offdiag = ls::count_elements(op, as_stream(stream));
+        return LS_OK;
+    });
+}
+
+ls_status ls_operator_check(const ls_operator *op, void *stream) {
+    return guarded([&] {
+        LS_REQUIRE(op != nullptr, "operator must not be NULL");
+        ls::check_operator(op, as_stream(stream));
+        return LS_OK;
+    });
+}
+
+ls_status ls_basis_test_drop_key(ls_basis *b, uint64_t index, void *stream) {
+    return guarded([&] {
+        LS_REQUIRE(b != nullptr, "basis must not be NULL");
+        LS_REQUIRE(index < b->dim, "index must be below the dimension");
+        ls::drop_key(b, index, as_stream(stream));
         return LS_OK;
     });
 }
@@ -337,6 +359,9 @@ ls_status ls_solver_result(const ls_solver *solver, double *e0, uint32_t *iters,
     return guarded([&] {
         LS_REQUIRE(solver != nullptr, "solver must not be NULL");
         ls::solver_result(solver, e0, iters, resid_bound, done, converged);
+        if (ls::solver_failed(solver))
+            throw ls::Error{LS_EINTERNAL, "the solve was stopped: its product met a neighbour whose "
+                                          "representative lies in the sector but is missing from the basis"};
         return LS_OK;
     });
 }

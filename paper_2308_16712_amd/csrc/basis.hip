@@ -325,6 +325,23 @@ __global__ void __launch_bounds__(kBlock) k_hash_insert(const uint64_t *reps, co
     }
 }
 
+// Test hook: the slot holding `key` gets `repl`, a key above every
+// representative (lookups above kmax stop before probing), so the slot stays
+// occupied, the probe sequences through it still end, and `key` misses.
+// One thread; the walk is bounded by the table size.
+__global__ void k_drop_key(HashSlot *table, uint64_t mask, uint32_t shift, uint64_t key, uint64_t repl) {
+    uint64_t s = slot_of(key, shift);
+    for (uint64_t n = 0; n <= mask; ++n) {
+        const uint64_t k = table[s].key;
+        if (k == key) {
+            table[s].key = repl;
+            return;
+        }
+        if (k == kEmptyKey) return;
+        s = (s + 1) & mask;
+    }
+}
+
 template <typename W, int KIND>
 __global__ void __launch_bounds__(kBlock) k_state_info(PlanDev P, int32_t weight, uint64_t n, const uint64_t *states,
                                                        uint64_t *reps, double *chi, double *norm) {
@@ -650,6 +667,18 @@ void build_basis(ls_basis *b, hipStream_t st) {
         LS_HIP_CHECK(hipGetLastError());
         S.buckets = b->d_buckets;
     }
+    LS_HIP_CHECK(hipStreamSynchronize(st));
+}
+
+void drop_key(ls_basis *b, uint64_t index, hipStream_t st) {
+    const SearchDev &S = b->search_dev;
+    LS_REQUIRE(S.mode == kLookupHash, "only a hash search layout can drop a key");
+    LS_REQUIRE(S.kmax + 1 != kEmptyKey, "no free key value above the representatives");
+    uint64_t key = 0;
+    LS_HIP_CHECK(hipMemcpyAsync(&key, b->d_reps + index, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    LS_HIP_CHECK(hipStreamSynchronize(st));
+    hipLaunchKernelGGL(k_drop_key, dim3(1), dim3(1), 0, st, b->d_table, S.hash_mask, S.hash_shift, key, S.kmax + 1);
+    LS_HIP_CHECK(hipGetLastError());
     LS_HIP_CHECK(hipStreamSynchronize(st));
 }
 

@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "ls_internal.hpp"
@@ -418,8 +419,14 @@ ls_status lanczos_impl(const ls_operator *op, const ls_lanczos_opts *o, hipStrea
         enqueue_reorth<CPLX>(Vb, n, static_cast<int>(k) + 1, static_cast<int>(o->reorth), w, rb, rb.nrm + 3, st);
         LS_HIP_CHECK(hipGetLastError());
         double2 wn;
+        uint32_t miss = 0;
         LS_HIP_CHECK(hipMemcpyAsync(&wn, rb.nrm + 3, sizeof(double2), hipMemcpyDeviceToHost, st));
+        enqueue_flag_read(op, &miss, st);
         LS_HIP_CHECK(hipStreamSynchronize(st));
+        if (miss)
+            throw Error{LS_EINTERNAL, "Lanczos step " + std::to_string(k) +
+                                          ": the product met a neighbour whose representative lies in the sector "
+                                          "but is missing from the basis"};
         const double bnext = std::sqrt(wn.x);
         alpha.push_back(a);
         e0 = tridiag_lowest(alpha, beta);
@@ -525,10 +532,12 @@ struct ls_solver {
     double *scal = nullptr;       // [2]: alpha_k, beta_{k+1}
     double *bprev = nullptr;      // beta_k (device copy)
     double *host = nullptr;       // pinned [2]
+    uint32_t *hflag = nullptr;    // pinned: the operator's error flag after a step
     std::vector<double> alpha, beta;
     uint32_t k = 0;
     double e0 = 0.0, resid = INFINITY, prev = 0.0;
     bool have_prev = false, done = false, converged = false;
+    bool failed = false;          // a product met a lookup miss (LS_EINTERNAL)
 };
 
 namespace ls {
@@ -548,6 +557,7 @@ void free_solver(ls_solver *s) {
     hipFree(s->scal);
     hipFree(s->bprev);
     if (s->host) hipHostFree(s->host);
+    if (s->hflag) hipHostFree(s->hflag);
     delete s;
 }
 
@@ -580,6 +590,7 @@ void enqueue_after_product(ls_solver *s, hipStream_t st) {
         LS_HIP_CHECK(hipMemcpyAsync(s->bprev, s->scal + 1, sizeof(double), hipMemcpyDeviceToDevice, st));
     }
     LS_HIP_CHECK(hipMemcpyAsync(s->host, s->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    enqueue_flag_read(s->op, s->hflag, st);
     LS_HIP_CHECK(hipGetLastError());
 }
 
@@ -636,6 +647,8 @@ ls_solver *solver_create(const ls_operator *op, const ls_lanczos_opts *o, hipStr
         LS_HIP_CHECK(hipMalloc(&s->scal, 2 * sizeof(double)));
         LS_HIP_CHECK(hipMalloc(&s->bprev, sizeof(double)));
         LS_HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&s->host), 2 * sizeof(double)));
+        LS_HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&s->hflag), sizeof(uint32_t)));
+        *s->hflag = 0;
         // start vector, normalised exactly as run_lanczos does
         const uint64_t nd = s->n * (s->cplx ? 2 : 1);
         if (o->d_v0)
@@ -692,8 +705,26 @@ void solver_step(ls_solver *const *ss, uint32_t n, hipStream_t st) {
         else enqueue_after_product<false>(s, st);
     }
     LS_HIP_CHECK(hipStreamSynchronize(st));
-    for (ls_solver *s : act) finish_step(s);
+    // a solve whose product met a lookup miss stops here (its step is not
+    // taken); the others finish theirs
+    uint32_t failed = 0;
+    for (ls_solver *s : act) {
+        if (*s->hflag) {
+            *s->hflag = 0;
+            s->failed = true;
+            s->done = true;
+            ++failed;
+        } else {
+            finish_step(s);
+        }
+    }
+    if (failed)
+        throw Error{LS_EINTERNAL, std::to_string(failed) + " of " + std::to_string(act.size()) +
+                                      " solves met a neighbour whose representative lies in the sector but is "
+                                      "missing from the basis; they are stopped (ls_solver_result reports them)"};
 }
+
+bool solver_failed(const ls_solver *s) { return s->failed; }
 
 void solver_result(const ls_solver *s, double *e0, uint32_t *iters, double *resid, int *done, int *converged) {
     if (e0) *e0 = s->e0;

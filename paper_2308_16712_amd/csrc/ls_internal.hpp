@@ -173,6 +173,10 @@ struct ls_operator {
     // applied to every off-diagonal flip mask, [n_off][kTorusCosetSlots]
     std::vector<uint64_t> host_cflip;
     uint64_t *d_cflip = nullptr;
+    // error flag: a product met a neighbour whose in-sector representative
+    // stateToIndex did not find (set by the kernels, read by ls_operator_check,
+    // ls_lanczos, ls_solver_step and ls_operator_store)
+    uint32_t *d_err = nullptr;
     // stored elements (ls_operator_store), sliced ELLPACK over 64-row slices
     bool stored = false;
     uint64_t st_slots = 0, st_bytes = 0;
@@ -187,6 +191,9 @@ namespace ls {
 
 // basis.hip
 void upload_plan(ls_basis *b);
+// Test hook: the representative at `index` is taken out of the hash index
+// (its slot keeps a key no lookup asks for), so lookups of it miss.
+void drop_key(ls_basis *b, uint64_t index, hipStream_t stream);
 // C(N, w) with U(1), else 2^N
 uint64_t candidate_count(const ls_basis *b);
 void build_basis(ls_basis *b, hipStream_t stream);
@@ -203,6 +210,12 @@ void compile_terms(const ls_basis *b, uint32_t n_terms, const ls_term *terms, ls
 
 // matvec.hip
 uint32_t matvec_max_terms();   // the term table is staged in LDS
+// Waits for `stream`; throws LS_EINTERNAL (clearing the flag) when a product
+// of op met a lookup miss of an in-sector representative.
+void check_operator(const ls_operator *op, hipStream_t stream);
+// Enqueues a copy of op's flag into host memory *dst, then a clear of the
+// flag, on `stream` (the caller synchronises before reading *dst).
+void enqueue_flag_read(const ls_operator *op, uint32_t *dst, hipStream_t stream);
 uint64_t count_elements(const ls_operator *op, hipStream_t stream);
 // Orbit search the products of op use (OrbitKind) and whether a torus
 // search runs with a compile-time shape.
@@ -234,6 +247,7 @@ ls_solver *solver_create(const ls_operator *op, const ls_lanczos_opts *o, hipStr
 void solver_destroy(ls_solver *s);
 void solver_step(ls_solver *const *solvers, uint32_t n, hipStream_t stream);
 void solver_result(const ls_solver *s, double *e0, uint32_t *iters, double *resid, int *done, int *converged);
+bool solver_failed(const ls_solver *s);   // stopped by a lookup miss in its product
 
 // lanczos.hip
 ls_status run_lanczos(const ls_operator *op, const ls_lanczos_opts *o, hipStream_t stream,

@@ -15,13 +15,19 @@ namespace {
 // 8 waves per SIMD, so two 1024-thread workgroups share a CU and twice the
 // waves are in flight to cover the latency of the random gathers (measured
 // 12% faster on the 6x6 product than the compiler's 71-register choice).
-// Other variants would spill at 64 registers and keep the launch bound.
-constexpr int waves_per_simd(int kind, bool cplx, int nr, uint32_t lx) {
-    return ((kind == kOrbitTorus && !cplx && nr == 1 && lx != 0) || (kind == kOrbitRing64 && nr <= 2)) ? 8 : 1;
+// The 33..63-site ring search with trivial characters (the paper's chains)
+// fits as well for one or two columns.  Other variants would spill at 64
+// registers (with non-trivial characters the stabilizer walk of a lookup
+// miss is compiled into the element loop) and keep the launch bound.
+constexpr int waves_per_simd(int kind, int chi, bool cplx, int nr, uint32_t lx) {
+    return ((kind == kOrbitTorus && !cplx && nr == 1 && lx != 0) ||
+            (kind == kOrbitRing64 && chi == kChiTrivial && nr <= 2))
+               ? 8
+               : 1;
 }
 
 template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
-__global__ void __launch_bounds__(block_of(KIND)) __attribute__((amdgpu_waves_per_eu(waves_per_simd(KIND, CPLX, NR, LX))))
+__global__ void __launch_bounds__(block_of(KIND)) __attribute__((amdgpu_waves_per_eu(waves_per_simd(KIND, CHI, CPLX, NR, LX))))
 k_matvec(MatvecJob a, uint64_t n_lanes, uint32_t rows_per_lane) {
     constexpr int BLOCK = block_of(KIND);
     extern __shared__ __align__(16) unsigned char smem[];
@@ -43,6 +49,8 @@ __global__ void __launch_bounds__(block_of(KIND)) k_matvec_push(MatvecJob a, uin
     const uint64_t lane = static_cast<uint64_t>(blockIdx.x) * BLOCK + threadIdx.x;
     push_rows<W, KIND, CHI, CPLX, NR, LX, LY, NZ>(a, L, lane, n_lanes, rows_per_lane);
 }
+
+__global__ void k_clear_flag(uint32_t *f) { *f = 0u; }
 
 // y = 0 for the push form (a fill kernel, so the sequence may be captured)
 __global__ void __launch_bounds__(256) k_zero(double *y, uint64_t n) {
@@ -119,6 +127,22 @@ uint64_t count_elements(const ls_operator *op, hipStream_t st) {
 
 uint32_t matvec_max_terms() { return kMaxLdsTerms; }
 
+void enqueue_flag_read(const ls_operator *op, uint32_t *dst, hipStream_t st) {
+    LS_HIP_CHECK(hipMemcpyAsync(dst, op->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, st, op->d_err);
+    LS_HIP_CHECK(hipGetLastError());
+}
+
+void check_operator(const ls_operator *op, hipStream_t st) {
+    uint32_t flag = 0;
+    enqueue_flag_read(op, &flag, st);
+    LS_HIP_CHECK(hipStreamSynchronize(st));
+    if (flag)
+        throw Error{LS_EINTERNAL,
+                    "a product met a neighbour whose representative lies in the sector but is missing from the "
+                    "basis (inconsistent basis or search layout)"};
+}
+
 void search_kind(const ls_operator *op, uint32_t *kind, uint32_t *fixed_shape) {
     const Variant v = variant_of(op);
     *kind = static_cast<uint32_t>(v.kind);
@@ -140,6 +164,7 @@ MatvecJob job_of(const ls_operator *op, const void *x, void *y, uint32_t ld, uin
     a.col = col;
     a.x = x;
     a.y = y;
+    a.err = op->d_err;
     return a;
 }
 

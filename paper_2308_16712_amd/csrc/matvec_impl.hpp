@@ -11,7 +11,10 @@
 //   y_i = acc                                     (one store, no atomics)
 // This is <r~_i|H|r~_j> written with P|s> = conj(chi(g*)) P|rep> and the
 // Hermiticity of H; a neighbour whose orbit the projector annihilates is
-// absent from the basis and contributes nothing.
+// absent from the basis and contributes nothing.  Any other miss means the
+// basis or its search layout is inconsistent (stateToIndex of Section 5.3
+// presumes the state is present): it raises the operator's error flag,
+// which the host reports as LS_EINTERNAL.
 //
 // Work layout.  Each off-diagonal term acts on only part of the rows (a
 // Heisenberg exchange term on about a quarter of them), so a loop over the
@@ -54,6 +57,7 @@ struct MatvecJob {
     uint32_t col;          // first column handled
     const void *x;
     void *y;
+    uint32_t *err;         // operator's error flag (lookup miss of an in-sector orbit)
 };
 
 __device__ __forceinline__ double sign_of(uint64_t v) {
@@ -210,6 +214,28 @@ __device__ __forceinline__ W neighbour_rep(const MatvecJob &a, const LdsTables &
     }
 }
 
+// A neighbour's representative rep was not found by stateToIndex.  That is
+// correct when the projector annihilates its orbit, i.e. some element that
+// fixes rep has a character other than 1 -- never with trivial characters,
+// where every orbit lies in the sector.  Otherwise the error flag is raised.
+// The stabilizer walk runs on misses only.
+template <typename W, int KIND, int CHI>
+__device__ __forceinline__ void lookup_miss(const MatvecJob &a, W rep) {
+    if constexpr (CHI != kChiTrivial) {
+        constexpr int WALK = KIND == kOrbitRing32 ? kOrbitRing32 : kOrbitGeneric;
+        bool annihilated = false;
+        for_each_image<W, WALK>(a.plan, rep, [&](W v, uint32_t code) {
+            if (v == rep && !chi_is_one(a.plan, code)) {
+                annihilated = true;
+                return false;
+            }
+            return true;
+        });
+        if (annihilated) return;
+    }
+    atomicOr(a.err, 1u);
+}
+
 // Rows as run_rows, for the searches that are cheap next to the memory
 // latency of the lookup (rings and the generic walk): the element loop is
 // software-pipelined one element deep.  An iteration searches element e+1 and
@@ -269,6 +295,8 @@ __device__ __forceinline__ void run_rows_ahead(const MatvecJob &a, const LdsTabl
                 if (n_live) {
                     n_slot = slot_of(n_rep, S.hash_shift);
                     n_e = *reinterpret_cast<const uint4 *>(S.table + n_slot);
+                } else {
+                    lookup_miss<W, KIND, CHI>(a, static_cast<W>(n_rep));
                 }
             } else {
                 n_live = true;
@@ -302,6 +330,8 @@ __device__ __forceinline__ void run_rows_ahead(const MatvecJob &a, const LdsTabl
                 const T c = element_value<CHI, CPLX>(sterm[p_t], r, st_j, st_i, a.plan, p_code);
 #pragma unroll
                 for (int q = 0; q < NR; ++q) accumulate(acc[q], c, x[j * a.ld + a.col + q]);
+            } else {
+                lookup_miss<W, KIND, CHI>(a, static_cast<W>(p_rep));
             }
         }
         if (!more) {
@@ -379,7 +409,10 @@ __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L,
         ++t;
         uint32_t st_j = 0;
         const int64_t j = lookup_index_stab(a.search, static_cast<uint64_t>(rep), a.stab, st_j);
-        if (j < 0) continue;
+        if (j < 0) {
+            lookup_miss<W, KIND, CHI>(a, rep);
+            continue;
+        }
         const T c = element_value<CHI, CPLX>(Tm, r, st_j, st_i, a.plan, code);
 #pragma unroll
         for (int q = 0; q < NR; ++q) accumulate(acc[q], c, x[j * a.ld + a.col + q]);
@@ -434,7 +467,10 @@ __device__ __forceinline__ void push_rows(const MatvecJob &a, const LdsTables &L
             const W rep = neighbour_rep<W, KIND, TRACK, LX, LY, NZ>(a, L, r, pr, t, code);
             uint32_t st_j = 0;
             const int64_t j = lookup_index_stab(a.search, static_cast<uint64_t>(rep), a.stab, st_j);
-            if (j < 0) continue;
+            if (j < 0) {
+                lookup_miss<W, KIND, CHI>(a, rep);
+                continue;
+            }
             const T v = element_value<CHI, CPLX>(Tm, r, st_j, st_i, a.plan, code);
 #pragma unroll
             for (int q = 0; q < NR; ++q) scatter_add(&y[static_cast<uint64_t>(j) * a.ld + a.col + q], v, xi[q]);

@@ -84,7 +84,10 @@ __global__ void __launch_bounds__(block_of(KIND)) k_store(StoreArgs s) {
         const int64_t j = lookup_index_stab(a.search, static_cast<uint64_t>(rep), a.stab, st_j);
         const uint64_t slot = base + static_cast<uint64_t>(k) * kSlice;
         ++k;
-        if (j < 0) continue;   // the slot keeps kNoCol
+        if (j < 0) {           // the slot keeps kNoCol
+            lookup_miss<W, KIND, CHI>(a, rep);
+            continue;
+        }
         s.cols[slot] = static_cast<uint32_t>(j);
         static_cast<T *>(s.vals)[slot] = element_value<CHI, CPLX>(Tm, r, st_j, st_i, a.plan, code);
     }
@@ -254,7 +257,8 @@ uint64_t store_elements(ls_operator *op, uint64_t max_bytes, hipStream_t st) {
             dispatch(variant_of(op), 1, L);
             LS_HIP_CHECK(hipGetLastError());
         }
-        LS_HIP_CHECK(hipStreamSynchronize(st));
+        // a lookup miss of an in-sector representative fails the store
+        check_operator(op, st);
     } catch (...) {
         release();
         throw;

@@ -137,3 +137,38 @@ def colex_rank(s: int) -> int:
         s >>= 1
         p += 1
     return r
+
+
+def bethe_ground_energy(n: int, J: float = 1.0) -> float:
+    """Ground energy of the closed spin-1/2 Heisenberg chain H = J sum_i
+    S_i . S_{i+1} (J > 0, even n) from Bethe's ansatz: M = n/2 magnons with
+    rapidities lambda_j solving the logarithmic Bethe equations
+        n * 2 atan(2 lambda_j) = 2 pi I_j + sum_{k != j} 2 atan(lambda_j - lambda_k),
+    I_j = -(M-1)/2, ..., (M-1)/2 (the ground state's quantum numbers), and
+        E = J n / 4 - sum_j (J/2) / (lambda_j^2 + 1/4).
+    Solved by the standard fixed-point iteration lambda_j = tan(...)/2,
+    then Newton's method on the equations above to machine precision."""
+    if n % 2 or n < 2:
+        raise ValueError("even n >= 2")
+    M = n // 2
+    I = -(M - 1) / 2.0 + np.arange(M)
+    lam = 0.5 * np.tan(np.pi * I / n)
+    for _ in range(5000):
+        d = lam[:, None] - lam[None, :]
+        new = 0.5 * np.tan((np.pi * I + np.arctan(d).sum(axis=1)) / n)
+        done = np.max(np.abs(new - lam)) < 1e-15
+        lam = new
+        if done:
+            break
+    for _ in range(100):
+        d = lam[:, None] - lam[None, :]
+        F = 2 * n * np.arctan(2 * lam) - 2 * np.pi * I - 2 * np.arctan(d).sum(axis=1)
+        Jm = 2.0 / (1.0 + d ** 2)
+        np.fill_diagonal(Jm, 0.0)
+        diag = 4 * n / (1 + 4 * lam ** 2) - Jm.sum(axis=1)
+        np.fill_diagonal(Jm, diag)
+        step = np.linalg.solve(Jm, -F)
+        lam = lam + step
+        if np.max(np.abs(step)) < 1e-15:
+            break
+    return float(J * n / 4.0 - J * np.sum(0.5 / (lam ** 2 + 0.25)))

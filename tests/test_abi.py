@@ -169,3 +169,101 @@ def test_group_compiler_random_relabelings():
         g = L.relabel_group(L.ring_group(n, 0, 1), perm)
         info = _lib.sector_check(n, 2, g.perm, g.flip, g.chi)
         assert info["n_cosets"] * info["lx"] * info["ly"] == g.size
+
+
+# ---------------------------------------------------------------- binding checks
+#
+# The binding refuses buffers the kernels would read or write past: wrong
+# element type, wrong length, y unlike x, non-64-bit states.  The checks run
+# before any library call, so they are exercised here on handle objects that
+# hold no library handle.
+
+def _fake_operator(dim, cplx):
+    op = _lib.Operator.__new__(_lib.Operator)
+    op._h = None
+    op.dim = dim
+    op.is_complex = cplx
+    return op
+
+
+def _fake_basis():
+    b = _lib.Basis.__new__(_lib.Basis)
+    b._h = None
+    b.dim = 10
+    return b
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_binding_rejects_mismatched_vectors(cplx):
+    import torch
+    op = _fake_operator(10, cplx)
+    good = torch.complex128 if cplx else torch.float64
+    bad = torch.float64 if cplx else torch.complex128
+    with pytest.raises(TypeError):
+        op.matvec(torch.zeros(10, dtype=torch.float32))
+    with pytest.raises(TypeError):
+        op.matvec(torch.zeros(10, dtype=bad))
+    with pytest.raises(ValueError):
+        op.matvec(torch.zeros(9, dtype=good))                   # short
+    with pytest.raises(ValueError):
+        op.matvec(torch.zeros(10, 65, dtype=good))              # nrhs above 64
+    with pytest.raises(ValueError):
+        op.matvec(torch.zeros(10, 2, 2, dtype=good))
+    with pytest.raises(TypeError):
+        op.matvec_push(torch.zeros(10, dtype=bad))
+    with pytest.raises(ValueError):
+        op.lanczos(5, v0=torch.zeros(9, dtype=good))
+    with pytest.raises(TypeError):
+        op.lanczos(5, v0=torch.zeros(10, dtype=bad))
+    with pytest.raises(ValueError):
+        op.lanczos(0)
+    with pytest.raises(ValueError):
+        _lib.Solver(op, 5, v0=torch.zeros(11, dtype=good))
+
+
+def test_binding_rejects_y_unlike_x():
+    import torch
+    x = torch.zeros(10, dtype=torch.float64)
+    for y in (torch.zeros(10, dtype=torch.float32), torch.zeros(9, dtype=torch.float64),
+              torch.zeros(10, 1, dtype=torch.float64)):
+        with pytest.raises(ValueError):
+            _lib._same_as(y, x)
+    with pytest.raises(TypeError):
+        _lib._same_as(np.zeros(10), x)
+
+
+def test_binding_rejects_non_64bit_states():
+    import torch
+    b = _fake_basis()
+    for bad in (torch.zeros(4, dtype=torch.int32), torch.zeros(4, dtype=torch.float64)):
+        with pytest.raises(TypeError):
+            b.state_info(bad)
+        with pytest.raises(TypeError):
+            b.index_lookup(bad)
+    with pytest.raises(ValueError):
+        b.index_lookup(torch.zeros(2, 2, dtype=torch.int64))
+
+
+def test_binding_rejects_host_buffers():
+    """Correct dtype and shape, but host memory: refused before the call."""
+    import torch
+    op = _fake_operator(10, False)
+    with pytest.raises(ValueError, match="GPU"):
+        op.matvec(torch.zeros(10, dtype=torch.float64))
+
+
+def test_batch_binding_checks_every_vector():
+    import torch
+    B = _lib.Batch.__new__(_lib.Batch)
+    B._h = None
+    B.ops = [_fake_operator(10, False), _fake_operator(6, True)]
+    B.nrhs = [2, 1]
+    c6 = torch.zeros(6, dtype=torch.complex128)
+    with pytest.raises(TypeError):       # element type of the operator
+        B.matvec([torch.zeros(10, 2, dtype=torch.complex128), c6], [c6, c6])
+    with pytest.raises(ValueError):      # nrhs of the batch entry
+        B.matvec([torch.zeros(10, 3, dtype=torch.float64), c6], [c6, c6])
+    with pytest.raises(ValueError):      # length
+        B.matvec([torch.zeros(11, 2, dtype=torch.float64), c6], [c6, c6])
+    with pytest.raises(ValueError):
+        B.matvec([c6], [c6])             # one x and one y per operator

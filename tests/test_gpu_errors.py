@@ -1,0 +1,140 @@
+"""The lookup-miss error path (C ABI: ls_operator_check, LS_EINTERNAL).
+
+A neighbour whose representative is missing from the basis contributes zero
+only when the projector annihilates its orbit.  Any other miss raises the
+operator's device flag.  These tests force the condition from the host: the
+test hook ls_basis_test_drop_key takes one representative out of a basis's
+hash index.  Every kernel still runs to its normal end; only the flag and
+the returned status change.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from workloads import configs, lattice, rng, terms
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2308_16712_amd as ls  # noqa: E402
+from paper_2308_16712_amd import _lib  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _sector(name, n, w, g, bonds):
+    return configs.sector_from_arrays(name, n, w, g.perm, g.flip, g.chi, terms.heisenberg_terms(bonds))
+
+
+CASES = {
+    # trivial characters: every orbit is in the sector
+    "ringD16_0pp": lambda: _sector("ringD16_0pp", 16, 8, lattice.ring_group(16, 0, 1, 1),
+                                   lattice.ring_bonds(16, 1.0, 0.3)),
+    # momentum k = 3: orbits with a translation in their stabilizer are annihilated
+    "ringT20_k3": lambda: _sector("ringT20_k3", 20, 10, lattice.ring_group(20, 3), lattice.ring_bonds(20, 1.0, 0.45)),
+    # 6x6 torus, full group, trivial characters (the headline search, small weight)
+    "torus6x6_w3_full": lambda: _sector("torus6x6_w3_full", 36, 3, lattice.torus_group(6, 6),
+                                        lattice.torus_bonds(6, 6, 1.0, 0.5)),
+}
+
+
+def _is_einternal(exc):
+    return isinstance(exc, ls.LSError) and exc.status == _lib.LS_EINTERNAL
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_dropped_key_raises_einternal(name):
+    sec = CASES[name]()
+    _say(f"[gpu] errors: {name}")
+    good_b = ls.ls_basis_build(sec)
+    good = ls.ls_operator_create(good_b, sec.terms)
+    bad_b = ls.ls_basis_build(sec)
+    bad = ls.ls_operator_create(bad_b, sec.terms)
+    reps, _ = good_b.copy()
+    k = good_b.dim // 2
+    x = torch.from_numpy(rng.vector(3, good_b.dim, complex_=good.is_complex)).cuda()
+    y_good = good.matvec(x)
+    good.check()                                   # nothing missing
+    bad_b.test_drop_key(k)
+    idx = bad_b.index_lookup(reps).cpu().numpy()
+    assert idx[k] == -1 and np.array_equal(np.delete(idx, k), np.delete(np.arange(good_b.dim), k))
+    # pull form
+    bad.matvec(x)
+    with pytest.raises(ls.LSError) as e:
+        bad.check()
+    assert _is_einternal(e.value)
+    bad.check()                                    # the check cleared the flag
+    # push form
+    bad.matvec_push(x)
+    with pytest.raises(ls.LSError) as e:
+        bad.check()
+    assert _is_einternal(e.value)
+    # batched product beside a healthy operator: only the bad one is flagged
+    B = ls.Batch([good, bad], [1, 1])
+    ys = [torch.empty_like(x), torch.empty_like(x)]
+    B.matvec([x, x], ys)
+    good.check()
+    with pytest.raises(ls.LSError) as e:
+        bad.check()
+    assert _is_einternal(e.value)
+    assert torch.equal(ys[0], y_good)
+    B.close()
+    # Lanczos stops at the first step
+    with pytest.raises(ls.LSError) as e:
+        bad.lanczos(10, seed=1)
+    assert _is_einternal(e.value)
+    # storing the elements fails and keeps nothing
+    with pytest.raises(ls.LSError) as e:
+        bad.store()
+    assert _is_einternal(e.value)
+    # the healthy operator is untouched by all of this
+    assert torch.equal(good.matvec(x), y_good)
+    good.check()
+    for h in (bad, bad_b, good, good_b):
+        h.close()
+
+
+def test_stepper_stops_only_the_failing_solve():
+    """Two solves stepped together, one on a basis with a dropped key: the
+    step reports LS_EINTERNAL, the failing solve is stopped and reports it,
+    and the healthy solve goes on to the ground energy it has alone."""
+    sec = CASES["ringD16_0pp"]()
+    b1 = ls.ls_basis_build(sec)
+    op1 = ls.ls_operator_create(b1, sec.terms)
+    b2 = ls.ls_basis_build(sec)
+    op2 = ls.ls_operator_create(b2, sec.terms)
+    b2.test_drop_key(5)
+    alone = op1.lanczos(60, tol=1e-10, seed=4)
+    s1 = ls.Solver(op1, 60, tol=1e-10, seed=4)
+    s2 = ls.Solver(op2, 60, tol=1e-10, seed=4)
+    with pytest.raises(ls.LSError) as e:
+        ls.Solver.step_all([s1, s2])
+    assert _is_einternal(e.value)
+    with pytest.raises(ls.LSError) as e:
+        s2.result()
+    assert _is_einternal(e.value)
+    for _ in range(60):
+        ls.Solver.step_all([s1, s2])               # the stopped solve is skipped
+        if s1.result()["done"]:
+            break
+    r1 = s1.result()
+    assert r1["converged"] and r1["e0"] == alone["e0"] and r1["iters"] == alone["iters"]
+    for h in (s1, s2, op1, op2, b1, b2):
+        h.close()
+
+
+def test_drop_key_rejects_other_layouts(monkeypatch):
+    sec = CASES["ringD16_0pp"]()
+    monkeypatch.setenv("LS_ED_SEARCH", "buckets")
+    b = ls.ls_basis_build(sec)
+    monkeypatch.delenv("LS_ED_SEARCH")
+    with pytest.raises(ls.LSError) as e:
+        b.test_drop_key(0)
+    assert e.value.status == _lib.LS_EINVAL
+    with pytest.raises(ls.LSError):
+        b.test_drop_key(b.dim)
+    b.close()

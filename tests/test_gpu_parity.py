@@ -6,6 +6,7 @@ relative to ||y||_inf), Lanczos energies within 1e-10.  Full-size sectors
 are checked on sampled rows that the oracle computes one by one and through
 properties that hold at any size.
 """
+import os
 import sys
 
 import numpy as np
@@ -76,6 +77,9 @@ def _small_sectors():
     out.append(_sector("torus6x6_w3_full", 36, 3, lattice.torus_group(6, 6), lattice.torus_bonds(6, 6, 1.0, 0.5)))
     out.append(_sector("torus6x6_w4_k10", 36, 4, lattice.torus_group(6, 6, 1, 0, "none"),
                        lattice.torus_bonds(6, 6, 1.0, 0.5)))
+    # N = 64: the whole 64-bit word (no bits above N)
+    out.append(_sector("ring64_w3_k5", 64, 3, lattice.ring_group(64, 5), lattice.ring_bonds(64, 1.0, 0.3)))
+    out.append(_sector("torus8x8_w3_full", 64, 3, lattice.torus_group(8, 8), lattice.torus_bonds(8, 8, 1.0, 0.5)))
     return out
 
 
@@ -152,13 +156,12 @@ def test_matvec_parity(sec, nrhs):
     d = len(reps)
     if d == 0:
         return
-    if nrhs > 1 and d > 20000:
-        pytest.skip("multi-RHS checked on the smaller sectors")
     x = rng.vector(sec.seed + 17 + nrhs, d, nrhs, complex_=op.is_complex)
     y_ref = oracle.matvec(P, reps, stab, x)
     xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
     y = op.matvec(xt).cpu().numpy()
     _compare(y, y_ref)
+    op.check()     # no lookup miss of an in-sector representative (LS_EINTERNAL)
 
 
 def test_matvec_empty_and_errors():
@@ -266,38 +269,112 @@ def test_lanczos_converges_cfg1():
     P, reps, stab, b, op = _built(sec)
     res = op.lanczos(200, tol=1e-12, seed=3)
     assert res["converged"]
-    assert abs(res["e0"] - (-7.142296360616781)) < 1e-10
+    # the 16-site chain's ground energy from Bethe's ansatz
+    assert abs(res["e0"] - ref.bethe_ground_energy(16)) < 1e-10
 
 
 # ----------------------------------------------------------------- full sizes
 
-def _full_size_checks(sec, dim_expected, n_sample=300, n_rows=150):
+def _host_workers():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _whole_list_check(P, sec, reps, stab):
+    """Every stored representative is its own orbit minimum, lies in the
+    sector and carries the oracle's stabilizer size (norm bit for bit); the
+    list is strictly increasing.  With the count equal to the character
+    formula this proves the set equals the oracle's basis."""
+    _say(f"[gpu] whole-list oracle check of {len(reps)} representatives ({_host_workers()} host threads)")
+    assert np.all(reps[1:] > reps[:-1])
+    o_rep, _, o_norm = oracle.state_info(P, reps, workers=_host_workers())
+    assert np.array_equal(o_rep, reps)
+    assert np.all(o_norm > 0)
+    assert np.array_equal(np.sqrt(stab.astype(np.float64) / sec.group.size), o_norm)
+
+
+def _neighbour_rows(P, reps, rs):
+    """Indices of the representatives adjacent to each r in rs (oracle rows)."""
+    out = []
+    for nb, _ in oracle.get_rows(P, rs, workers=_host_workers()):
+        j = np.searchsorted(reps, nb)
+        ok = (j < len(reps))
+        j = j[ok]
+        out.append(j[reps[j] == nb[ok]])
+    return np.concatenate(out) if out else np.zeros(0, np.int64)
+
+
+def _top_pair_periodic(v, lx, ly):
+    """Whether the top two rows of each state (rows ly-1 and ly-2 of an
+    lx-wide layout) are invariant under some x-rotation by 1..lx-1: the
+    pair tables of the pruned torus search then hold an ambiguous entry and
+    the search evaluates every x-shift of the candidates."""
+    rm = np.uint64((1 << lx) - 1)
+    top = (v >> np.uint64(lx * (ly - 1))) & rm
+    sec = (v >> np.uint64(lx * (ly - 2))) & rm
+
+    def rot(w, a):
+        return ((w << np.uint64(a)) | (w >> np.uint64(lx - a))) & rm
+
+    per = np.zeros(v.shape, dtype=bool)
+    for a in range(1, lx):
+        per |= (rot(top, a) == top) & (rot(sec, a) == sec)
+    return per
+
+
+def _sampled_rows(P, sec, reps, stab, n_random, n_stab, seed, torus=None):
+    """Rows for the oracle: n_random uniform ones, the n_stab representatives
+    with the largest stabilizers and the neighbours of the first 200 of
+    them, the first and last rows and their neighbours, and for tori the
+    neighbours of representatives whose top pair is x-periodic (rows whose
+    elements take the ambiguous pair-table branch)."""
+    d = len(reps)
+    parts = {"random": (rng.counter_u64(seed, np.arange(n_random, dtype=np.uint64)) % np.uint64(d)).astype(np.int64)}
+    top = np.argsort(-stab.astype(np.int64), kind="stable")[:n_stab]
+    parts["largest_stabilizers"] = top
+    parts["neighbours_of_largest_stabilizers"] = _neighbour_rows(P, reps, reps[top[:200]])
+    ends = np.array([0, d - 1], dtype=np.int64)
+    parts["first_last"] = ends
+    parts["neighbours_of_first_last"] = _neighbour_rows(P, reps, reps[ends])
+    if torus is not None:
+        per = np.flatnonzero(_top_pair_periodic(reps, *torus))
+        assert per.size > 0
+        tie = per[(rng.counter_u64(seed + 1, np.arange(min(300, per.size), dtype=np.uint64)) %
+                   np.uint64(per.size)).astype(np.int64)]
+        nbr = _neighbour_rows(P, reps, reps[tie])
+        parts["neighbours_of_tie_keys"] = nbr[:4000]
+    rows = np.unique(np.concatenate(list(parts.values())))
+    _say("[gpu] oracle rows: " + ", ".join(f"{k} {len(v)}" for k, v in parts.items()) + f"; {len(rows)} distinct")
+    return rows
+
+
+def _rows_check(P, reps, y, rows, seed, complex_):
+    got = oracle.get_rows(P, reps[rows], workers=_host_workers())
+    ref_y = np.array([np.sum(coef * rng.state_values(seed, nb, complex_=complex_)) for nb, coef in got])
+    scale = max(1.0, np.max(np.abs(ref_y)))
+    err = np.abs(y[rows] - ref_y)
+    worst = int(np.argmax(err))
+    assert err[worst] <= MATVEC_TOL * scale, (int(rows[worst]), y[rows][worst], ref_y[worst])
+
+
+def _full_size_checks(sec, dim_expected, n_random=10000, n_stab=1000, torus=None):
     _say(f"[gpu] full-size {sec.name}")
     b = ls.ls_basis_build(sec)
     assert b.dim == dim_expected
     reps_t, stab_t = b.copy()
     reps = _u64(reps_t)
-    assert np.all(np.diff(reps.astype(np.uint64)) > 0)
+    stab = stab_t.cpu().numpy().view(np.uint16)
     P = oracle.Problem(sec)
-    pick = (rng.counter_u64(5, np.arange(n_sample, dtype=np.uint64)) % np.uint64(b.dim)).astype(np.int64)
-    pick = np.unique(np.concatenate([pick, [0, b.dim - 1]]))
-    o_rep, o_chi, o_norm = oracle.state_info(P, reps[pick])
-    assert np.array_equal(o_rep, reps[pick])                   # each is its own orbit minimum
-    assert np.all(o_norm > 0)                                  # and in the sector
-    stab = stab_t.cpu().numpy().view(np.uint16)[pick].astype(np.float64)
-    assert np.array_equal(np.sqrt(stab / sec.group.size), o_norm)
-    # index of sampled representatives
-    idx = b.index_lookup(_dev_u64(reps[pick])).cpu().numpy()
-    assert np.array_equal(idx, pick)
-    # matvec on rows sampled by the oracle, x keyed by basis state
+    _whole_list_check(P, sec, reps, stab)
+    # stateToIndex of every representative, and of states outside the list
+    idx = b.index_lookup(reps_t).cpu().numpy()
+    assert np.array_equal(idx, np.arange(b.dim))
+    # the product on the timed launch, checked on oracle rows (x keyed by state)
     op = ls.ls_operator_create(b, sec.terms)
     x = rng.state_values(11, reps, complex_=op.is_complex)
     y = op.matvec(torch.from_numpy(x).cuda()).cpu().numpy()
-    rows = pick[:n_rows]
-    for i in rows:
-        nb, coef = oracle.get_row(P, int(reps[i]))
-        yi = np.sum(coef * rng.state_values(11, nb, complex_=op.is_complex))
-        assert abs(y[i] - yi) <= MATVEC_TOL * max(1.0, np.max(np.abs(y[rows]))), (i, y[i], yi)
+    op.check()
+    rows = _sampled_rows(P, sec, reps, stab, n_random, n_stab, 5, torus)
+    _rows_check(P, reps, y, rows, 11, op.is_complex)
     # Hermiticity at full size
     u = rng.vector(21, b.dim, complex_=op.is_complex)
     v = rng.vector(22, b.dim, complex_=op.is_complex)
@@ -308,22 +385,56 @@ def _full_size_checks(sec, dim_expected, n_sample=300, n_rows=150):
     return b, op
 
 
+@pytest.mark.timeout(900)
 def test_full_ring32_symmetric():
     sec = configs.ring32_symmetric()
     dim = ref.character_dimension(sec.group, 16)
     assert dim == 4707969
     b, op = _full_size_checks(sec, dim)
     assert op.search_kind() == ("ring32", False)
+    # 100-step Lanczos on the same launch: the ground energy of the 32-site
+    # chain from Bethe's ansatz (the ground state lies in this sector)
+    res = op.lanczos(100, seed=1)
+    e_bethe = ref.bethe_ground_energy(32)
+    _say(f"[gpu] ring32 100-step Lanczos E0 {res['e0']!r}, Bethe ansatz {e_bethe!r}")
+    assert abs(res["e0"] - e_bethe) <= LANCZOS_TOL * abs(e_bethe)
+    sel = op.lanczos(100, seed=1, reorth="selective")
+    assert abs(sel["e0"] - e_bethe) <= LANCZOS_TOL * abs(e_bethe)
 
 
+@pytest.mark.timeout(900)
 def test_full_square6x6_j1j2():
     sec = configs.square_j1j2()
     dim = ref.character_dimension(sec.group, 18)
     assert dim == 15804956
-    b, op = _full_size_checks(sec, dim, n_sample=200, n_rows=60)
+    b, op = _full_size_checks(sec, dim, torus=(6, 6))
     # the timed configuration runs the pruned torus search with its
     # compile-time layout (a fallback would still pass the checks above)
     assert op.search_kind() == ("torus", True)
+
+
+def test_lanczos_100_steps_ring24_parity():
+    """100 Lanczos steps on the 24-site chain's (k=0, R=+1, Z=+1) sector --
+    the 32-bit ring search of the 32-site headline sector -- against the
+    oracle's recurrence on its getRow matrix: the same steps, alpha, beta and
+    ground energy (full CGS2 and selective second pass), and the Bethe-ansatz
+    ground energy."""
+    sec = configs.ring_symmetric(24, 0, 1, 1)
+    P = oracle.Problem(sec)
+    reps, stab = oracle.enumerate_basis(P)
+    H = oracle.sparse_matrix(P, reps, workers=_host_workers())
+    b = ls.ls_basis_build(sec)
+    op = ls.ls_operator_create(b, sec.terms)
+    assert op.search_kind() == ("ring32", False)
+    v0 = rng.vector(1, len(reps))
+    for mode in (True, "selective"):
+        want = oracle.lanczos(lambda v: H @ v, v0, 100, reorth=mode)
+        got = op.lanczos(100, seed=1, reorth=mode)
+        assert got["iters"] == want["iters"] == 100
+        assert abs(got["e0"] - want["e0"]) <= LANCZOS_TOL * max(1.0, abs(want["e0"]))
+        assert np.allclose(got["alpha"], want["alpha"], atol=1e-10, rtol=0)
+        assert np.allclose(got["beta"], want["beta"], atol=1e-10, rtol=0)
+        assert abs(got["e0"] - ref.bethe_ground_energy(24)) <= LANCZOS_TOL * 11.0
 
 
 @pytest.mark.parametrize("name,want", [("ringD16_0pp", ("ring32", False)), ("ring40_w3_D", ("ring64", False)),
@@ -336,31 +447,38 @@ def test_search_kind(name, want):
     assert ls.ls_operator_search_kind(op) == want
 
 
+@pytest.mark.timeout(900)
 def test_full_chain40_paper_workload():
     """The paper's 40-spin chain (Section 6: Heisenberg chain, U(1), spin
     inversion, translation, reflection; Table 2 dimension): the full product
-    on the GPU, checked on rows the oracle computes one by one, with x keyed
-    by basis state and filled on the device."""
+    on the GPU, checked on 10^4 uniformly drawn rows, the 1000 rows with the
+    largest stabilizers and the first and last rows, which the oracle
+    computes one by one, with x keyed by basis state and filled on the
+    device."""
     sec = configs.ring_symmetric(40, 0, 1, 1)
     P = oracle.Problem(sec)
     _say("[gpu] full-size chain40")
     b = ls.ls_basis_build(sec)
     try:
         assert b.dim == 861725794
-        reps_t, _ = b.copy()
+        reps_t, stab_t = b.copy()
         x = rng.state_values_torch(11, reps_t)
         op = ls.ls_operator_create(b, sec.terms)
+        assert op.search_kind() == ("ring64", False)
         y = op.matvec(x)
-        pick = (rng.counter_u64(6, np.arange(60, dtype=np.uint64)) % np.uint64(b.dim)).astype(np.int64)
-        pick = np.unique(np.concatenate([pick, [0, b.dim - 1]]))
+        pick = (rng.counter_u64(6, np.arange(10000, dtype=np.uint64)) % np.uint64(b.dim)).astype(np.int64)
+        top = torch.topk(stab_t.to(torch.int32), 1000).indices.cpu().numpy()
+        pick = np.unique(np.concatenate([pick, top, [0, b.dim - 1]]))
         idx = torch.from_numpy(pick).cuda()
         reps = reps_t[idx].cpu().numpy().view(np.uint64)
         ys = y[idx].cpu().numpy()
-        del x, y, reps_t
-        for i, r in enumerate(reps):
-            nb, coef = oracle.get_row(P, int(r))
-            yi = np.sum(coef * rng.state_values(11, nb))
-            assert abs(ys[i] - yi) <= MATVEC_TOL * max(1.0, np.max(np.abs(ys))), (pick[i], ys[i], yi)
+        del x, y, reps_t, stab_t
+        _say(f"[gpu] chain40: {len(pick)} oracle rows")
+        got = oracle.get_rows(P, reps, workers=_host_workers())
+        ref_y = np.array([np.sum(coef * rng.state_values(11, nb)) for nb, coef in got])
+        err = np.abs(ys - ref_y)
+        worst = int(np.argmax(err))
+        assert err[worst] <= MATVEC_TOL * max(1.0, np.max(np.abs(ref_y))), (pick[worst], ys[worst], ref_y[worst])
         op.close()
     finally:
         b.close()

@@ -245,6 +245,28 @@ def test_majumdar_ghosh_point(n):
     assert abs(e_sym + 3 * n / 8) < 1e-10
 
 
+@pytest.mark.parametrize("n", [6, 8, 10])
+def test_bethe_ansatz_matches_full_space_ground_energy(n):
+    """The Bethe-ansatz ground energy of the closed chain equals the lowest
+    eigenvalue of the Sz=0 block of the full 2^n Hamiltonian built from Pauli
+    matrices (no oracle code involved)."""
+    H = ref.heisenberg_full(n, lattice.ring_bonds(n, 1.0))
+    idx = ref.weight_states(n, n // 2)
+    e_full = np.linalg.eigvalsh(H[np.ix_(idx, idx)])[0]
+    assert abs(ref.bethe_ground_energy(n) - e_full) < 1e-11
+
+
+def test_bethe_ansatz_closed_form_and_oracle_sector():
+    """n = 4: E0 = -2J.  n = 8, 12 (n divisible by 4, ground state at k = 0,
+    even under reflection and spin inversion): the oracle's (k=0, R=+1,
+    Z=+1) sector has the Bethe-ansatz energy as its lowest eigenvalue."""
+    assert abs(ref.bethe_ground_energy(4) + 2.0) < 1e-14
+    assert abs(ref.bethe_ground_energy(4, 2.5) + 5.0) < 1e-13
+    for n in (8, 12):
+        e = _e0(n, n // 2, lattice.ring_group(n, 0, 1, 1), lattice.ring_bonds(n, 1.0))
+        assert abs(e - ref.bethe_ground_energy(n)) < 1e-11
+
+
 def test_hermiticity_random_vectors():
     for g, n, bonds in [(lattice.ring_group(10, 3), 10, lattice.ring_bonds(10, 1.0, 0.3)),
                         (lattice.torus_group(4, 3), 12, lattice.torus_bonds(4, 3, 1.0, 0.5))]:
@@ -306,6 +328,41 @@ def test_index_is_colex_rank_for_u1_only_basis():
         assert oracle.index_lookup(reps, absent).tolist() == [-1, -1]
 
 
+def test_threaded_state_info_and_rows_match_serial():
+    """Splitting the oracle's state_info and getRow over host threads changes
+    nothing: the same representatives, characters, norms and rows."""
+    sec = _sector(14, 7, lattice.ring_group(14, 3, 0, 0), lattice.ring_bonds(14, 1.0, 0.3))
+    P = oracle.Problem(sec)
+    st = rng.counter_u64(5, np.arange(20000, dtype=np.uint64)) & np.uint64((1 << 14) - 1)
+    a = oracle.state_info(P, st)
+    b = oracle.state_info(P, st, workers=4)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+    reps, _ = oracle.enumerate_basis(P)
+    rows1 = [oracle.get_row(P, int(r)) for r in reps[:300]]
+    rows4 = oracle.get_rows(P, reps[:300], workers=4)
+    for (n1, c1), (n4, c4) in zip(rows1, rows4):
+        assert np.array_equal(n1, n4) and np.array_equal(c1, c4)
+
+
+@pytest.mark.parametrize("case", ["ring12_D", "ring12_k5", "torus4x3"])
+def test_sparse_matrix_equals_column_product(case):
+    """The sparse matrix assembled from getRow applies H like the
+    column-by-column product (real and complex sectors)."""
+    g, n, bonds = {
+        "ring12_D": (lattice.ring_group(12, 0, 1, 1), 12, lattice.ring_bonds(12, 1.0, 0.4)),
+        "ring12_k5": (lattice.ring_group(12, 5), 12, lattice.ring_bonds(12, 1.0, 0.2)),
+        "torus4x3": (lattice.torus_group(4, 3), 12, lattice.torus_bonds(4, 3, 1.0, 0.5)),
+    }[case]
+    P = oracle.Problem(_sector(n, n // 2, g, bonds))
+    reps, stab = oracle.enumerate_basis(P)
+    H = oracle.sparse_matrix(P, reps, workers=2)
+    x = rng.vector(4, len(reps), 3, complex_=not P.is_real)
+    y = oracle.matvec(P, reps, stab, x)
+    assert np.linalg.norm(H @ x - y) <= 1e-13 * np.linalg.norm(y)
+    assert (H - H.conj().T).count_nonzero() == 0 or abs(H - H.conj().T).max() < 1e-14
+
+
 # ---------------------------------------------------------------- Lanczos
 
 def test_lanczos_converges_to_dense_ground_energy():
@@ -345,6 +402,8 @@ def test_lanczos_ring16_against_full_space_sparse():
     reps, stab = oracle.enumerate_basis(P)
     res = oracle.lanczos(lambda v: oracle.matvec(P, reps, stab, v), rng.vector(1, len(reps)), 80)
     assert abs(res["e0"] - e_full) < 1e-10
+    # and the Bethe-ansatz value for the 16-site chain
+    assert abs(ref.bethe_ground_energy(16) - e_full) < 1e-10
 
 
 
