@@ -127,6 +127,23 @@ ls_status ls_basis_build(const ls_sector_desc *desc, void *stream, ls_basis **ou
 ls_status ls_sector_count(const ls_sector_desc *desc, uint64_t rank_begin, uint64_t rank_end,
                           uint64_t *n_members, uint64_t *n_candidates, void *stream);
 
+/* ls_sector_count without device allocation, for callers that cannot
+ * allocate device memory (tight loops that must not call hipMalloc,
+ * harnesses that forbid it).  Same arguments, results and errors as
+ * ls_sector_count.  The compiled group's device tables and the 8-byte
+ * accumulator live in a static device array of 256 KiB that each GPU the
+ * library runs on holds until the process ends (groups whose tables need
+ * more -- binomial table, coset representatives at 96 bytes each,
+ * characters at 16 bytes per element, the torus pair table -- are refused
+ * with LS_EINVAL; groups with lattice translations need a few KB).  No
+ * hipMalloc, hipFree or other device allocation is made.  Every call on a
+ * GPU shares that GPU's array and overwrites what the last call left:
+ * calls from one process are serialised by a lock inside the library;
+ * overlapping calls from several processes on one GPU use separate arrays.
+ * Blocks until the count on `stream` has finished.                         */
+ls_status ls_sector_count_noalloc(const ls_sector_desc *desc, uint64_t rank_begin, uint64_t rank_end,
+                                  uint64_t *n_members, uint64_t *n_candidates, void *stream);
+
 /* Validates a sector descriptor and compiles its group on the host only (no
  * device work): the checks of ls_basis_build plus the group compiler's own
  * self-checks (Benes routing verified on every wire).  Optional outputs

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libls_ed.so")
 LS_OK, LS_WNOTCONV, LS_EINVAL, LS_ENOMEM, LS_EDEVICE, LS_EINTERNAL = 0, 1, -1, -2, -3, -4
 _NAMES = {0: "LS_OK", 1: "LS_WNOTCONV", -1: "LS_EINVAL", -2: "LS_ENOMEM", -3: "LS_EDEVICE", -4: "LS_EINTERNAL"}
 
-EXPORTS = ["ls_sector_check", "ls_sector_count", "ls_basis_build", "ls_basis_info", "ls_basis_copy", "ls_basis_destroy", "ls_state_info",
+EXPORTS = ["ls_sector_check", "ls_sector_count", "ls_sector_count_noalloc", "ls_basis_build", "ls_basis_info", "ls_basis_copy", "ls_basis_destroy", "ls_state_info",
            "ls_index_lookup", "ls_operator_create", "ls_operator_destroy", "ls_operator_info",
            "ls_operator_count", "ls_operator_store", "ls_operator_search_kind", "ls_operator_check",
            "ls_basis_test_drop_key", "ls_matvec", "ls_matvec_push",
@@ -67,6 +67,7 @@ def load(path: str = LIB_PATH):
     sig = {
         "ls_sector_check": ([P, P, P, P, P], i32),
         "ls_sector_count": ([P, u64, u64, P, P, P], i32),
+        "ls_sector_count_noalloc": ([P, u64, u64, P, P, P], i32),
         "ls_basis_build": ([P, P, P], i32),
         "ls_operator_store": ([P, u64, P, P], i32),
         "ls_basis_info": ([P, P, P, P], i32),
@@ -185,9 +186,10 @@ def sector_check(n_sites: int, hamming_weight: int, perm, flip, chi) -> dict:
 
 
 def sector_count(n_sites: int, hamming_weight: int, perm, flip, chi, rank_begin: int = 0,
-                 rank_end: int = 2**64 - 1, stream=None) -> tuple:
+                 rank_end: int = 2**64 - 1, stream=None, noalloc: bool = False) -> tuple:
     """(members, candidates) among the candidates of rank [rank_begin,
-    rank_end), counted on the GPU without storing them (ls_sector_count)."""
+    rank_end), counted on the GPU without storing them (ls_sector_count, or
+    ls_sector_count_noalloc when noalloc: no device allocation)."""
     L = load()
     perm = np.ascontiguousarray(perm, dtype=np.uint16)
     flip = np.ascontiguousarray(flip, dtype=np.uint8)
@@ -196,8 +198,9 @@ def sector_count(n_sites: int, hamming_weight: int, perm, flip, chi, rank_begin:
                       chi.ctypes.data)
     m, c = ctypes.c_uint64(), ctypes.c_uint64()
     # synchronous: without a stream the count runs on the null stream
-    _check(L.ls_sector_count(ctypes.byref(desc), rank_begin, rank_end, ctypes.byref(m), ctypes.byref(c),
-                             _stream_ptr(stream) if stream is not None else None))
+    fn = L.ls_sector_count_noalloc if noalloc else L.ls_sector_count
+    _check(fn(ctypes.byref(desc), rank_begin, rank_end, ctypes.byref(m), ctypes.byref(c),
+              _stream_ptr(stream) if stream is not None else None))
     return m.value, c.value
 
 

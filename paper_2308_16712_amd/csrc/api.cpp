@@ -97,6 +97,20 @@ ls_status ls_sector_count(const ls_sector_desc *desc, uint64_t rank_begin, uint6
     return st;
 }
 
+ls_status ls_sector_count_noalloc(const ls_sector_desc *desc, uint64_t rank_begin, uint64_t rank_end,
+                                  uint64_t *n_members, uint64_t *n_candidates, void *stream) {
+    return guarded([&] {
+        LS_REQUIRE(desc != nullptr && n_members != nullptr, "desc and n_members must not be NULL");
+        LS_REQUIRE(rank_begin <= rank_end, "rank_begin must not exceed rank_end");
+        const ls::GroupPlan plan = ls::compile_group(*desc);
+        uint64_t cand = 0;
+        *n_members = ls::count_members_noalloc(plan, desc->hamming_weight, rank_begin, rank_end,
+                                               as_stream(stream), &cand);
+        if (n_candidates) *n_candidates = cand;
+        return LS_OK;
+    });
+}
+
 ls_status ls_sector_check(const ls_sector_desc *desc, uint32_t *lx, uint32_t *ly, uint32_t *pair_flip,
                           uint32_t *n_cosets) {
     return guarded([&] {

@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
 #include <string>
 
 #include "orbit.hpp"
@@ -505,16 +506,47 @@ uint64_t hash_capacity(uint64_t dim) {
     return 0;
 }
 
+namespace {
+
+// Host images of the device tables of a compiled group, shared by
+// upload_plan (device allocations) and the allocation-free count (static
+// scratch): binomial table [65][65], coset representatives, characters by
+// code, chi == 1 bitset, pair table (tori).
+struct PlanTables {
+    std::vector<uint64_t> binom;
+};
+
+PlanTables plan_tables() {
+    PlanTables t;
+    t.binom.assign(65 * 65, 0);
+    for (uint32_t i = 0; i <= 64; ++i)
+        for (uint32_t k = 0; k <= i; ++k) t.binom[i * 65 + k] = host_binom(i, k);
+    return t;
+}
+
+// PlanDev fields that do not point into device memory.
+void fill_plan_dev(const GroupPlan &gp, PlanDev &pd) {
+    pd.n_sites = gp.n_sites;
+    pd.lx = gp.lx;
+    pd.ly = gp.ly;
+    pd.n_trans = gp.lx * gp.ly;
+    pd.n_cosets = static_cast<uint32_t>(gp.cosets.size());
+    pd.pair_flip = gp.pair_flip;
+    pd.n_stages = gp.n_stages;
+    pd.n_elements = gp.n_elements;
+    pd.full = gp.full;
+    pd.col0 = gp.col0;
+    pd.pair_lut = nullptr;
+    for (int a = 0; a < 8; ++a) pd.col_ge[a] = gp.col_ge[a];
+}
+
+}  // namespace
+
 void upload_plan(ls_basis *b) {
     const GroupPlan &gp = b->plan;
-    const uint32_t n = gp.n_sites;
-    // binomial table
-    std::vector<uint64_t> tab(65 * 65, 0);
-    for (uint32_t i = 0; i <= 64; ++i)
-        for (uint32_t k = 0; k <= i; ++k) tab[i * 65 + k] = host_binom(i, k);
-    LS_HIP_CHECK(hipMalloc(&b->d_binom, tab.size() * sizeof(uint64_t)));
-    LS_HIP_CHECK(hipMemcpy(b->d_binom, tab.data(), tab.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
-    // plan
+    const PlanTables t = plan_tables();
+    LS_HIP_CHECK(hipMalloc(&b->d_binom, t.binom.size() * sizeof(uint64_t)));
+    LS_HIP_CHECK(hipMemcpy(b->d_binom, t.binom.data(), t.binom.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
     const size_t ncos = gp.cosets.size();
     LS_HIP_CHECK(hipMalloc(&b->d_cosets, ncos * sizeof(CosetRep)));
     LS_HIP_CHECK(hipMemcpy(b->d_cosets, gp.cosets.data(), ncos * sizeof(CosetRep), hipMemcpyHostToDevice));
@@ -524,21 +556,10 @@ void upload_plan(ls_basis *b) {
     LS_HIP_CHECK(hipMemcpy(b->d_chi_one, gp.chi_one.data(), gp.chi_one.size() * sizeof(uint32_t),
                            hipMemcpyHostToDevice));
     PlanDev &pd = b->plan_dev;
-    pd.n_sites = n;
-    pd.lx = gp.lx;
-    pd.ly = gp.ly;
-    pd.n_trans = gp.lx * gp.ly;
-    pd.n_cosets = static_cast<uint32_t>(ncos);
-    pd.pair_flip = gp.pair_flip;
-    pd.n_stages = gp.n_stages;
-    pd.n_elements = gp.n_elements;
-    pd.full = gp.full;
-    pd.col0 = gp.col0;
+    fill_plan_dev(gp, pd);
     pd.cosets = b->d_cosets;
     pd.chi = b->d_chi;
     pd.chi_one = b->d_chi_one;
-    pd.pair_lut = nullptr;
-    for (int a = 0; a < 8; ++a) pd.col_ge[a] = gp.col_ge[a];
     if (gp.torus) {
         LS_HIP_CHECK(hipMalloc(&b->d_pair_lut, gp.pair_lut.size() * sizeof(uint32_t)));
         LS_HIP_CHECK(hipMemcpy(b->d_pair_lut, gp.pair_lut.data(), gp.pair_lut.size() * sizeof(uint32_t),
@@ -553,48 +574,145 @@ uint64_t candidate_count(const ls_basis *b) {
     return n == 64 ? ~0ULL : (1ULL << n);
 }
 
+namespace {
+
+__global__ void k_clear_u64(unsigned long long *p) { *p = 0ull; }
+
+// Members among the candidates of rank [begin, end) (end within range),
+// accumulated into *acc (device, 8 bytes; cleared here by a fill kernel);
+// the plan's tables must be on the device.
 template <typename W>
-uint64_t count_impl(ls_basis *b, uint64_t begin, uint64_t end, hipStream_t st) {
+uint64_t count_impl(const GroupPlan &gp, const PlanDev &pd, const uint64_t *binom, int32_t weight, uint64_t begin,
+                    uint64_t end, unsigned long long *acc, hipStream_t st) {
     // 64 candidates per lane as in the mark pass; a launch covers up to 2^20
     // workgroups (1.7e10 candidates, a fraction of a second)
     constexpr uint32_t kPerLane = kCandPerLane;
     constexpr uint64_t kSpan = (1ull << 20) * kBlock * kPerLane;
-    StreamBuf acc_b(sizeof(unsigned long long), st);
-    unsigned long long *acc = acc_b.as<unsigned long long>();
     unsigned long long total = 0;
-    {
-        LS_HIP_CHECK(hipMemsetAsync(acc, 0, sizeof(unsigned long long), st));
-        EnumArgs a{};
-        a.plan = b->plan_dev;
-        a.binom = b->d_binom;
-        a.total = end;
-        a.n_sites = b->plan.n_sites;
-        a.weight = b->weight;
-        const int kind = orbit_kind<W>(b->plan);
-        for (uint64_t lo = begin; lo < end;) {
-            const uint64_t hi = end - lo > kSpan ? lo + kSpan : end;
-            const uint64_t lanes = (hi - lo + kPerLane - 1) / kPerLane;
-            const uint32_t blocks = static_cast<uint32_t>((lanes + kBlock - 1) / kBlock);
-            if (kind == kOrbitRing32)
-                hipLaunchKernelGGL((k_enum_count<W, kOrbitRing32>), dim3(blocks), dim3(kBlock), 0, st, a, lo, hi,
-                                   kPerLane, acc);
-            else
-                hipLaunchKernelGGL((k_enum_count<W, kOrbitGeneric>), dim3(blocks), dim3(kBlock), 0, st, a, lo, hi,
-                                   kPerLane, acc);
-            LS_HIP_CHECK(hipGetLastError());
-            lo = hi;
-        }
-        LS_HIP_CHECK(hipMemcpyAsync(&total, acc, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-        LS_HIP_CHECK(hipStreamSynchronize(st));
+    hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(1), 0, st, acc);
+    LS_HIP_CHECK(hipGetLastError());
+    EnumArgs a{};
+    a.plan = pd;
+    a.binom = binom;
+    a.total = end;
+    a.n_sites = gp.n_sites;
+    a.weight = weight;
+    const int kind = orbit_kind<W>(gp);
+    for (uint64_t lo = begin; lo < end;) {
+        const uint64_t hi = end - lo > kSpan ? lo + kSpan : end;
+        const uint64_t lanes = (hi - lo + kPerLane - 1) / kPerLane;
+        const uint32_t blocks = static_cast<uint32_t>((lanes + kBlock - 1) / kBlock);
+        if (kind == kOrbitRing32)
+            hipLaunchKernelGGL((k_enum_count<W, kOrbitRing32>), dim3(blocks), dim3(kBlock), 0, st, a, lo, hi,
+                               kPerLane, acc);
+        else
+            hipLaunchKernelGGL((k_enum_count<W, kOrbitGeneric>), dim3(blocks), dim3(kBlock), 0, st, a, lo, hi,
+                               kPerLane, acc);
+        LS_HIP_CHECK(hipGetLastError());
+        lo = hi;
     }
+    LS_HIP_CHECK(hipMemcpyAsync(&total, acc, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    LS_HIP_CHECK(hipStreamSynchronize(st));
     return static_cast<uint64_t>(total);
 }
+
+uint64_t candidates_of(const GroupPlan &gp, int32_t weight) {
+    const uint32_t n = gp.n_sites;
+    if (weight >= 0) return host_binom(n, static_cast<uint32_t>(weight));
+    return n == 64 ? ~0ULL : (1ULL << n);
+}
+
+}  // namespace
 
 uint64_t count_members(ls_basis *b, uint64_t begin, uint64_t end, hipStream_t st) {
     const uint64_t total = candidate_count(b);
     end = std::min(end, total);
     if (begin >= end) return 0;
-    return b->plan.n_sites <= 32 ? count_impl<uint32_t>(b, begin, end, st) : count_impl<uint64_t>(b, begin, end, st);
+    StreamBuf acc_b(sizeof(unsigned long long), st);
+    unsigned long long *acc = acc_b.as<unsigned long long>();
+    const GroupPlan &gp = b->plan;
+    return gp.n_sites <= 32 ? count_impl<uint32_t>(gp, b->plan_dev, b->d_binom, b->weight, begin, end, acc, st)
+                            : count_impl<uint64_t>(gp, b->plan_dev, b->d_binom, b->weight, begin, end, acc, st);
+}
+
+// ---- the allocation-free count --------------------------------------------
+//
+// The same count for callers that cannot allocate device memory: the
+// compiled group's tables and the accumulator live in `scratch`, a
+// file-scope device array of kCountScratchBytes that each GPU holds for the
+// life of the process.  Host code never passes the array's name to a
+// kernel or a copy (on the host it is only a stand-in symbol): the device
+// address of each GPU's copy is taken once with hipGetSymbolAddress, with
+// that GPU current, and used everywhere.  Calls are serialised by a
+// process-wide lock, since every call on a GPU shares its array; calls from
+// several processes on one GPU use separate arrays.
+
+constexpr size_t kCountScratchBytes = 256 * 1024;
+static __device__ __align__(256) unsigned char scratch[kCountScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[256] = {};   // per device ordinal
+
+void *scratch_address(int dev) {
+    if (dev < 0 || dev >= 256) throw Error{LS_EDEVICE, "device ordinal out of range"};
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            throw Error{LS_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+uint64_t count_members_noalloc(const GroupPlan &gp, int32_t weight, uint64_t begin, uint64_t end, hipStream_t st,
+                               uint64_t *n_candidates) {
+    const uint64_t total = candidates_of(gp, weight);
+    if (n_candidates) *n_candidates = total;
+    end = std::min(end, total);
+    // layout: accumulator | binomials | cosets | characters | chi == 1 bits | pair table
+    const PlanTables t = plan_tables();
+    const size_t o_binom = 256;
+    const size_t o_cos = align_up(o_binom + t.binom.size() * sizeof(uint64_t), 256);
+    const size_t o_chi = align_up(o_cos + gp.cosets.size() * sizeof(CosetRep), 256);
+    const size_t o_one = align_up(o_chi + gp.chi.size() / 2 * sizeof(double2), 256);
+    const size_t o_lut = align_up(o_one + gp.chi_one.size() * sizeof(uint32_t), 256);
+    const size_t need = o_lut + (gp.torus ? gp.pair_lut.size() * sizeof(uint32_t) : 0);
+    if (need > kCountScratchBytes)
+        throw Error{LS_EINVAL, "the compiled group needs " + std::to_string(need) + " bytes of device tables, above the " +
+                                   std::to_string(kCountScratchBytes) +
+                                   "-byte scratch of the allocation-free count (use ls_sector_count)"};
+    if (begin >= end) return 0;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    int dev = 0;
+    LS_HIP_CHECK(hipGetDevice(&dev));
+    unsigned char *base = static_cast<unsigned char *>(scratch_address(dev));
+    auto put = [&](size_t off, const void *src, size_t bytes) {
+        if (bytes) LS_HIP_CHECK(hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, st));
+    };
+    put(o_binom, t.binom.data(), t.binom.size() * sizeof(uint64_t));
+    put(o_cos, gp.cosets.data(), gp.cosets.size() * sizeof(CosetRep));
+    put(o_chi, gp.chi.data(), gp.chi.size() * sizeof(double));
+    put(o_one, gp.chi_one.data(), gp.chi_one.size() * sizeof(uint32_t));
+    PlanDev pd{};
+    fill_plan_dev(gp, pd);
+    pd.cosets = reinterpret_cast<const CosetRep *>(base + o_cos);
+    pd.chi = reinterpret_cast<const double2 *>(base + o_chi);
+    pd.chi_one = reinterpret_cast<const uint32_t *>(base + o_one);
+    if (gp.torus) {
+        put(o_lut, gp.pair_lut.data(), gp.pair_lut.size() * sizeof(uint32_t));
+        pd.pair_lut = reinterpret_cast<const uint32_t *>(base + o_lut);
+    }
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(base);
+    const uint64_t *binom = reinterpret_cast<const uint64_t *>(base + o_binom);
+    return gp.n_sites <= 32 ? count_impl<uint32_t>(gp, pd, binom, weight, begin, end, acc, st)
+                            : count_impl<uint64_t>(gp, pd, binom, weight, begin, end, acc, st);
 }
 
 void build_basis(ls_basis *b, hipStream_t st) {

@@ -200,6 +200,10 @@ void build_basis(ls_basis *b, hipStream_t stream);
 // Members among the candidates of colex rank [begin, end) (end clamped to
 // the number of candidates); the plan must be uploaded.
 uint64_t count_members(ls_basis *b, uint64_t begin, uint64_t end, hipStream_t stream);
+// The same count with the compiled group and the accumulator in a static
+// device array (no device allocation); *n_candidates = C(N, w) or 2^N.
+uint64_t count_members_noalloc(const GroupPlan &gp, int32_t weight, uint64_t begin, uint64_t end,
+                               hipStream_t stream, uint64_t *n_candidates);
 void launch_state_info(const ls_basis *b, uint64_t n, const uint64_t *states, uint64_t *reps,
                        double *chi, double *norm, hipStream_t stream);
 void launch_index_lookup(const ls_basis *b, uint64_t n, const uint64_t *keys, int64_t *index,
