@@ -27,6 +27,11 @@ PEAK_HBM = 8.0e12            # B/s, MI355X HBM3E
 # Integer/logic VALU lane-operations per second: 256 CUs x 4 SIMDs x 16
 # lanes per clock x 2.4 GHz (one 32-bit op per lane per clock).
 PEAK_VALU = 256 * 64 * 2.4e9
+# Algorithmic HBM bytes of the on-the-fly product: per row the
+# representative, x_i and y_i (8 B each); per off-diagonal element the
+# gathered x_j and the matched key of stateToIndex (8 B each).
+ALG_ROW_BYTES = 24
+ALG_ELEMENT_BYTES = 16
 
 
 def workload(name: str):
@@ -54,42 +59,127 @@ def count_elements(reps, term_table):
     return n_off, len(reps)
 
 
+def host_cores() -> int:
+    """Host threads for the oracle: the GPU's share of the host (at most 16)."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
 def cpu_baseline(sector, budget_s: float):
-    """The oracle's getRow timed on the host: rows drawn by the oracle itself
-    (seeded random states of the sector's weight -> their representatives
-    in the sector), processed until the time budget is spent."""
+    """The oracle's getRow timed on the host cores, as it stands: rows drawn
+    by the oracle itself (seeded random states of the sector's weight ->
+    their representatives in the sector), first on one thread, then split
+    over all host cores (rows in parallel), each until its share of the time
+    budget is spent."""
     import numpy as np
     import oracle
     from workloads import rng
     P = oracle.Problem(sector)
     n = sector.n_sites
     w = sector.weight
-    # seeded random weight-w states
-    states = []
-    st = rng.Stream(2024)
-    while len(states) < 4096:
-        bits = list(range(n))
-        for i in range(n - 1, 0, -1):
-            j = st.randint(0, i + 1)
-            bits[i], bits[j] = bits[j], bits[i]
-        states.append(sum(1 << b for b in bits[:w]))
-    reps, chi, norm = oracle.state_info(P, np.array(states, dtype=np.uint64))
+    # seeded random weight-w states: the w sites with the smallest counter
+    # values of each row of an m x n draw
+    m = 65536
+    keys = rng.counter_u64(2024, np.arange(m * n, dtype=np.uint64)).reshape(m, n)
+    sites = np.argsort(keys, axis=1, kind="stable")[:, :w].astype(np.uint64)
+    states = np.bitwise_or.reduce(np.left_shift(np.uint64(1), sites), axis=1)
+    reps, chi, norm = oracle.state_info(P, states, workers=host_cores())
     rows = np.unique(reps[norm > 0])
     off = sector.terms[sector.terms["flip"] != 0]
+    acting = [int(np.count_nonzero((np.uint64(r) & off["sel_mask"]) == off["sel_value"])) + 1 for r in rows]
+
+    # one thread
     t0 = time.perf_counter()
-    elems = 0
-    done = 0
-    for r in rows:
+    e1 = d1 = 0
+    for r, a in zip(rows, acting):
         oracle.get_row(P, int(r))
-        acting = int(np.count_nonzero((np.uint64(r) & off["sel_mask"]) == off["sel_value"]))
-        elems += acting + 1
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
+        e1 += a
+        d1 += 1
+        if time.perf_counter() - t0 > budget_s / 3:
             break
-    dt = time.perf_counter() - t0
-    return {"value": elems / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"getRow of {done} representatives (drawn by the oracle from seeded random "
-                      f"weight-{w} states), {elems} element applications in {dt:.1f} s, single thread"}
+    dt1 = time.perf_counter() - t0
+    # all host cores: the rows not used above, in chunks, until the budget is spent
+    cores = host_cores()
+    t0 = time.perf_counter()
+    ea = da = 0
+    k = d1
+    while k < len(rows) and time.perf_counter() - t0 < budget_s * 2 / 3:
+        chunk = rows[k:k + 64 * cores]
+        oracle.get_rows(P, chunk, workers=cores)
+        ea += sum(acting[k:k + len(chunk)])
+        da += len(chunk)
+        k += len(chunk)
+    dta = time.perf_counter() - t0
+    return {"value": ea / dta, "unit": "elements/s", "cores": cores, "kind": "oracle",
+            "sample": f"getRow of {da} representatives ({ea} element applications) in {dta:.1f} s on {cores} "
+                      f"host threads; rows drawn by the oracle from seeded random weight-{w} states",
+            "single_thread": {"value": e1 / dt1, "unit": "elements/s", "cores": 1,
+                              "sample": f"getRow of {d1} representatives, {e1} element applications in {dt1:.1f} s"},
+            "host_cpu_count": os.cpu_count()}
+
+
+def copy_peak(mib: int = 4096, reps: int = 5):
+    """A plain device-to-device copy (the HBM rate a streaming kernel can
+    reach on this GPU): bytes read + written per second, best of reps."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    stream = torch.cuda.current_stream()
+    best = 1e30
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        b.copy_(a)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes": 2 * n * 8, "ms": best, "gbps": 2 * n * 8 / (best * 1e-3) / 1e9,
+            "frac_of_spec": 2 * n * 8 / (best * 1e-3) / PEAK_HBM}
+
+
+def small_configs(steps: int):
+    """The product alone on the N=16 ring (no lattice symmetry) and the
+    N=32 symmetric ring: elements applied per second and the algorithmic HBM
+    rate, per product on the launch stream."""
+    import torch
+    import paper_2308_16712_amd as ls
+    from workloads import configs, rng
+
+    out = {}
+    for key, sec, desc in (("ring16", configs.ring16_u1(), "Heisenberg ring N=16, Sz=0, no lattice symmetry"),
+                           ("ring32", configs.ring32_symmetric(),
+                            "Heisenberg ring N=32, Sz=0, k=0, R=+1, Z=+1 (128)")):
+        b = ls.ls_basis_build(sec)
+        op = ls.ls_operator_create(b, sec.terms)
+        n_off = op.count_elements()
+        x = torch.from_numpy(rng.vector(sec.seed, b.dim)).cuda()
+        y = torch.empty_like(x)
+        ls.ls_matvec(op, x, y)
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = max(steps, 50 if b.dim < 1 << 20 else steps)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            ls.ls_matvec(op, x, y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        op.check()
+        elements = n_off + b.dim
+        alg = b.dim * ALG_ROW_BYTES + n_off * ALG_ELEMENT_BYTES
+        out[key] = {"workload": desc, "dim": b.dim, "elements_per_product": elements, "ms_per_product": ms,
+                    "elements_per_s": elements / (ms * 1e-3), "hbm_algorithmic_gbps": alg / (ms * 1e-3) / 1e9,
+                    "orbit_search": op.search_kind()[0]}
+        op.close()
+        b.close()
+    return out
 
 
 def batched_vs_plain(count: int, nrhs: int, reps_timed: int = 3):
@@ -140,18 +230,31 @@ def batched_vs_plain(count: int, nrhs: int, reps_timed: int = 3):
             for q in range(nrhs):
                 ls.ls_matvec(op, xl[q], yl[q])
 
+    ym = [torch.empty_like(x) for x in xs]
+
+    def plain_multi():
+        for op, x, y in zip(ops, xs, ym):
+            ls.ls_matvec(op, x, y)
+
     t_batch = timed(lambda: batch.matvec(xs, ys))
     t_plain = timed(plain)
+    t_multi = timed(plain_multi)
+    for op in ops:
+        op.check()
     # same results (the row arithmetic is shared)
     same = all(torch.equal(ys[k][:, q], yp[k][q]) for k in range(count) for q in range(nrhs))
+    same = same and all(torch.equal(ys[k], ym[k]) for k in range(count))
     dims = [op.dim for op in ops]
     return {"sectors": count, "nrhs": nrhs, "dtype": "c128", "dim_min": min(dims), "dim_max": max(dims),
             "dim_total": int(sum(dims)), "element_applications": elements,
             "batched_ms": t_batch, "plain_ms": t_plain, "speedup": t_plain / t_batch,
+            "plain_multi_rhs_ms": t_multi, "speedup_vs_plain_multi_rhs": t_multi / t_batch,
             "batched_elements_per_s": elements / (t_batch * 1e-3),
             "plain_elements_per_s": elements / (t_plain * 1e-3),
             "identical_results": bool(same), "launches_batched": batch.info()["launches"],
-            "launches_plain": count * nrhs, "basis_build_s": build_s}
+            "launches_plain": count * nrhs, "launches_plain_multi_rhs": count, "basis_build_s": build_s,
+            "note": "plain: one single-column ls_matvec per sector and column; plain_multi_rhs: one "
+                    f"{nrhs}-column ls_matvec per sector (the columns share each orbit search, as in the batch)"}
 
 
 def serving(count: int, rate: float, budget_gb: float, max_iter: int, tol: float):
@@ -270,10 +373,12 @@ def lanczos_leg(steps: int = 100):
     return out
 
 
-def stored_product(basis, sector, x, y, fly_ms: float, elements: int, steps: int):
+def stored_product(basis, sector, x, y, fly_ms: float, elements: int, n_off: int, steps: int, workload: str):
     """The same product from stored elements (ls_operator_store): store time
-    and size, product time on the launch stream, and bit-identity with the
-    on-the-fly result."""
+    and size, product time on the launch stream, bit-identity with the
+    on-the-fly result, and the HBM roofline of the stored product
+    (algorithmic bytes: the stored form read once, one x_j gather per
+    off-diagonal element, x_i and y_i per row)."""
     import torch
     import paper_2308_16712_amd as ls
 
@@ -299,12 +404,21 @@ def stored_product(basis, sector, x, y, fly_ms: float, elements: int, steps: int
     ls.ls_matvec(fly, x, y)
     torch.cuda.synchronize()
     same = bool(torch.equal(y, y2))
+    op.check()
     op.close()
     fly.close()
     del y2
     torch.cuda.empty_cache()
+    rows = basis.dim
+    alg = nbytes + n_off * 8 + rows * 16
+    roof = {"bound": "hbm", "kernel": "k_spmv", "kernel_ms": ms, "achieved": alg / (ms * 1e-3) / 1e9,
+            "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": alg / (ms * 1e-3) / PEAK_HBM,
+            "algorithmic_bytes_per_launch": alg,
+            "algorithmic_model": "stored form read once + 8 B x_j gather per off-diagonal element + "
+                                 "x_i and y_i per row"}
+    roof.update(counter_fields(counter_record("k_spmv", workload), ms, elements, alg))
     return {"bytes": nbytes, "store_s": store_s, "ms_per_product": ms, "elements_per_s": elements / (ms * 1e-3),
-            "speedup_vs_on_the_fly": fly_ms / ms, "identical_to_on_the_fly": same,
+            "speedup_vs_on_the_fly": fly_ms / ms, "identical_to_on_the_fly": same, "roofline": roof,
             "layout": "sliced ELLPACK, 64-row slices, uint32 column + value per slot"}
 
 
@@ -408,25 +522,52 @@ def enumeration(count_ns, build_n):
     return out
 
 
-# the sources that make up the product kernel: a counter record taken on
-# other sources no longer describes it
-TRAFFIC_SOURCES = ("matvec.hip", "matvec_impl.hpp", "dispatch.hpp", "orbit.hpp")
+# the sources of each profiled kernel: a counter record taken on other
+# sources no longer describes it
+KERNEL_SOURCES = {
+    "k_matvec": ("matvec.hip", "matvec_impl.hpp", "dispatch.hpp", "orbit.hpp"),
+    "k_spmv": ("stored.hip", "matvec_impl.hpp"),
+}
 
 
-def traffic_record(name: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source."""
+def sources_sha256(kernel: str) -> str:
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"traffic_matvec_{name}.json")
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_2308_16712_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def counter_record(kernel: str, name: str):
+    """The committed rocprofv3 counter record of a kernel on a workload
+    (HBM bytes per launch from FETCH_SIZE / WRITE_SIZE, VALU and LDS
+    counters per launch), if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"counters_{kernel}_{name}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2308_16712_amd", "csrc", f), "rb").read())
-    if rec.get("kernel_source_sha256") != h.hexdigest():
+    if rec.get("kernel_source_sha256") != sources_sha256(kernel):
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def counter_fields(rec, kernel_ms: float, elements: int, alg_bytes: float) -> dict:
+    """Executed work of a launch from its counter record, over the live
+    kernel time."""
+    if rec is None:
+        return {"traffic": None, "counters": "no record taken on the current kernel sources"}
+    t = kernel_ms * 1e-3
+    tb = rec["bytes_per_launch"]
+    out = {"traffic": tb, "traffic_gbps": tb / t / 1e9, "traffic_frac_of_hbm_peak": tb / t / PEAK_HBM,
+           "traffic_over_algorithmic": tb / alg_bytes}
+    c = rec.get("counters_per_launch", {})
+    if "SQ_INSTS_VALU" in c:
+        out["valu_executed_frac"] = c["SQ_INSTS_VALU"] * 64 / t / PEAK_VALU
+        out["valu_lane_instructions_per_element"] = c["SQ_INSTS_VALU"] * 64 / elements
+    if "SQ_INSTS_LDS" in c and c["SQ_INSTS_LDS"] > 0 and "SQ_LDS_BANK_CONFLICT" in c:
+        out["lds_bank_conflict_cycles_per_lds_instruction"] = c["SQ_LDS_BANK_CONFLICT"] / c["SQ_INSTS_LDS"]
+    out["counter_record"] = rec.get("file")
+    return out
 
 
 def main():
@@ -449,6 +590,7 @@ def main():
     ap.add_argument("--no-stored", action="store_true", help="skip the stored-elements product")
     ap.add_argument("--no-push", action="store_true", help="skip the push (atomic) product")
     ap.add_argument("--no-lanczos", action="store_true", help="skip the 100-step Lanczos leg (ring N=32)")
+    ap.add_argument("--no-small", action="store_true", help="skip the N=16 and N=32 ring products")
     ap.add_argument("--chains", default="40,42", help="paper-workload chain sizes to time (empty: none)")
     ap.add_argument("--enum-counts", default="40,42", help="chain sizes counted without storage")
     ap.add_argument("--enum-build", type=int, default=40, help="chain size built and stored (0: none)")
@@ -513,20 +655,22 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     value = elements * args.steps / wall
 
+    alg_bytes = rows * ALG_ROW_BYTES + n_off * ALG_ELEMENT_BYTES
+    achieved = alg_bytes / (kernel_ms * 1e-3)
+    roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM, "kernel": "k_matvec", "kernel_ms": kernel_ms,
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "algorithmic_model": f"{ALG_ROW_BYTES} B per row (representative, x_i, y_i) + {ALG_ELEMENT_BYTES} B "
+                                 "per off-diagonal element (x_j, matched key)"}
+    roof.update(counter_fields(counter_record("k_matvec", args.workload), kernel_ms, elements, alg_bytes))
+    # the exhaustive-search model of round one, kept under its own name: one
+    # compare-select per group image and 32-bit word for every element
     words = (sector.n_sites + 31) // 32
-    ops_per_launch = float(n_off) * sector.group.size * words
-    achieved_ops = ops_per_launch / (kernel_ms * 1e-3)
-    roof = {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": PEAK_VALU / 1e12, "unit": "TOP/s",
-            "frac": achieved_ops / PEAK_VALU, "traffic": traffic_record(args.workload),
-            "kernel": "k_matvec", "kernel_ms": kernel_ms,
-            "ops_model": f"{sector.group.size} group images x {words} word-min per off-diagonal element"}
-    alg_bytes = rows * (8 + 8 + 8 + 2) + n_off * (8 + 8 + 2)
-    if roof["traffic"] is not None:
-        # the HBM-side view: counter bytes per launch over the live kernel time
-        t_bps = roof["traffic"] / (kernel_ms * 1e-3)
-        roof["traffic_gbps"] = t_bps / 1e9
-        roof["traffic_frac_of_hbm_peak"] = t_bps / PEAK_HBM
-        roof["gather_efficiency"] = alg_bytes / roof["traffic"]
+    dense_ops = float(n_off) * sector.group.size * words
+    roof["dense_equivalent_ops_frac"] = dense_ops / (kernel_ms * 1e-3) / PEAK_VALU
+    cp = copy_peak()
+    roof["measured_copy_gbps"] = cp["gbps"]
+    roof["frac_of_measured_copy"] = achieved / (cp["gbps"] * 1e9)
     out = {
         "metric": "H matrix elements/s", "value": value, "unit": "elements/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
@@ -534,18 +678,22 @@ def main():
         "config": {"workload": desc, "dim": basis.dim, "elements_per_step": elements,
                    "group_order": sector.group.size, "nrhs": 1},
         "roofline": roof,
-        "hbm_algorithmic_gbps": alg_bytes / (kernel_ms * 1e-3) / 1e9,
         "basis_build_s": build_s,
         "orbit_search": dict(zip(("kind", "compile_time_shape"), op.search_kind())),
+        "copy_peak": cp,
     }
+    op.check()
     if not args.no_push:
         print("[bench] push form", file=sys.stderr, flush=True)
         out["push"] = push_product(op, x, kernel_ms, elements, args.steps)
     if not args.no_stored:
         print("[bench] stored elements", file=sys.stderr, flush=True)
-        out["stored"] = stored_product(basis, sector, x, y, kernel_ms, elements, args.steps)
+        out["stored"] = stored_product(basis, sector, x, y, kernel_ms, elements, n_off, args.steps, args.workload)
     del x, y, op, basis
     torch.cuda.empty_cache()
+    if not args.no_small:
+        print("[bench] ring16 and ring32 products", file=sys.stderr, flush=True)
+        out["small_configs"] = small_configs(args.steps)
     if not args.no_batched:
         print("[bench] batched vs plain", file=sys.stderr, flush=True)
         out["batched"] = batched_vs_plain(args.batched_count, args.batched_nrhs)

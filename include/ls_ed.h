@@ -215,13 +215,17 @@ ls_status ls_operator_info(const ls_operator *op, int *is_complex, uint64_t *dim
  * elements on the fly because a stored H does not fit its machines
  * (Section 2.2); where it fits one GPU, a stored product is bound by memory
  * traffic rather than by the orbit searches.  Layout: sliced ELLPACK over
- * slices of 64 consecutive rows (uint32 column and double / complex128 value
- * per slot, plus each row's diagonal sum).
+ * slices of 64 consecutive rows (a uint32 column per slot, plus each row's
+ * diagonal sum); a real operator with at most 256 distinct element values
+ * stores a one-byte code per slot into a table of those values (5 bytes a
+ * slot), otherwise each slot holds its double / complex128 value.
  *   max_bytes  refuse (LS_ENOMEM, operator unchanged) if the stored form
  *              would need more device memory than this.
  *   bytes      out (may be NULL): device bytes held by the stored form.
- * Afterwards ls_matvec, ls_lanczos and single-solve ls_solver_step use the
- * stored elements; batched and fused products keep generating them.  Both
+ * Afterwards ls_matvec, ls_lanczos and ls_solver_step use the stored
+ * elements (in a step over several solves a stored solve takes its own
+ * stored product beside the fused launch of the others); ls_batch_matvec
+ * keeps generating them.  Both
  * forms run the same row arithmetic in the same order and give identical
  * results bit for bit.  Storing again is a no-op.  This call changes the
  * operator: make it before the handle is shared by concurrent calls.
@@ -366,9 +370,9 @@ ls_status ls_lanczos(const ls_operator *op, const ls_lanczos_opts *opts, void *s
  * and arithmetic of ls_lanczos) with its Krylov vectors resident in HBM.
  * ls_solver_step advances every listed solver that is not done by one
  * iteration: the products of several solves run as one fused launch (the
- * batched kernel; a single solve takes ls_matvec's launch, or its stored
- * elements), alpha and beta stay on the device, and the step ends with one
- * synchronisation.  A solve stepped alone or among others produces the same
+ * batched kernel; a single solve takes ls_matvec's launch; a solve whose
+ * operator holds stored elements takes its stored product), alpha and beta
+ * stay on the device, and the step ends with one synchronisation.  A solve stepped alone or among others produces the same
  * numbers.  Calls to ls_solver_step are serialised inside the library.     */
 typedef struct ls_solver ls_solver;
 

@@ -217,6 +217,8 @@ void ls_operator_destroy(ls_operator *op) {
     hipFree(op->d_st_width);
     hipFree(op->d_st_cols);
     hipFree(op->d_st_vals);
+    hipFree(op->d_st_codes);
+    hipFree(op->d_st_vtab);
     hipFree(op->d_st_diag);
     delete op;
 }

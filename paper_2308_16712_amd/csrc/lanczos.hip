@@ -696,10 +696,25 @@ void solver_step(ls_solver *const *ss, uint32_t n, hipStream_t st) {
         xs.push_back(static_cast<const char *>(s->V) + static_cast<size_t>(s->k) * s->n * es);
         ys.push_back(s->w);
     }
-    // a single solve takes the single launch (its tuned shape; the row code,
-    // and so every result bit, is the same in both launches)
-    if (act.size() == 1) launch_matvec(ops[0], 1, xs[0], ys[0], st);
-    else fused_matvec(g_fused, static_cast<uint32_t>(act.size()), ops.data(), xs.data(), ys.data(), st);
+    // a solve whose operator holds stored elements takes its stored product;
+    // the others share one fused launch, or take the single launch when
+    // alone (its tuned shape).  The row arithmetic, and so every result bit,
+    // is the same in all three.
+    std::vector<const ls_operator *> fops;
+    std::vector<const void *> fxs;
+    std::vector<void *> fys;
+    for (size_t i = 0; i < ops.size(); ++i) {
+        if (ops[i]->stored) {
+            launch_matvec(ops[i], 1, xs[i], ys[i], st);
+        } else {
+            fops.push_back(ops[i]);
+            fxs.push_back(xs[i]);
+            fys.push_back(ys[i]);
+        }
+    }
+    if (fops.size() == 1) launch_matvec(fops[0], 1, fxs[0], fys[0], st);
+    else if (fops.size() > 1)
+        fused_matvec(g_fused, static_cast<uint32_t>(fops.size()), fops.data(), fxs.data(), fys.data(), st);
     for (ls_solver *s : act) {
         if (s->cplx) enqueue_after_product<true>(s, st);
         else enqueue_after_product<false>(s, st);

@@ -183,7 +183,9 @@ struct ls_operator {
     uint64_t *d_st_off = nullptr;       // [slices] first slot of each slice
     uint32_t *d_st_width = nullptr;     // [slices] elements per row in the slice
     uint32_t *d_st_cols = nullptr;      // [slots] column, or ~0 for none
-    void *d_st_vals = nullptr;          // [slots] double or double2
+    void *d_st_vals = nullptr;          // [slots] double or double2 (full values)
+    uint8_t *d_st_codes = nullptr;      // [slots] value codes (coded form, real operators)
+    uint64_t *d_st_vtab = nullptr;      // [256] the coded form's values (double bit patterns)
     void *d_st_diag = nullptr;          // [dim] diagonal sum, double or double2
 };
 

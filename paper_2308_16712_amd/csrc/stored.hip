@@ -4,8 +4,8 @@
 // The paper generates elements on the fly because a stored Hamiltonian does
 // not fit the memory of its machines (Section 2.2); one GPU with 288 GB of
 // HBM holds the elements of sectors with up to a few billion of them (the
-// 6x6 J1-J2 sector: 1.19e9 elements, 14 GB), and a product then reads them
-// at HBM speed instead of redoing the orbit searches.
+// 6x6 J1-J2 sector: 1.19e9 elements), and a product then reads them at HBM
+// speed instead of redoing the orbit searches.
 //
 // Layout (sliced ELLPACK, slice = 64 consecutive rows = one wavefront): for
 // slice g of width w_g (the most off-diagonal terms acting on one of its
@@ -15,9 +15,18 @@
 // basis, and padding, hold column kNoCol.  The diagonal sum of each row is
 // stored separately.
 //
+// Values.  A real operator has few distinct element values (a coupling
+// times a sign times sqrt(stab_j / stab_i), times a real character), so a
+// slot holds a one-byte code into a table of at most 256 values (the table
+// is filled during the store by an open-addressing set of the values' bit
+// patterns, and staged in LDS by the product): 5 bytes per slot instead of
+// 12.  When a sector has more than 256 distinct values, or the operator is
+// complex, the slots hold the values themselves.
+//
 // The store runs the same row code as the on-the-fly product (diag_sum,
 // neighbour_rep, lookup, element_value) and the stored product accumulates
-// in the same order with the same operations, so both give the same bits.
+// in the same order with the same operations on the same value bits, so
+// both give the same results bit for bit.
 
 #include <algorithm>
 #include <vector>
@@ -30,6 +39,8 @@ namespace {
 
 constexpr uint32_t kSlice = 64;
 constexpr uint32_t kNoCol = 0xFFFFFFFFu;
+constexpr uint32_t kCodes = 256;                       // values of the coded form
+constexpr uint64_t kNoValue = 0xFFFFFFFFFFFFFFFFull;   // free entry (a NaN pattern no element takes)
 
 // Width of every slice: the most acting off-diagonal terms over its rows.
 __global__ void __launch_bounds__(256) k_slice_width(const uint64_t *reps, uint64_t dim, const ls_term_dev *terms,
@@ -49,9 +60,35 @@ struct StoreArgs {
     MatvecJob job;
     const uint64_t *off;     // [slices]
     uint32_t *cols;          // [slots]
-    void *vals;              // [slots] double or double2
+    void *vals;              // [slots] double or double2 (full values), or null
+    uint8_t *codes;          // [slots] value codes (coded form), or null
+    uint64_t *vtab;          // [kCodes] value bit patterns of the coded form
+    uint32_t *overflow;      // set when the coded form needs more than kCodes values
     void *diag;              // [dim] double (dre) or double2 (dre, dim)
 };
+
+// Code of a value in the coded form's table: linear probing over the
+// table from a hash of the value's bits; a free entry is claimed with a
+// compare-and-swap (entries only ever go from free to a value, so a stale
+// read of a free entry is settled by the swap's result).  All kCodes
+// entries taken by other values: the overflow flag is raised.
+__device__ __forceinline__ uint32_t value_code(double v, uint64_t *vtab, uint32_t *overflow) {
+    const uint64_t bits = static_cast<uint64_t>(__double_as_longlong(v));
+    uint32_t h = static_cast<uint32_t>((bits * 0x9E3779B97F4A7C15ull) >> 56);
+    for (uint32_t n = 0; n < kCodes; ++n) {
+        const uint64_t k = __hip_atomic_load(&vtab[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == bits) return h;
+        if (k == kNoValue) {
+            const unsigned long long prev = atomicCAS(reinterpret_cast<unsigned long long *>(&vtab[h]),
+                                                      static_cast<unsigned long long>(kNoValue),
+                                                      static_cast<unsigned long long>(bits));
+            if (prev == kNoValue || prev == bits) return h;
+        }
+        h = (h + 1) & (kCodes - 1);
+    }
+    atomicOr(overflow, 1u);
+    return 0;
+}
 
 template <typename W, int KIND, int CHI, bool CPLX, uint32_t LX, uint32_t LY, uint32_t NZ>
 __global__ void __launch_bounds__(block_of(KIND)) k_store(StoreArgs s) {
@@ -89,7 +126,13 @@ __global__ void __launch_bounds__(block_of(KIND)) k_store(StoreArgs s) {
             continue;
         }
         s.cols[slot] = static_cast<uint32_t>(j);
-        static_cast<T *>(s.vals)[slot] = element_value<CHI, CPLX>(Tm, r, st_j, st_i, a.plan, code);
+        const T v = element_value<CHI, CPLX>(Tm, r, st_j, st_i, a.plan, code);
+        if constexpr (CPLX) {
+            static_cast<T *>(s.vals)[slot] = v;
+        } else {
+            if (s.codes) s.codes[slot] = static_cast<uint8_t>(value_code(v, s.vtab, s.overflow));
+            else static_cast<T *>(s.vals)[slot] = v;
+        }
     }
 }
 
@@ -111,12 +154,19 @@ struct StoreLaunch {
     }
 };
 
-// y = H x from the stored elements; one lane per row, NR columns.
-template <bool CPLX, int NR>
+// y = H x from the stored elements; one lane per row, NR columns.  CODED:
+// values through the code table (staged in LDS), else read per slot.
+template <bool CPLX, int NR, bool CODED>
 __global__ void __launch_bounds__(256) k_spmv(const uint64_t *off, const uint32_t *width, const uint32_t *cols,
-                                              const void *vals_, const void *diag_, uint64_t dim, uint32_t ld,
-                                              uint32_t col0, const void *x_, void *y_) {
+                                              const void *vals_, const uint8_t *codes, const uint64_t *vtab_g,
+                                              const void *diag_, uint64_t dim, uint32_t ld, uint32_t col0,
+                                              const void *x_, void *y_) {
     using T = typename Val<CPLX>::T;
+    __shared__ double vtab[CODED ? kCodes : 1];
+    if constexpr (CODED) {
+        for (uint32_t q = threadIdx.x; q < kCodes; q += 256) vtab[q] = __longlong_as_double(static_cast<long long>(vtab_g[q]));
+        __syncthreads();
+    }
     const uint64_t row = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (row >= dim) return;
     const T *x = static_cast<const T *>(x_);
@@ -136,6 +186,10 @@ __global__ void __launch_bounds__(256) k_spmv(const uint64_t *off, const uint32_
     const uint64_t g = row / kSlice;
     const uint32_t w = width[g];      // the same for the whole wavefront
     const uint64_t base = off[g] + (row & (kSlice - 1));
+    auto value = [&](uint64_t slot) -> T {
+        if constexpr (CODED) return vtab[codes[slot]];
+        else return vals[slot];
+    };
     // U elements per step: their columns, values and x gathers are all issued
     // before the first add, so U gathers per lane are in flight at once; the
     // adds keep the element order (same bits as the one-by-one loop).
@@ -148,7 +202,7 @@ __global__ void __launch_bounds__(256) k_spmv(const uint64_t *off, const uint32_
         for (int u = 0; u < U; ++u) {
             const uint64_t slot = base + static_cast<uint64_t>(k + u) * kSlice;
             j[u] = cols[slot];
-            v[u] = vals[slot];
+            v[u] = value(slot);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -167,7 +221,7 @@ __global__ void __launch_bounds__(256) k_spmv(const uint64_t *off, const uint32_
         const uint64_t slot = base + static_cast<uint64_t>(k) * kSlice;
         const uint32_t j = cols[slot];
         if (j == kNoCol) continue;
-        const T v = vals[slot];
+        const T v = value(slot);
 #pragma unroll
         for (int q = 0; q < NR; ++q) accumulate(acc[q], v, x[static_cast<uint64_t>(j) * ld + col0 + q]);
     }
@@ -175,30 +229,41 @@ __global__ void __launch_bounds__(256) k_spmv(const uint64_t *off, const uint32_
     for (int q = 0; q < NR; ++q) y[row * ld + col0 + q] = acc[q];
 }
 
-template <bool CPLX>
+template <bool CPLX, bool CODED>
 void launch_spmv_nr(const ls_operator *op, int nr, uint32_t nrhs, uint32_t col, const void *x, void *y,
                     hipStream_t st) {
     const uint64_t dim = op->basis->dim;
     const dim3 grid(static_cast<uint32_t>((dim + 255) / 256));
+#define LS_SPMV(NRV)                                                                                                \
+    hipLaunchKernelGGL((k_spmv<CPLX, NRV, CODED>), grid, dim3(256), 0, st, op->d_st_off, op->d_st_width,          \
+                       op->d_st_cols, op->d_st_vals, op->d_st_codes, op->d_st_vtab, op->d_st_diag, dim, nrhs, col, \
+                       x, y)
     switch (nr) {
-        case 8:
-            hipLaunchKernelGGL((k_spmv<CPLX, 8>), grid, dim3(256), 0, st, op->d_st_off, op->d_st_width, op->d_st_cols,
-                               op->d_st_vals, op->d_st_diag, dim, nrhs, col, x, y);
-            break;
-        case 4:
-            hipLaunchKernelGGL((k_spmv<CPLX, 4>), grid, dim3(256), 0, st, op->d_st_off, op->d_st_width, op->d_st_cols,
-                               op->d_st_vals, op->d_st_diag, dim, nrhs, col, x, y);
-            break;
-        case 2:
-            hipLaunchKernelGGL((k_spmv<CPLX, 2>), grid, dim3(256), 0, st, op->d_st_off, op->d_st_width, op->d_st_cols,
-                               op->d_st_vals, op->d_st_diag, dim, nrhs, col, x, y);
-            break;
-        default:
-            hipLaunchKernelGGL((k_spmv<CPLX, 1>), grid, dim3(256), 0, st, op->d_st_off, op->d_st_width, op->d_st_cols,
-                               op->d_st_vals, op->d_st_diag, dim, nrhs, col, x, y);
-            break;
+        case 8: LS_SPMV(8); break;
+        case 4: LS_SPMV(4); break;
+        case 2: LS_SPMV(2); break;
+        default: LS_SPMV(1); break;
     }
+#undef LS_SPMV
 }
+
+// Device buffers of a store attempt, released unless handed to the operator.
+struct StoreBufs {
+    uint32_t *width = nullptr, *cols = nullptr, *overflow = nullptr;
+    uint64_t *off = nullptr, *vtab = nullptr;
+    void *vals = nullptr, *diag = nullptr;
+    uint8_t *codes = nullptr;
+    ~StoreBufs() {
+        hipFree(width);
+        hipFree(off);
+        hipFree(cols);
+        hipFree(vals);
+        hipFree(codes);
+        hipFree(vtab);
+        hipFree(overflow);
+        hipFree(diag);
+    }
+};
 
 }  // namespace
 
@@ -208,66 +273,85 @@ uint64_t store_elements(ls_operator *op, uint64_t max_bytes, hipStream_t st) {
     const uint64_t dim = b->dim;
     const uint64_t slices = (dim + kSlice - 1) / kSlice;
     const size_t es = op->is_complex ? sizeof(double2) : sizeof(double);
+    StoreBufs B;
     std::vector<uint32_t> width(slices, 0);
     std::vector<uint64_t> off(slices, 0);
-    uint32_t *d_width = nullptr;
     if (slices > 0) {
-        LS_HIP_CHECK(hipMalloc(&d_width, slices * sizeof(uint32_t)));
+        LS_HIP_CHECK(hipMalloc(&B.width, slices * sizeof(uint32_t)));
         hipLaunchKernelGGL(k_slice_width, dim3(static_cast<uint32_t>((dim + 255) / 256)), dim3(256), 0, st, b->d_reps,
-                           dim, op->d_terms, op->n_diag, op->n_diag + op->n_off, d_width);
-        const hipError_t e = hipGetLastError();
-        if (e == hipSuccess) hipMemcpyAsync(width.data(), d_width, slices * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
-        const hipError_t e2 = hipStreamSynchronize(st);
-        if (e != hipSuccess || e2 != hipSuccess) {
-            hipFree(d_width);
-            throw Error{LS_EDEVICE, "slice widths failed"};
-        }
+                           dim, op->d_terms, op->n_diag, op->n_diag + op->n_off, B.width);
+        LS_HIP_CHECK(hipGetLastError());
+        LS_HIP_CHECK(hipMemcpyAsync(width.data(), B.width, slices * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        LS_HIP_CHECK(hipStreamSynchronize(st));
     }
     uint64_t slots = 0;
     for (uint64_t g = 0; g < slices; ++g) {
         off[g] = slots;
         slots += static_cast<uint64_t>(width[g]) * kSlice;
     }
-    const uint64_t bytes = slots * (sizeof(uint32_t) + es) + slices * (sizeof(uint64_t) + sizeof(uint32_t)) + dim * es;
-    if (bytes > max_bytes) {
-        hipFree(d_width);
-        throw Error{LS_ENOMEM, "the stored elements would exceed max_bytes"};
-    }
-    uint64_t *d_off = nullptr;
-    uint32_t *d_cols = nullptr;
-    void *d_vals = nullptr, *d_diag = nullptr;
-    auto release = [&]() {
-        hipFree(d_width);
-        hipFree(d_off);
-        hipFree(d_cols);
-        hipFree(d_vals);
-        hipFree(d_diag);
-    };
-    try {
-        if (hipMalloc(&d_off, std::max<uint64_t>(slices, 1) * sizeof(uint64_t)) != hipSuccess ||
-            hipMalloc(&d_cols, std::max<uint64_t>(slots, 1) * sizeof(uint32_t)) != hipSuccess ||
-            hipMalloc(&d_vals, std::max<uint64_t>(slots, 1) * es) != hipSuccess ||
-            hipMalloc(&d_diag, std::max<uint64_t>(dim, 1) * es) != hipSuccess)
+    const uint64_t fixed = slices * (sizeof(uint64_t) + sizeof(uint32_t)) + dim * es;
+    const uint64_t full_bytes = slots * (sizeof(uint32_t) + es) + fixed;
+    const uint64_t coded_bytes = slots * (sizeof(uint32_t) + 1) + kCodes * sizeof(uint64_t) + fixed;
+    bool coded = !op->is_complex;
+    uint64_t bytes = coded ? coded_bytes : full_bytes;
+    if (bytes > max_bytes) throw Error{LS_ENOMEM, "the stored elements would exceed max_bytes"};
+    auto alloc = [](void **p, uint64_t n) {
+        if (hipMalloc(p, std::max<uint64_t>(n, 1)) != hipSuccess)
             throw Error{LS_ENOMEM, "device allocation for the stored elements failed"};
-        if (slices > 0)
-            LS_HIP_CHECK(hipMemcpyAsync(d_off, off.data(), slices * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-        if (slots > 0) LS_HIP_CHECK(hipMemsetAsync(d_cols, 0xFF, slots * sizeof(uint32_t), st));
+    };
+    alloc(reinterpret_cast<void **>(&B.off), slices * sizeof(uint64_t));
+    alloc(reinterpret_cast<void **>(&B.cols), slots * sizeof(uint32_t));
+    alloc(&B.diag, dim * es);
+    if (slices > 0)
+        LS_HIP_CHECK(hipMemcpyAsync(B.off, off.data(), slices * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+    // one pass in the coded form; a second in the full form when the values
+    // do not fit the code table
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        if (coded) {
+            alloc(reinterpret_cast<void **>(&B.codes), slots);
+            alloc(reinterpret_cast<void **>(&B.vtab), kCodes * sizeof(uint64_t));
+            alloc(reinterpret_cast<void **>(&B.overflow), sizeof(uint32_t));
+            LS_HIP_CHECK(hipMemsetAsync(B.vtab, 0xFF, kCodes * sizeof(uint64_t), st));
+            LS_HIP_CHECK(hipMemsetAsync(B.overflow, 0, sizeof(uint32_t), st));
+        } else {
+            alloc(&B.vals, slots * es);
+        }
+        if (slots > 0) LS_HIP_CHECK(hipMemsetAsync(B.cols, 0xFF, slots * sizeof(uint32_t), st));
         if (dim > 0) {
-            StoreLaunch L{StoreArgs{job_of(op, nullptr, nullptr, 1, 0), d_off, d_cols, d_vals, d_diag}, st};
+            StoreLaunch L{StoreArgs{job_of(op, nullptr, nullptr, 1, 0), B.off, B.cols, B.vals, B.codes, B.vtab,
+                                    B.overflow, B.diag},
+                          st};
             dispatch(variant_of(op), 1, L);
             LS_HIP_CHECK(hipGetLastError());
         }
         // a lookup miss of an in-sector representative fails the store
         check_operator(op, st);
-    } catch (...) {
-        release();
-        throw;
+        if (!coded) break;
+        uint32_t over = 0;
+        LS_HIP_CHECK(hipMemcpyAsync(&over, B.overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        LS_HIP_CHECK(hipStreamSynchronize(st));
+        if (!over) break;
+        hipFree(B.codes);
+        hipFree(B.vtab);
+        hipFree(B.overflow);
+        B.codes = nullptr;
+        B.vtab = nullptr;
+        B.overflow = nullptr;
+        coded = false;
+        bytes = full_bytes;
+        if (bytes > max_bytes) throw Error{LS_ENOMEM, "the stored elements would exceed max_bytes"};
     }
-    op->d_st_width = d_width;
-    op->d_st_off = d_off;
-    op->d_st_cols = d_cols;
-    op->d_st_vals = d_vals;
-    op->d_st_diag = d_diag;
+    op->d_st_width = B.width;
+    op->d_st_off = B.off;
+    op->d_st_cols = B.cols;
+    op->d_st_vals = B.vals;
+    op->d_st_codes = B.codes;
+    op->d_st_vtab = B.vtab;
+    op->d_st_diag = B.diag;
+    B.width = B.cols = nullptr;
+    B.off = B.vtab = nullptr;
+    B.vals = B.diag = nullptr;
+    B.codes = nullptr;
     op->st_slots = slots;
     op->st_bytes = bytes;
     op->stored = true;
@@ -279,8 +363,9 @@ void launch_stored(const ls_operator *op, uint32_t nrhs, const void *x, void *y,
     uint32_t col = 0;
     while (col < nrhs) {
         const int nr = nr_chunk(nrhs - col);
-        if (op->is_complex) launch_spmv_nr<true>(op, nr, nrhs, col, x, y, st);
-        else launch_spmv_nr<false>(op, nr, nrhs, col, x, y, st);
+        if (op->is_complex) launch_spmv_nr<true, false>(op, nr, nrhs, col, x, y, st);
+        else if (op->d_st_codes) launch_spmv_nr<false, true>(op, nr, nrhs, col, x, y, st);
+        else launch_spmv_nr<false, false>(op, nr, nrhs, col, x, y, st);
         LS_HIP_CHECK(hipGetLastError());
         col += static_cast<uint32_t>(nr);
     }

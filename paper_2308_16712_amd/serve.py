@@ -17,15 +17,14 @@ cycles of the permutation).
 """
 from __future__ import annotations
 
+import threading
 import time
 from dataclasses import dataclass, field
-from typing import List, Optional
+from typing import Callable, Dict, List, Optional
 
 import numpy as np
 
-import threading
-
-from ._lib import Basis, LSError, Operator, Solver
+from ._lib import LS_EINTERNAL, Basis, LSError, Operator, Solver
 
 
 def _cycles(perm) -> List[int]:
@@ -108,6 +107,8 @@ class Record:
     e0: float = float("nan")
     iters: int = 0
     converged: bool = False
+    status: str = "ok"        # ok | rejected | failed | cancelled
+    error: str = ""
 
     @property
     def latency(self) -> float:
@@ -135,14 +136,16 @@ class ServeStats:
     step_s: float = 0.0       # Lanczos steps (or whole solves, one at a time)
 
     def summary(self) -> dict:
-        lat = np.array([r.latency for r in self.records]) * 1e3
-        return dict(requests=len(self.records), makespan_s=self.makespan,
-                    throughput_rps=len(self.records) / self.makespan if self.makespan > 0 else 0.0,
+        ok = [r for r in self.records if r.status == "ok"]
+        lat = np.array([r.latency for r in ok] or [0.0]) * 1e3
+        by = {k: sum(r.status == k for r in self.records) for k in ("ok", "rejected", "failed", "cancelled")}
+        return dict(requests=len(self.records), completed=len(ok), makespan_s=self.makespan,
+                    throughput_rps=len(ok) / self.makespan if self.makespan > 0 else 0.0,
                     p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                     mean_ms=float(lat.mean()), steps=self.steps, max_active=self.max_active,
                     peak_bytes=self.peak_bytes, build_s=self.build_s, step_s=self.step_s,
-                    stored_bytes=self.stored_bytes,
-                    converged=int(sum(r.converged for r in self.records)))
+                    stored_bytes=self.stored_bytes, status=by,
+                    converged=int(sum(r.converged for r in ok)))
 
 
 def _wait_until(t0: float, t: float):
@@ -177,7 +180,8 @@ def _pick(live, policy: str):
 
 
 def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=None,
-          policy: str = "sjf", store_elements: bool = False) -> ServeStats:
+          policy: str = "sjf", store_elements: bool = False, cancel: Optional[Dict[int, float]] = None,
+          on_built: Optional[Callable] = None) -> ServeStats:
     """Continuous batching: admit by footprint, advance the admitted solves
     with fused steps (see _pick), retire converged ones.  Arrivals are
     replayed in real time.
@@ -190,7 +194,17 @@ def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=N
     With store_elements, the builder also stores the operator's matrix
     elements (ls_operator_store) when they fit the budget left at that
     moment; the solve then steps with stored products (results identical bit
-    for bit) and the stored bytes count against the budget until it retires."""
+    for bit) and the stored bytes count against the budget until it retires.
+
+    One request cannot take the others down: a request whose footprint
+    exceeds the whole budget is rejected on arrival; a failed build, a
+    failed solver creation or a solve stopped by the library (LS_EINTERNAL,
+    a lookup miss in its product) fails that request only, and its memory
+    returns to the budget.  cancel maps a request id to a time (seconds
+    since the start) at which it is withdrawn, wherever it then is: queued,
+    building or stepping.  Every request ends with a record whose status is
+    ok, rejected, failed or cancelled.  on_built(request, basis, operator),
+    if given, is called after each build (a test hook)."""
     import torch
     from concurrent.futures import FIRST_COMPLETED, ThreadPoolExecutor, wait
 
@@ -199,17 +213,37 @@ def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=N
     live: List[_Live] = []
     building = []           # (request, bytes, record, future)
     needs = {}              # request id -> footprint bytes
+    cancel = dict(cancel or {})
     stats = ServeStats()
     step_stream = torch.cuda.Stream()
     build_stream = torch.cuda.Stream()
 
     lock = threading.Lock()
     budget = {"used": 0}
+    t0 = time.perf_counter()
+
+    def now():
+        return time.perf_counter() - t0
+
+    def finish(rec, status, error=""):
+        rec.status, rec.error = status, error
+        rec.done = now()
+        stats.records.append(rec)
+        if log and status != "ok":
+            log(f"[serve] t={rec.done:.3f}s {status} {rec.rid} {rec.name}: {error}")
+
+    def release(nbytes):
+        with lock:
+            budget["used"] -= nbytes
 
     def build(req):
         t = time.perf_counter()
         b = Basis.from_sector(req.sector, build_stream)
-        op = Operator(b, req.sector.terms)
+        try:
+            op = Operator(b, req.sector.terms)
+        except Exception:
+            b.close()
+            raise
         stored = 0
         if store_elements:
             with lock:      # reserve what is left of the budget for the store
@@ -221,32 +255,53 @@ def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=N
                 stored = 0
             with lock:      # keep what the store holds, return the rest
                 budget["used"] -= room - stored
+        if on_built is not None:
+            on_built(req, b, op)
         return b, op, stored, time.perf_counter() - t
 
+    def retire(lv, status, error=""):
+        lv.solver.close()
+        lv.op.close()
+        lv.basis.close()
+        release(lv.bytes)
+        finish(lv.rec, status, error)
+
     pool = ThreadPoolExecutor(max_workers=1)
-    t0 = time.perf_counter()
     i = 0
     try:
         with torch.cuda.stream(step_stream):
             while i < len(pending) or queue or live or building:
-                now = time.perf_counter() - t0
-                while i < len(pending) and pending[i].arrival <= now:
+                while i < len(pending) and pending[i].arrival <= now():
                     queue.append(pending[i])
                     i += 1
+                # withdrawn requests: queued ones leave at once, live ones now,
+                # building ones when their build returns
+                due = {rid for rid, tc in cancel.items() if tc <= now()}
+                for req in [q for q in queue if q.rid in due]:
+                    queue.remove(req)
+                    cancel.pop(req.rid)
+                    finish(Record(req.rid, req.sector.name, 0, req.arrival), "cancelled", "withdrawn while queued")
+                for lv in [lv for lv in live if lv.rec.rid in due]:
+                    live.remove(lv)
+                    cancel.pop(lv.rec.rid)
+                    retire(lv, "cancelled", f"withdrawn after {lv.solver.result()['iters']} steps")
                 # first-fit admission in arrival order; the build starts now
                 for req in list(queue):
                     if req.rid not in needs:     # the character formula runs once per request
                         needs[req.rid] = footprint_bytes(req.sector, max_iter)
                     need = needs[req.rid]
                     if need > hbm_budget:
-                        raise ValueError(f"request {req.rid} needs {need} bytes, more than the whole budget")
+                        queue.remove(req)
+                        finish(Record(req.rid, req.sector.name, 0, req.arrival), "rejected",
+                               f"needs {need} bytes, more than the whole budget of {hbm_budget}")
+                        continue
                     with lock:
                         if budget["used"] + need > hbm_budget:
                             continue
                         budget["used"] += need
                         stats.peak_bytes = max(stats.peak_bytes, budget["used"])
                     queue.remove(req)
-                    rec = Record(req.rid, req.sector.name, 0, req.arrival, admitted=time.perf_counter() - t0)
+                    rec = Record(req.rid, req.sector.name, 0, req.arrival, admitted=now())
                     building.append((req, need, rec, pool.submit(build, req)))
                 # finished builds join the live set
                 for item in list(building):
@@ -254,54 +309,86 @@ def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=N
                     if not fut.done():
                         continue
                     building.remove(item)
-                    b, op, stored, dt = fut.result()
+                    try:
+                        b, op, stored, dt = fut.result()
+                    except Exception as e:   # this request only
+                        release(need)
+                        finish(rec, "failed", f"build: {e}")
+                        continue
                     stats.build_s += dt
                     stats.stored_bytes += stored
                     with lock:
                         stats.peak_bytes = max(stats.peak_bytes, budget["used"])
-                    s = Solver(op, max_iter, tol=tol, seed=req.sector.seed)
                     rec.dim = b.dim
+                    if req.rid in cancel and cancel[req.rid] <= now():
+                        cancel.pop(req.rid)
+                        op.close()
+                        b.close()
+                        release(need + stored)
+                        finish(rec, "cancelled", "withdrawn while building")
+                        continue
+                    try:
+                        s = Solver(op, max_iter, tol=tol, seed=req.sector.seed)
+                    except LSError as e:
+                        op.close()
+                        b.close()
+                        release(need + stored)
+                        finish(rec, "failed", f"solver: {e}")
+                        continue
                     live.append(_Live(rec, b, op, s, need + stored))
                     if log:
-                        log(f"[serve] t={time.perf_counter() - t0:.3f}s start {req.rid} {req.sector.name} "
+                        log(f"[serve] t={now():.3f}s start {req.rid} {req.sector.name} "
                             f"dim={b.dim} active={len(live)}")
                 if live:
                     stats.max_active = max(stats.max_active, len(live))
                     step = _pick(live, policy)
                     ts = time.perf_counter()
-                    Solver.step_all([lv.solver for lv in step])
+                    try:
+                        Solver.step_all([lv.solver for lv in step])
+                    except LSError as e:
+                        # the stopped solves report LS_EINTERNAL in their result;
+                        # anything else is not a per-request condition
+                        if e.status != LS_EINTERNAL:
+                            raise
                     stats.step_s += time.perf_counter() - ts
                     stats.steps += 1
                     keep = []
                     stepped = {id(lv) for lv in step}
                     for lv in live:
-                        r = lv.solver.result() if id(lv) in stepped else {"done": False}
+                        if id(lv) not in stepped:
+                            keep.append(lv)
+                            continue
+                        try:
+                            r = lv.solver.result()
+                        except LSError as e:
+                            if e.status != LS_EINTERNAL:
+                                raise
+                            retire(lv, "failed", str(e))
+                            continue
                         if r["done"]:
-                            lv.rec.done = time.perf_counter() - t0
                             lv.rec.e0, lv.rec.iters, lv.rec.converged = r["e0"], r["iters"], r["converged"]
-                            stats.records.append(lv.rec)
-                            lv.solver.close()
-                            lv.op.close()
-                            lv.basis.close()
-                            with lock:
-                                budget["used"] -= lv.bytes
+                            retire(lv, "ok")
                         else:
                             keep.append(lv)
                     live = keep
                 elif building:
-                    wait([item[3] for item in building], return_when=FIRST_COMPLETED)
+                    wait([item[3] for item in building], return_when=FIRST_COMPLETED, timeout=0.05)
                 elif i < len(pending) and not queue:
-                    _wait_until(t0, pending[i].arrival)
+                    later = [tc for tc in cancel.values() if tc > now()]
+                    _wait_until(t0, min([pending[i].arrival] + later))
     finally:
         pool.shutdown(wait=True)
     step_stream.synchronize()
-    stats.makespan = time.perf_counter() - t0
+    stats.makespan = now()
     stats.records.sort(key=lambda r: r.rid)
     return stats
 
 
-def serve_one_at_a_time(trace, max_iter: int = 150, tol: float = 1e-10) -> ServeStats:
-    """Baseline: each request in arrival order, alone, with ls_lanczos."""
+def serve_one_at_a_time(trace, max_iter: int = 150, tol: float = 1e-10, store_elements: bool = False,
+                        hbm_budget: Optional[int] = None) -> ServeStats:
+    """Baseline: each request in arrival order, alone, with ls_lanczos.  With
+    store_elements each operator's elements are stored first (when they fit
+    hbm_budget less the request's footprint), as the server does."""
     pending = sorted(trace, key=lambda r: r.arrival)
     stats = ServeStats()
     t0 = time.perf_counter()
@@ -309,8 +396,20 @@ def serve_one_at_a_time(trace, max_iter: int = 150, tol: float = 1e-10) -> Serve
         _wait_until(t0, req.arrival)
         tb = time.perf_counter()
         rec = Record(req.rid, req.sector.name, 0, req.arrival, admitted=tb - t0)
+        need = footprint_bytes(req.sector, max_iter)
+        if hbm_budget is not None and need > hbm_budget:
+            rec.status, rec.error = "rejected", "footprint above the budget"
+            rec.done = time.perf_counter() - t0
+            stats.records.append(rec)
+            continue
         b = Basis.from_sector(req.sector)
         op = Operator(b, req.sector.terms)
+        if store_elements:
+            room = (hbm_budget if hbm_budget is not None else 1 << 62) - need
+            try:
+                stats.stored_bytes += op.store(max(room, 0))
+            except LSError:
+                pass
         ts = time.perf_counter()
         stats.build_s += ts - tb
         r = op.lanczos(max_iter, tol=tol, seed=req.sector.seed)

@@ -77,6 +77,20 @@ def test_stepper_against_oracle_lanczos():
     assert abs(s.result()["e0"] - want["e0"]) < 1e-10 * max(1, abs(want["e0"]))
 
 
+_EXACT = {}
+
+
+def _exact_e0(sec):
+    """Lowest eigenvalue of the oracle's sector Hamiltonian (its getRow
+    matrix, diagonalised densely)."""
+    if sec.name not in _EXACT:
+        P = oracle.Problem(sec)
+        reps, _ = oracle.enumerate_basis(P)
+        H = oracle.sparse_matrix(P, reps, workers=0).toarray()
+        _EXACT[sec.name] = float(np.linalg.eigvalsh(H)[0])
+    return _EXACT[sec.name]
+
+
 def test_serving_loop_admits_by_footprint_and_matches_alone():
     trace = _small_trace()
     budget = sorted(serve.footprint_bytes(r.sector, 120) for r in trace)[-1] * 2   # forces queueing
@@ -85,26 +99,86 @@ def test_serving_loop_admits_by_footprint_and_matches_alone():
     assert len(served.records) == len(trace) == len(alone.records)
     assert served.peak_bytes <= budget
     assert served.max_active >= 2                  # requests overlapped on the device
-    for a, b in zip(served.records, alone.records):
-        assert a.rid == b.rid and a.converged and b.converged
+    for req, a, b in zip(sorted(trace, key=lambda r: r.rid), served.records, alone.records):
+        assert a.rid == b.rid == req.rid and a.status == b.status == "ok"
+        assert a.converged and b.converged
         assert abs(a.e0 - b.e0) <= 1e-10 * max(1.0, abs(b.e0)), (a.name, a.e0, b.e0)
+        # the converged solve reaches the sector's ground energy (oracle, dense)
+        e = _exact_e0(req.sector)
+        assert abs(a.e0 - e) <= 1e-9 * max(1.0, abs(e)), (a.name, a.e0, e)
         assert a.latency > 0
 
 
 def test_serving_rejects_request_larger_than_budget():
+    """A request that can never fit is rejected on arrival and recorded; the
+    loop does not raise."""
     trace = _small_trace(count=2)
-    with pytest.raises(ValueError):
-        serve.serve(trace, hbm_budget=1 << 20, max_iter=50)
+    st = serve.serve(trace, hbm_budget=1 << 20, max_iter=50)
+    assert [r.status for r in st.records] == ["rejected", "rejected"]
+    assert all("budget" in r.error for r in st.records)
+
+
+def test_serving_isolates_failures_and_cancellation():
+    """A mixed trace: one request whose basis loses a key after its build
+    (its solve is stopped with LS_EINTERNAL), one that can never fit the
+    budget, one withdrawn while it runs.  Only those three end without a
+    result; every other request converges to the oracle's ground energy and
+    to the energy it has alone."""
+    trace = _small_trace(count=10, rate=400.0, seed=13)
+    big = configs.Request(len(trace), trace[-1].arrival, configs.ring_symmetric(32, 0, 1, 1, 0.1, seed=77))
+    trace.append(big)
+    budget = max(serve.footprint_bytes(r.sector, 120) for r in trace[:-1]) * 3
+    assert serve.footprint_bytes(big.sector, 120) > budget
+    bad, gone = trace[2].rid, trace[5].rid
+
+    def corrupt(req, basis, op):
+        if req.rid == bad:
+            basis.test_drop_key(basis.dim // 3)
+
+    st = serve.serve(trace, budget, max_iter=120, tol=1e-10, cancel={gone: trace[5].arrival + 0.02},
+                     on_built=corrupt)
+    by = {r.rid: r for r in st.records}
+    assert len(by) == len(trace)
+    assert by[bad].status == "failed" and "LS_EINTERNAL" in by[bad].error
+    assert by[big.rid].status == "rejected"
+    assert by[gone].status in ("cancelled", "ok")       # a fast solve may finish first
+    alone = {r.rid: r for r in serve.serve_one_at_a_time(trace[:-1], max_iter=120, tol=1e-10).records}
+    done = [r for r in st.records if r.status == "ok"]
+    assert len(done) >= len(trace) - 3
+    for r in done:
+        req = trace[r.rid]
+        assert r.converged and r.e0 == alone[r.rid].e0
+        e = _exact_e0(req.sector)
+        assert abs(r.e0 - e) <= 1e-9 * max(1.0, abs(e))
+    assert st.summary()["status"]["failed"] == 1
 
 
 def test_serve_with_stored_elements_matches_alone():
     """Stored products are bit-identical to generated ones, so a trace served
-    with element storage returns the energies of the plain solves exactly."""
+    with element storage returns the energies of the plain solves exactly,
+    and so does the one-at-a-time baseline that stores as well."""
     trace = configs.serving_trace(count=12, rate=50.0, seed=9)
     trace = [r for r in trace if serve.sector_dimension(r.sector) < 2_000_000][:4]
     assert len(trace) == 4
     a = serve.serve(trace, 64 << 30, max_iter=80, tol=1e-9, store_elements=True)
     b = serve.serve_one_at_a_time(trace, max_iter=80, tol=1e-9)
-    assert a.stored_bytes > 0
-    for x, y in zip(a.records, b.records):
-        assert x.e0 == y.e0 and x.iters == y.iters
+    c = serve.serve_one_at_a_time(trace, max_iter=80, tol=1e-9, store_elements=True, hbm_budget=64 << 30)
+    assert a.stored_bytes > 0 and c.stored_bytes > 0
+    for x, y, z in zip(a.records, b.records, c.records):
+        assert x.e0 == y.e0 == z.e0 and x.iters == y.iters == z.iters
+
+
+def test_stepper_mixes_stored_and_generated_products():
+    """In one step, a solve with stored elements takes its stored product and
+    the others the fused launch: the numbers are those of each solve alone."""
+    secs = [configs.ring_symmetric(20, 0, 1, 1, 0.3, seed=7), configs.ring_symmetric(18, 3, 0, 0, 0.2, seed=8),
+            configs.square_j1j2(4, 4, 0.4, seed=9)]
+    ops = [ls.ls_operator_create(ls.ls_basis_build(s), s.terms) for s in secs]
+    alone = [op.lanczos(40, seed=s.seed) for op, s in zip(ops, secs)]
+    ops[0].store()
+    ops[2].store()
+    solvers = [ls.Solver(op, 40, seed=s.seed) for op, s in zip(ops, secs)]
+    while not all(s.result()["done"] for s in solvers):
+        ls.Solver.step_all(solvers)
+    for a, s in zip(alone, solvers):
+        assert s.result()["e0"] == a["e0"] and s.result()["iters"] == a["iters"]
