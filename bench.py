@@ -257,40 +257,60 @@ def batched_vs_plain(count: int, nrhs: int, reps_timed: int = 3):
                     f"{nrhs}-column ls_matvec per sector (the columns share each orbit search, as in the batch)"}
 
 
-def serving(count: int, rate: float, budget_gb: float, max_iter: int, tol: float):
-    """Poisson stream of ground-state requests (rings N in {24..36}, 4x6 and
-    6x6 J1-J2, fully symmetric sectors), served with continuous batching and
-    one at a time on the same trace."""
-    import numpy as np
+def _serve_compare(trace, budget: int, max_iter: int, tol: float, log):
+    """One trace served with continuous batching and one request at a time,
+    each with generated and with stored elements; energies compared."""
     from paper_2308_16712_amd import serve as sv
-    from workloads import configs
 
-    trace = configs.serving_trace(count=count, rate=rate)
-    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
-    served = sv.serve(trace, int(budget_gb * 2 ** 30), max_iter=max_iter, tol=tol, log=log)
+    served = sv.serve(trace, budget, max_iter=max_iter, tol=tol, log=log)
     alone = sv.serve_one_at_a_time(trace, max_iter=max_iter, tol=tol)
-    stored = sv.serve(trace, int(budget_gb * 2 ** 30), max_iter=max_iter, tol=tol, log=log, store_elements=True)
-    de = max(abs(a.e0 - b.e0) / max(1.0, abs(b.e0)) for a, b in zip(served.records, alone.records))
-    s, b = served.summary(), alone.summary()
-    work = sum(r.dim * r.iters for r in served.records)
-    return {"requests": count, "arrival_rate_per_s": rate, "tol": tol, "max_iter": max_iter,
-            "hbm_budget_gb": budget_gb, "policy": "sjf (small solves fused first, then shortest large; "
-                                                  "builds overlapped with steps)",
-            "dims": sorted({r.dim for r in served.records}),
+    served_st = sv.serve(trace, budget, max_iter=max_iter, tol=tol, log=log, store_elements=True)
+    alone_st = sv.serve_one_at_a_time(trace, max_iter=max_iter, tol=tol, store_elements=True, hbm_budget=budget)
+    s, b, ss, bs = served.summary(), alone.summary(), served_st.summary(), alone_st.summary()
+
+    def de(x, y):
+        return max(abs(a.e0 - c.e0) / max(1.0, abs(c.e0)) for a, c in zip(x.records, y.records)
+                   if a.status == c.status == "ok")
+
+    # one-at-a-time service time per request (build + solve, no queueing):
+    # the rate a one-at-a-time server sustains
+    service = (b["build_s"] + b["step_s"]) / max(1, b["completed"])
+    return {"requests": len(trace), "dims": sorted({r.dim for r in served.records}),
             "served": s, "one_at_a_time": b,
             "speedup_throughput": s["throughput_rps"] / b["throughput_rps"],
             "p50_ratio": b["p50_ms"] / s["p50_ms"], "p99_ratio": b["p99_ms"] / s["p99_ms"],
-            "max_rel_e0_diff_served_vs_alone": de, "row_steps": work,
-            "served_with_stored_elements": dict(
-                stored.summary(),
-                speedup_throughput_vs_one_at_a_time=stored.summary()["throughput_rps"] / b["throughput_rps"],
-                p50_ratio=b["p50_ms"] / stored.summary()["p50_ms"],
-                max_rel_e0_diff_vs_alone=max(abs(a.e0 - c.e0) / max(1.0, abs(c.e0))
-                                             for a, c in zip(stored.records, alone.records)),
-                note="the server also keeps each solve's matrix elements in HBM when the budget allows "
-                     "(ls_operator_store); the one-at-a-time baseline generates them"),
-            "offered_load_note": "arrivals at the stated rate exceed capacity for the large sectors; "
-                                 "latency includes queueing"}
+            "max_rel_e0_diff_served_vs_alone": de(served, alone),
+            "stored": {"served": ss, "one_at_a_time": bs,
+                       "speedup_throughput": ss["throughput_rps"] / bs["throughput_rps"],
+                       "p50_ratio": bs["p50_ms"] / ss["p50_ms"], "p99_ratio": bs["p99_ms"] / ss["p99_ms"],
+                       "max_rel_e0_diff_vs_generated": de(served_st, alone)},
+            "one_at_a_time_service_s_per_request": service,
+            "one_at_a_time_capacity_rps": 1.0 / service if service > 0 else None}
+
+
+def serving(count: int, rate: float, budget_gb: float, max_iter: int, tol: float, full_count: int):
+    """Poisson streams of ground-state requests on fully symmetric sectors,
+    served with continuous batching and one request at a time on the same
+    trace: (1) `count` requests over the smaller sectors of the serving mix
+    (rings N = 24, 26, 28 and the 4x6 J1-J2 torus); (2) `full_count`
+    requests over the whole mix (rings N = 24..36, 4x6 and 6x6)."""
+    from workloads import configs
+
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    budget = int(budget_gb * 2 ** 30)
+    out = {"arrival_rate_per_s": rate, "tol": tol, "max_iter": max_iter, "hbm_budget_gb": budget_gb,
+           "policy": "sjf (small solves fused first, then the shortest large one; builds overlapped with steps)"}
+    small = configs.serving_trace(count=count, rate=rate, ring_sizes=(24, 26, 28), squares=((4, 6),))
+    out["small_mix"] = _serve_compare(small, budget, max_iter, tol, log)
+    full = configs.serving_trace(count=full_count, rate=rate)
+    out["full_mix"] = _serve_compare(full, budget, max_iter, tol, log)
+    for key in ("small_mix", "full_mix"):
+        cap = out[key]["one_at_a_time_capacity_rps"]
+        out[key]["offered_load"] = rate / cap if cap else None
+        out[key]["offered_load_note"] = (f"arrivals at {rate:g}/s against a one-at-a-time capacity of "
+                                         f"{cap:.2f}/s (load {rate / cap:.2f}); latency includes queueing"
+                                         if cap else "")
+    return out
 
 
 def push_product(op, x, pull_ms: float, elements: int, steps: int):
@@ -582,7 +602,8 @@ def main():
     ap.add_argument("--batched-count", type=int, default=64)
     ap.add_argument("--batched-nrhs", type=int, default=4)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving comparison")
-    ap.add_argument("--serve-count", type=int, default=12)
+    ap.add_argument("--serve-count", type=int, default=120, help="requests of the small-sector trace")
+    ap.add_argument("--serve-full-count", type=int, default=12, help="requests of the whole-mix trace")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--serve-max-iter", type=int, default=150)
@@ -592,7 +613,7 @@ def main():
     ap.add_argument("--no-lanczos", action="store_true", help="skip the 100-step Lanczos leg (ring N=32)")
     ap.add_argument("--no-small", action="store_true", help="skip the N=16 and N=32 ring products")
     ap.add_argument("--chains", default="40,42", help="paper-workload chain sizes to time (empty: none)")
-    ap.add_argument("--enum-counts", default="40,42", help="chain sizes counted without storage")
+    ap.add_argument("--enum-counts", default="40,42,44,46,48", help="chain sizes counted without storage")
     ap.add_argument("--enum-build", type=int, default=40, help="chain size built and stored (0: none)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run only a plain device copy of this many MiB (counter calibration)")
@@ -712,7 +733,7 @@ def main():
     if not args.no_serving:
         print("[bench] serving", file=sys.stderr, flush=True)
         out["serving"] = serving(args.serve_count, args.serve_rate, args.serve_budget_gb, args.serve_max_iter,
-                                 1e-10)
+                                 1e-10, args.serve_full_count)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)

@@ -32,12 +32,16 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
 
 def _scratch_kernels(remarks: str):
     """Kernels whose resource-usage remark reports scratch (register spills
-    to memory), from hipcc's -Rpass-analysis=kernel-resource-usage output."""
+    to memory) or a stack whose size is only known at run time (which the
+    runtime would have to guess), from hipcc's
+    -Rpass-analysis=kernel-resource-usage output."""
     out = []
     for block in re.split(r"remark: Function Name: ", remarks)[1:]:
         m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", block)
         if m and int(m.group(1)) > 0:
             out.append((block.split()[0], int(m.group(1))))
+        if re.search(r"Dynamic Stack: True", block):
+            out.append((block.split()[0], "dynamic stack"))
     return out
 
 
