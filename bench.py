@@ -302,13 +302,18 @@ def serving(count: int, rate: float, budget_gb: float, max_iter: int, tol: float
            "policy": "sjf (small solves fused first, then the shortest large one; builds overlapped with steps)"}
     small = configs.serving_trace(count=count, rate=rate, ring_sizes=(24, 26, 28), squares=((4, 6),))
     out["small_mix"] = _serve_compare(small, budget, max_iter, tol, log)
+    # the same mix offered ten times faster: above one-at-a-time capacity, so
+    # requests overlap and steps carry many solves
+    fast = configs.serving_trace(count=count, rate=10 * rate, ring_sizes=(24, 26, 28), squares=((4, 6),))
+    out["small_mix_saturated"] = _serve_compare(fast, budget, max_iter, tol, log)
+    out["small_mix_saturated"]["arrival_rate_per_s"] = 10 * rate
     full = configs.serving_trace(count=full_count, rate=rate)
     out["full_mix"] = _serve_compare(full, budget, max_iter, tol, log)
-    for key in ("small_mix", "full_mix"):
+    for key, r in (("small_mix", rate), ("small_mix_saturated", 10 * rate), ("full_mix", rate)):
         cap = out[key]["one_at_a_time_capacity_rps"]
-        out[key]["offered_load"] = rate / cap if cap else None
-        out[key]["offered_load_note"] = (f"arrivals at {rate:g}/s against a one-at-a-time capacity of "
-                                         f"{cap:.2f}/s (load {rate / cap:.2f}); latency includes queueing"
+        out[key]["offered_load"] = r / cap if cap else None
+        out[key]["offered_load_note"] = (f"arrivals at {r:g}/s against a one-at-a-time capacity of "
+                                         f"{cap:.2f}/s (load {r / cap:.2f}); latency includes queueing"
                                          if cap else "")
     return out
 

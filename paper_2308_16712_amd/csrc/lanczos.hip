@@ -679,6 +679,403 @@ void solver_destroy(ls_solver *s) {
     free_solver(s);
 }
 
+// ---- batched step: the work after the products of several solves, one
+// launch per kernel for all of them ------------------------------------------
+//
+// A step of a single solve runs about thirty small kernels (dot products,
+// the three-term update, two Gram-Schmidt passes in tiles of eight vectors,
+// reductions, the normalisation); over many small solves those launches, not
+// the GPU, set the step time.  Here each kernel runs once for all solves of
+// the step: its flat grid is mapped onto (solve, block) pairs through prefix
+// tables.  Every block computes exactly the partial sums the single kernels
+// compute for the non-empty blocks of the fixed 2048-block dot grid (the
+// same element sets, accumulation order and reduction tree), and the
+// reductions read the missing partials as the zeros that the empty blocks
+// of the single kernels write, so a solve gets the same bits alone or here.
+
+namespace {
+
+struct StepJob {
+    const void *V;        // [m][n] Krylov vectors
+    void *w;              // [n]
+    uint64_t n;
+    uint32_t k, m;        // step, Krylov dimension cap
+    uint32_t nb;          // non-empty blocks of the dot grid: min(2048, ceil(n / 256))
+    uint32_t mode;        // reorthogonalisation: none, full, selective
+    uint32_t last;        // k + 1 == m: no next vector is formed
+    uint32_t pad_;
+    double2 *partial;     // [kDotBlocks][m]
+    double2 *hs;          // [m]
+    double2 *npart;       // [2][kDotBlocks] block parts of ||w||^2 before / after a pass
+    double2 *nrm;         // [4]
+    int *gate;            // second Gram-Schmidt pass needed
+    double2 *dots;        // [2]: <v_k, w>, ||w||^2
+    double *scal;         // [2]: alpha_k, beta_{k+1}
+    double *bprev;        // beta_k
+    uint32_t *err;        // the operator's lookup-miss flag
+    double *row;          // [4] device staging row: alpha, beta, flag (read back in one copy)
+};
+
+// One reduction of 2048 virtual block partials into one output (the loop
+// and tree of k_reduce_partials); partials at or beyond nb are zeros.
+struct RedTask {
+    const double2 *src;   // partial b of output j at src[b * stride + j]
+    uint32_t stride, nb, nout, pad_;
+    double2 *dst;         // dst[j], j < nout
+};
+
+// Index of the segment holding flat block index x: off[0] = 0 <= ... <= off[count].
+__device__ __forceinline__ uint32_t segment_of(const uint32_t *off, uint32_t count, uint32_t x) {
+    uint32_t lo = 0, hi = count;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(kBlock) kb_reduce(const RedTask *tasks, const uint32_t *off, uint32_t count) {
+    __shared__ double sh[kBlock];
+    const uint32_t t = segment_of(off, count, blockIdx.x);
+    const RedTask T = tasks[t];
+    const uint32_t j = blockIdx.x - off[t];
+    double re = 0.0, im = 0.0;
+    for (uint32_t b = threadIdx.x; b < static_cast<uint32_t>(kDotBlocks); b += kBlock) {
+        const double2 v = b < T.nb ? T.src[static_cast<size_t>(b) * T.stride + j] : make_double2(0.0, 0.0);
+        re += v.x;
+        im += v.y;
+    }
+    re = block_reduce(re, sh);
+    im = block_reduce(im, sh);
+    if (threadIdx.x == 0) T.dst[j] = make_double2(re, im);
+}
+
+// partial[b] = the block's part of <a, b> (k_dot_partial) with a = v_k, b = w
+// (which = 0) or a = b = w (which = 1, written to partial too)
+template <bool CPLX>
+__global__ void __launch_bounds__(kBlock) kb_dot(const StepJob *jobs, const uint32_t *off, uint32_t count, int which) {
+    using T = typename V<CPLX>::T;
+    __shared__ double sh[kBlock];
+    const uint32_t s = segment_of(off, count, blockIdx.x);
+    const StepJob &J = jobs[s];
+    const uint32_t b = blockIdx.x - off[s];
+    const T *pa = which == 0 ? static_cast<const T *>(J.V) + static_cast<uint64_t>(J.k) * J.n
+                             : static_cast<const T *>(J.w);
+    const T *pb = static_cast<const T *>(J.w);
+    double re = 0.0, im = 0.0;
+    const uint64_t stride = static_cast<uint64_t>(kDotBlocks) * kBlock;
+    for (uint64_t i = static_cast<uint64_t>(b) * kBlock + threadIdx.x; i < J.n; i += stride) {
+        if constexpr (CPLX) {
+            const double2 x = pa[i], y = pb[i];
+            re = fma(x.x, y.x, fma(x.y, y.y, re));
+            im = fma(x.x, y.y, fma(-x.y, y.x, im));
+        } else {
+            re = fma(pa[i], pb[i], re);
+        }
+    }
+    re = block_reduce(re, sh);
+    if constexpr (CPLX) im = block_reduce(im, sh);
+    if (threadIdx.x == 0) J.partial[b] = make_double2(re, im);
+}
+
+// w -= alpha v_k + beta_k v_{k-1}, elementwise (k_three_term_dev)
+template <bool CPLX>
+__global__ void __launch_bounds__(kBlock) kb_three_term(const StepJob *jobs, const uint32_t *off, uint32_t count) {
+    using T = typename V<CPLX>::T;
+    const uint32_t s = segment_of(off, count, blockIdx.x);
+    const StepJob &J = jobs[s];
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x - off[s]) * kBlock + threadIdx.x;
+    if (i >= J.n) return;
+    const T *Vb = static_cast<const T *>(J.V);
+    const T *pv = Vb + static_cast<uint64_t>(J.k) * J.n;
+    const T *pvp = J.k > 0 ? Vb + static_cast<uint64_t>(J.k - 1) * J.n : nullptr;
+    const double alpha = J.dots[0].x;
+    const double beta = pvp ? *J.bprev : 0.0;
+    T *pw = static_cast<T *>(J.w);
+    if constexpr (CPLX) {
+        double2 w = pw[i];
+        const double2 v = pv[i];
+        w.x -= alpha * v.x;
+        w.y -= alpha * v.y;
+        if (pvp) {
+            const double2 u = pvp[i];
+            w.x -= beta * u.x;
+            w.y -= beta * u.y;
+        }
+        pw[i] = w;
+    } else {
+        double w = pw[i];
+        w -= alpha * pv[i];
+        if (pvp) w -= beta * pvp[i];
+        pw[i] = w;
+    }
+}
+
+// Gram-Schmidt pass `pass` (k_multidot_partial for every tile of eight
+// vectors of V_0 .. V_k, in order); the selective mode's second pass runs
+// only when the gate is set, and its first pass also records ||w||^2.
+template <bool CPLX>
+__global__ void __launch_bounds__(kBlock) kb_multidot(const StepJob *jobs, const uint32_t *off, uint32_t count,
+                                                      int pass) {
+    __shared__ double sh[kBlock];
+    const uint32_t s = segment_of(off, count, blockIdx.x);
+    const StepJob &J = jobs[s];
+    const bool sel = J.mode == kReorthSelective;
+    if (sel && pass == 1 && *J.gate == 0) return;
+    const uint32_t b = blockIdx.x - off[s];
+    const int nv = static_cast<int>(J.k) + 1;
+    const uint64_t n = J.n;
+    const uint64_t gstride = static_cast<uint64_t>(kDotBlocks) * kBlock;
+    for (int j0 = 0; j0 < nv; j0 += kTile) {
+        const int tile = min(kTile, nv - j0);
+        const bool wn = sel && pass == 0 && j0 == 0;
+        double re[kTile], im[kTile];
+        double nre = 0.0;
+#pragma unroll
+        for (int q = 0; q < kTile; ++q) re[q] = im[q] = 0.0;
+        for (uint64_t i = static_cast<uint64_t>(b) * kBlock + threadIdx.x; i < n; i += gstride) {
+            if constexpr (CPLX) {
+                const double2 w = static_cast<const double2 *>(J.w)[i];
+                if (wn) nre = fma(w.x, w.x, fma(w.y, w.y, nre));
+                const double2 *Vb = static_cast<const double2 *>(J.V);
+#pragma unroll
+                for (int q = 0; q < kTile; ++q) {
+                    if (q < tile) {
+                        const double2 v = Vb[static_cast<uint64_t>(j0 + q) * n + i];
+                        re[q] = fma(v.x, w.x, fma(v.y, w.y, re[q]));
+                        im[q] = fma(v.x, w.y, fma(-v.y, w.x, im[q]));
+                    }
+                }
+            } else {
+                const double w = static_cast<const double *>(J.w)[i];
+                if (wn) nre = fma(w, w, nre);
+                const double *Vb = static_cast<const double *>(J.V);
+#pragma unroll
+                for (int q = 0; q < kTile; ++q)
+                    if (q < tile) re[q] = fma(Vb[static_cast<uint64_t>(j0 + q) * n + i], w, re[q]);
+            }
+        }
+        for (int q = 0; q < tile; ++q) {
+            const double r = block_reduce(re[q], sh);
+            double m = 0.0;
+            if constexpr (CPLX) m = block_reduce(im[q], sh);
+            if (threadIdx.x == 0) J.partial[static_cast<size_t>(b) * J.m + j0 + q] = make_double2(r, m);
+        }
+        if (wn) {
+            const double r = block_reduce(nre, sh);
+            if (threadIdx.x == 0) J.npart[b] = make_double2(r, 0.0);
+        }
+    }
+}
+
+// w -= sum_j V_j h_j with the block part of the new ||w||^2 (k_gemv_sub)
+template <bool CPLX>
+__global__ void __launch_bounds__(kBlock) kb_gemv_sub(const StepJob *jobs, const uint32_t *off, uint32_t count,
+                                                      int pass) {
+    __shared__ double sh[kBlock];
+    const uint32_t s = segment_of(off, count, blockIdx.x);
+    const StepJob &J = jobs[s];
+    const bool sel = J.mode == kReorthSelective;
+    if (sel && pass == 1 && *J.gate == 0) return;
+    const uint32_t b = blockIdx.x - off[s];
+    const int nv = static_cast<int>(J.k) + 1;
+    const uint64_t n = J.n;
+    const double2 *h = J.hs;
+    double nre = 0.0;
+    const uint64_t gstride = static_cast<uint64_t>(kDotBlocks) * kBlock;
+    for (uint64_t i = static_cast<uint64_t>(b) * kBlock + threadIdx.x; i < n; i += gstride) {
+        if constexpr (CPLX) {
+            const double2 *Vb = static_cast<const double2 *>(J.V);
+            double2 w = static_cast<double2 *>(J.w)[i];
+            double sre = 0.0, sim = 0.0;
+            for (int j = 0; j < nv; ++j) {
+                const double2 v = Vb[static_cast<uint64_t>(j) * n + i];
+                const double2 c = h[j];
+                sre = fma(v.x, c.x, fma(-v.y, c.y, sre));
+                sim = fma(v.x, c.y, fma(v.y, c.x, sim));
+            }
+            w.x -= sre;
+            w.y -= sim;
+            static_cast<double2 *>(J.w)[i] = w;
+            nre = fma(w.x, w.x, fma(w.y, w.y, nre));
+        } else {
+            const double *Vb = static_cast<const double *>(J.V);
+            double acc = 0.0;
+            for (int j = 0; j < nv; ++j) acc = fma(Vb[static_cast<uint64_t>(j) * n + i], h[j].x, acc);
+            const double w = static_cast<double *>(J.w)[i] - acc;
+            static_cast<double *>(J.w)[i] = w;
+            nre = fma(w, w, nre);
+        }
+    }
+    if (sel || pass == 1) {
+        const double r = block_reduce(nre, sh);
+        if (threadIdx.x == 0) J.npart[kDotBlocks + b] = make_double2(r, 0.0);
+    }
+}
+
+// per solve (one thread each): the selective test after the first pass
+// (k_reorth_decide), or the norm of the pass that ran (k_reorth_pick)
+__global__ void kb_decide(const StepJob *jobs, uint32_t count, int stage) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= count) return;
+    const StepJob &J = jobs[s];
+    if (J.mode != kReorthSelective) return;
+    if (stage == 0) {
+        *J.gate = J.nrm[1].x < 0.5 * J.nrm[0].x ? 1 : 0;
+        J.dots[1] = J.nrm[1];
+    } else if (*J.gate) {
+        J.dots[1] = J.nrm[2];
+    }
+}
+
+// per solve: alpha, beta (k_alpha_beta), beta_k for the next step, and the
+// staging row read back by the host (alpha, beta, lookup-miss flag, which
+// is cleared)
+__global__ void kb_alpha_beta(const StepJob *jobs, uint32_t count) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= count) return;
+    const StepJob &J = jobs[s];
+    J.scal[0] = J.dots[0].x;
+    J.scal[1] = __dsqrt_rn(J.dots[1].x);
+    J.row[0] = J.scal[0];
+    J.row[1] = J.scal[1];
+    J.row[2] = static_cast<double>(*J.err);
+    *J.err = 0u;
+}
+
+// V_{k+1} = w / beta_{k+1} elementwise over doubles (k_div_dev), and beta_k
+// for the next step
+template <bool CPLX>
+__global__ void __launch_bounds__(kBlock) kb_div(const StepJob *jobs, const uint32_t *off, uint32_t count) {
+    const uint32_t s = segment_of(off, count, blockIdx.x);
+    const StepJob &J = jobs[s];
+    if (J.last) return;
+    const uint64_t nd = J.n * (CPLX ? 2 : 1);
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x - off[s]) * kBlock + threadIdx.x;
+    if (i == 0) *J.bprev = J.scal[1];
+    if (i >= nd) return;
+    double *dst = static_cast<double *>(const_cast<void *>(J.V)) + (static_cast<uint64_t>(J.k) + 1) * nd;
+    dst[i] = static_cast<const double *>(J.w)[i] / J.scal[1];
+}
+
+// Device tables of a batched step, grown by doubling and reused.
+struct StepTables {
+    StepJob *jobs = nullptr;
+    RedTask *tasks = nullptr;
+    uint32_t *offs = nullptr;     // prefix tables, packed
+    double *staging = nullptr;    // [count][4] device side of the read-back
+    double *host = nullptr;       // pinned [count][4]
+    size_t cap_jobs = 0, cap_tasks = 0, cap_offs = 0, cap_staging = 0, cap_host = 0;
+};
+StepTables g_tables;
+
+template <typename X>
+void grow(X **p, size_t *cap, size_t need) {
+    if (need <= *cap) return;
+    const size_t c = std::max<size_t>(need, *cap * 2 + 16);
+    if (*p) LS_HIP_CHECK(hipFree(*p));
+    *p = nullptr;
+    LS_HIP_CHECK(hipMalloc(p, c * sizeof(X)));
+    *cap = c;
+}
+
+}  // namespace
+
+// The after-product work of step k for every solve in `act`, batched: all
+// of one element type, and either all reorthogonalising (full or selective,
+// mixed) or none.  Each solve's (alpha, beta, flag) row lands in host_rows
+// ([act][4], pinned) on `st`.
+template <bool CPLX>
+void batched_after_products(const std::vector<ls_solver *> &act, hipStream_t st, double *host_rows) {
+    const uint32_t S = static_cast<uint32_t>(act.size());
+    StepTables &G = g_tables;   // sized by the caller for the whole step
+    std::vector<StepJob> jobs(S);
+    std::vector<uint32_t> off_dot(S + 1, 0), off_el(S + 1, 0), off_div(S + 1, 0), o_one(S + 1), o_h(S + 1, 0);
+    bool none = false;
+    for (uint32_t i = 0; i < S; ++i) {
+        ls_solver *sv = act[i];
+        StepJob &J = jobs[i];
+        J.V = sv->V;
+        J.w = sv->w;
+        J.n = sv->n;
+        J.k = sv->k;
+        J.m = sv->m;
+        J.nb = static_cast<uint32_t>(std::min<uint64_t>(kDotBlocks, (sv->n + kBlock - 1) / kBlock));
+        J.mode = static_cast<uint32_t>(sv->reorth);
+        J.last = sv->k + 1 >= sv->m ? 1u : 0u;
+        const ReorthBufs rb = reorth_bufs(sv->partial, sv->hs, sv->aux, static_cast<int>(sv->m));
+        J.partial = rb.partial;
+        J.hs = rb.hs;
+        J.npart = rb.npart;
+        J.nrm = rb.nrm;
+        J.gate = rb.gate;
+        J.dots = sv->dots;
+        J.scal = sv->scal;
+        J.bprev = sv->bprev;
+        J.err = sv->op->d_err;
+        J.row = G.staging + 4 * static_cast<size_t>(i);
+        none = J.mode == kReorthNone;
+        off_dot[i + 1] = off_dot[i] + J.nb;
+        off_el[i + 1] = off_el[i] + static_cast<uint32_t>((sv->n + kBlock - 1) / kBlock);
+        const uint64_t nd = sv->n * (CPLX ? 2 : 1);
+        off_div[i + 1] = off_div[i] + static_cast<uint32_t>((nd + kBlock - 1) / kBlock);
+        o_one[i] = i;
+        o_h[i + 1] = o_h[i] + J.k + 1;
+    }
+    o_one[S] = S;
+    // reduction tasks: alpha, h, ||w||^2 before / after the first pass, the
+    // final ||w||^2 (after the second pass, or without reorthogonalisation)
+    std::vector<RedTask> tasks;
+    tasks.reserve(5 * static_cast<size_t>(S));
+    for (const StepJob &J : jobs) tasks.push_back(RedTask{J.partial, 1, J.nb, 1, 0, J.dots});
+    for (const StepJob &J : jobs) tasks.push_back(RedTask{J.partial, J.m, J.nb, J.k + 1, 0, J.hs});
+    for (const StepJob &J : jobs) tasks.push_back(RedTask{J.npart, 1, J.nb, 1, 0, J.nrm});
+    for (const StepJob &J : jobs)
+        tasks.push_back(RedTask{J.npart + kDotBlocks, 1, J.nb, 1, 0, J.mode == kReorthSelective ? J.nrm + 1 : J.nrm + 3});
+    for (const StepJob &J : jobs)
+        tasks.push_back(none ? RedTask{J.partial, 1, J.nb, 1, 0, J.dots + 1}
+                             : RedTask{J.npart + kDotBlocks, 1, J.nb, 1, 0,
+                                       J.mode == kReorthSelective ? J.nrm + 2 : J.dots + 1});
+    std::vector<uint32_t> offs;
+    for (auto *L : {&off_dot, &off_el, &off_div, &o_one, &o_h}) offs.insert(offs.end(), L->begin(), L->end());
+    LS_HIP_CHECK(hipMemcpyAsync(G.jobs, jobs.data(), S * sizeof(StepJob), hipMemcpyHostToDevice, st));
+    LS_HIP_CHECK(hipMemcpyAsync(G.tasks, tasks.data(), tasks.size() * sizeof(RedTask), hipMemcpyHostToDevice, st));
+    LS_HIP_CHECK(hipMemcpyAsync(G.offs, offs.data(), offs.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    const uint32_t *d_dot = G.offs, *d_el = d_dot + (S + 1), *d_div = d_el + (S + 1), *d_one = d_div + (S + 1),
+                   *d_h = d_one + (S + 1);
+    const RedTask *T_alpha = G.tasks, *T_h = T_alpha + S, *T_before = T_h + S, *T_after = T_before + S,
+                  *T_final = T_after + S;
+    const dim3 blk(kBlock);
+    const uint32_t per = 64;   // solves per block of the per-solve kernels
+    const dim3 gs((S + per - 1) / per);
+    // alpha = <v_k, w>
+    hipLaunchKernelGGL(kb_dot<CPLX>, dim3(off_dot[S]), blk, 0, st, G.jobs, d_dot, S, 0);
+    hipLaunchKernelGGL(kb_reduce, dim3(S), blk, 0, st, T_alpha, d_one, S);
+    // w -= alpha v_k + beta_k v_{k-1}
+    hipLaunchKernelGGL(kb_three_term<CPLX>, dim3(off_el[S]), blk, 0, st, G.jobs, d_el, S);
+    if (none) {
+        // ||w||^2 directly
+        hipLaunchKernelGGL(kb_dot<CPLX>, dim3(off_dot[S]), blk, 0, st, G.jobs, d_dot, S, 1);
+    } else {
+        for (int pass = 0; pass < 2; ++pass) {
+            hipLaunchKernelGGL(kb_multidot<CPLX>, dim3(off_dot[S]), blk, 0, st, G.jobs, d_dot, S, pass);
+            hipLaunchKernelGGL(kb_reduce, dim3(o_h[S]), blk, 0, st, T_h, d_h, S);
+            hipLaunchKernelGGL(kb_gemv_sub<CPLX>, dim3(off_dot[S]), blk, 0, st, G.jobs, d_dot, S, pass);
+            if (pass == 0) {
+                hipLaunchKernelGGL(kb_reduce, dim3(S), blk, 0, st, T_before, d_one, S);
+                hipLaunchKernelGGL(kb_reduce, dim3(S), blk, 0, st, T_after, d_one, S);
+                hipLaunchKernelGGL(kb_decide, gs, dim3(per), 0, st, G.jobs, S, 0);
+            }
+        }
+    }
+    hipLaunchKernelGGL(kb_reduce, dim3(S), blk, 0, st, T_final, d_one, S);
+    if (!none) hipLaunchKernelGGL(kb_decide, gs, dim3(per), 0, st, G.jobs, S, 1);
+    hipLaunchKernelGGL(kb_alpha_beta, gs, dim3(per), 0, st, G.jobs, S);
+    hipLaunchKernelGGL(kb_div<CPLX>, dim3(off_div[S]), blk, 0, st, G.jobs, d_div, S);
+    LS_HIP_CHECK(hipGetLastError());
+    LS_HIP_CHECK(hipMemcpyAsync(host_rows, G.staging, S * 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+}
+
 void solver_step(ls_solver *const *ss, uint32_t n, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_step_mu);
     if (!g_fused) g_fused = fused_create();
@@ -715,11 +1112,53 @@ void solver_step(ls_solver *const *ss, uint32_t n, hipStream_t st) {
     if (fops.size() == 1) launch_matvec(fops[0], 1, fxs[0], fys[0], st);
     else if (fops.size() > 1)
         fused_matvec(g_fused, static_cast<uint32_t>(fops.size()), fops.data(), fxs.data(), fys.data(), st);
-    for (ls_solver *s : act) {
-        if (s->cplx) enqueue_after_product<true>(s, st);
-        else enqueue_after_product<false>(s, st);
+    // the work after the products: per solve for a single solve, else
+    // batched by element type and reorthogonalisation (identical numbers)
+    const bool batched = act.size() >= 2;
+    std::vector<size_t> row_of(act.size(), 0);
+    if (!batched) {
+        for (ls_solver *s : act) {
+            if (s->cplx) enqueue_after_product<true>(s, st);
+            else enqueue_after_product<false>(s, st);
+        }
+    } else {
+        StepTables &G = g_tables;
+        const size_t A = act.size();
+        grow(&G.jobs, &G.cap_jobs, A);
+        grow(&G.staging, &G.cap_staging, 4 * A);
+        grow(&G.tasks, &G.cap_tasks, 5 * A);
+        grow(&G.offs, &G.cap_offs, 5 * (A + 1));
+        if (G.cap_host < 4 * A) {
+            if (G.host) LS_HIP_CHECK(hipHostFree(G.host));
+            G.host = nullptr;
+            LS_HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&G.host), 4 * A * sizeof(double) * 2));
+            G.cap_host = 8 * A;
+        }
+        std::vector<ls_solver *> groups[4];   // (complex, without reorthogonalisation)
+        std::vector<size_t> where[4];
+        for (size_t i = 0; i < A; ++i) {
+            const int g = (act[i]->cplx ? 2 : 0) + (act[i]->reorth == kReorthNone ? 1 : 0);
+            groups[g].push_back(act[i]);
+            where[g].push_back(i);
+        }
+        size_t r = 0;
+        for (int g = 0; g < 4; ++g) {
+            if (groups[g].empty()) continue;
+            if (g >= 2) batched_after_products<true>(groups[g], st, G.host + 4 * r);
+            else batched_after_products<false>(groups[g], st, G.host + 4 * r);
+            for (size_t q = 0; q < groups[g].size(); ++q) row_of[where[g][q]] = r + q;
+            r += groups[g].size();
+        }
     }
     LS_HIP_CHECK(hipStreamSynchronize(st));
+    if (batched) {
+        for (size_t i = 0; i < act.size(); ++i) {
+            const double *row = g_tables.host + 4 * row_of[i];
+            act[i]->host[0] = row[0];
+            act[i]->host[1] = row[1];
+            *act[i]->hflag = row[2] != 0.0 ? 1u : 0u;
+        }
+    }
     // a solve whose product met a lookup miss stops here (its step is not
     // taken); the others finish theirs
     uint32_t failed = 0;

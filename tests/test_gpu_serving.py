@@ -182,3 +182,24 @@ def test_stepper_mixes_stored_and_generated_products():
         ls.Solver.step_all(solvers)
     for a, s in zip(alone, solvers):
         assert s.result()["e0"] == a["e0"] and s.result()["iters"] == a["iters"]
+
+
+def test_batched_step_all_modes_match_lanczos_alone():
+    """Several solves in one step run their Lanczos work batched (one launch
+    per kernel for all of them): real and complex solves, with full,
+    selective and no reorthogonalisation, each give exactly the numbers of
+    ls_lanczos alone."""
+    secs = [configs.ring_symmetric(20, 0, 1, 1, 0.3, seed=7), configs.ring_symmetric(18, 3, 0, 0, 0.2, seed=8),
+            configs.square_j1j2(4, 4, 0.4, seed=9), configs.ring_symmetric(22, 0, 1, 1, 0.1, seed=10),
+            configs.ring_symmetric(16, 5, 0, 0, 0.4, seed=11)]
+    modes = ["full", "selective", "none", "full", "none"]
+    ops = [ls.ls_operator_create(ls.ls_basis_build(s), s.terms) for s in secs]
+    alone = [op.lanczos(45, seed=s.seed, reorth=m) for op, s, m in zip(ops, secs, modes)]
+    solvers = [ls.Solver(op, 45, seed=s.seed, reorth=m) for op, s, m in zip(ops, secs, modes)]
+    while not all(s.result()["done"] for s in solvers):
+        ls.Solver.step_all(solvers)
+    for a, s, m in zip(alone, solvers, modes):
+        r = s.result()
+        assert r["iters"] == a["iters"], m
+        assert r["e0"] == a["e0"], (m, r["e0"], a["e0"])
+        assert r["resid"] == a["resid"], m
