@@ -32,6 +32,13 @@
  * freed with the matching *_destroy.  Calls on different streams may
  * overlap; a handle may be shared by concurrent calls.
  *
+ * Destruction: handle memory is stream-ordered (hipMallocAsync).  Each
+ * handle records the streams it was used on (a basis and an operator also
+ * those of the calls that used an operator or solver built on them);
+ * *_destroy waits for those streams only, never the whole device, and then
+ * releases the memory.  Those streams must still exist when the handle is
+ * destroyed; destroy a handle before the streams it ran on.
+ *
  * Errors: every call returns ls_status.  No exception crosses this boundary.
  * On LS_EINVAL nothing has been enqueued and out-parameters are untouched.
  * ls_last_error() returns a thread-local message for the last failure.
@@ -165,7 +172,7 @@ ls_status ls_basis_info(const ls_basis *basis, uint64_t *dim, int *is_real,
  * buffers on `stream`.  Either destination may be NULL.                   */
 ls_status ls_basis_copy(const ls_basis *basis, uint64_t *d_reps_out, uint16_t *d_stab_out, void *stream);
 
-/* Frees the handle and its device memory (after synchronizing the device). */
+/* Waits for the streams the basis was used on, then frees it. */
 void ls_basis_destroy(ls_basis *basis);
 
 /* Test hook for the lookup-miss error path (host-forced fault injection):
@@ -204,6 +211,7 @@ ls_status ls_index_lookup(const ls_basis *basis, uint64_t n, const uint64_t *d_k
  * must outlive it.                                                         */
 ls_status ls_operator_create(const ls_basis *basis, uint32_t n_terms, const ls_term *terms,
                              ls_operator **out);
+/* Waits for the streams the operator was used on, then frees it. */
 void ls_operator_destroy(ls_operator *op);
 
 /* Whether the operator acts on complex vectors (complex characters or
@@ -326,6 +334,7 @@ ls_status ls_batch_info(const ls_batch *batch, uint32_t *n_launches, uint32_t *n
  * first ls_batch_matvec.                                                   */
 ls_status ls_batch_set_graph(ls_batch *batch, int enabled);
 
+/* Waits for the streams of the batch's products, then frees it. */
 void ls_batch_destroy(ls_batch *batch);
 
 /* Lanczos ground-state solve on top of ls_matvec.  FP64 throughout, Krylov
@@ -399,6 +408,7 @@ ls_status ls_solver_step(ls_solver *const *solvers, uint32_t n, void *stream);
 ls_status ls_solver_result(const ls_solver *solver, double *e0, uint32_t *iters, double *resid_bound, int *done,
                            int *converged);
 
+/* Waits for the streams the solver stepped on, then frees it. */
 void ls_solver_destroy(ls_solver *solver);
 
 /* Thread-local description of the last non-OK status. */

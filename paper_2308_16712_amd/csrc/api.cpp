@@ -14,6 +14,35 @@ thread_local std::string g_last_error;
 void set_error(const std::string &msg) { g_last_error = msg; }
 const char *last_error() { return g_last_error.c_str(); }
 
+void *dev_alloc(size_t bytes, hipStream_t stream) {
+    void *p = nullptr;
+    if (hipMallocAsync(&p, bytes > 0 ? bytes : 1, stream) != hipSuccess || p == nullptr)
+        throw Error{LS_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed"};
+    return p;
+}
+
+void dev_free(void *p, hipStream_t stream) {
+    if (p) (void)hipFreeAsync(p, stream);
+}
+
+void StreamSet::add(hipStream_t st) {
+    std::lock_guard<std::mutex> lk(mu);
+    for (hipStream_t x : streams)
+        if (x == st) return;
+    streams.push_back(st);
+}
+
+void StreamSet::drain() {
+    std::lock_guard<std::mutex> lk(mu);
+    for (hipStream_t x : streams) (void)hipStreamSynchronize(x);
+    streams.clear();
+}
+
+void touch(const ls_operator *op, hipStream_t st) {
+    op->used.add(st);
+    op->basis->used.add(st);
+}
+
 }  // namespace ls
 
 namespace {
@@ -36,16 +65,33 @@ ls_status guarded(F &&f) {
 
 void free_basis(ls_basis *b) {
     if (!b) return;
-    hipFree(b->d_reps);
-    hipFree(b->d_stab);
-    hipFree(b->d_buckets);
-    hipFree(b->d_table);
-    hipFree(b->d_binom);
-    hipFree(b->d_cosets);
-    hipFree(b->d_chi);
-    hipFree(b->d_chi_one);
-    hipFree(b->d_pair_lut);
+    b->used.drain();
+    ls::dev_free(b->d_reps);
+    ls::dev_free(b->d_stab);
+    ls::dev_free(b->d_buckets);
+    ls::dev_free(b->d_table);
+    ls::dev_free(b->d_binom);
+    ls::dev_free(b->d_cosets);
+    ls::dev_free(b->d_chi);
+    ls::dev_free(b->d_chi_one);
+    ls::dev_free(b->d_pair_lut);
     delete b;
+}
+
+void free_operator(ls_operator *op) {
+    if (!op) return;
+    op->used.drain();
+    ls::dev_free(op->d_terms);
+    ls::dev_free(op->d_cflip);
+    ls::dev_free(op->d_err);
+    ls::dev_free(op->d_st_off);
+    ls::dev_free(op->d_st_width);
+    ls::dev_free(op->d_st_cols);
+    ls::dev_free(op->d_st_vals);
+    ls::dev_free(op->d_st_codes);
+    ls::dev_free(op->d_st_vtab);
+    ls::dev_free(op->d_st_diag);
+    delete op;
 }
 
 hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
@@ -69,6 +115,7 @@ ls_status ls_basis_build(const ls_sector_desc *desc, void *stream, ls_basis **ou
         b->perm_copy.assign(desc->perm, desc->perm + static_cast<size_t>(desc->n_elements) * desc->n_sites);
         b->flip_copy.assign(desc->flip, desc->flip + desc->n_elements);
         LS_HIP_CHECK(hipGetDevice(&b->device));
+        b->used.add(as_stream(stream));
         ls::build_basis(b, as_stream(stream));
         *out = b;
         return LS_OK;
@@ -88,7 +135,8 @@ ls_status ls_sector_count(const ls_sector_desc *desc, uint64_t rank_begin, uint6
         b->plan = std::move(plan);
         b->weight = desc->hamming_weight;
         LS_HIP_CHECK(hipGetDevice(&b->device));
-        ls::upload_plan(b);
+        b->used.add(as_stream(stream));
+        ls::upload_plan(b, as_stream(stream));
         *n_members = ls::count_members(b, rank_begin, rank_end, as_stream(stream));
         if (n_candidates) *n_candidates = ls::candidate_count(b);
         return LS_OK;
@@ -138,6 +186,7 @@ ls_status ls_basis_copy(const ls_basis *b, uint64_t *d_reps_out, uint16_t *d_sta
     return guarded([&] {
         LS_REQUIRE(b != nullptr, "basis must not be NULL");
         if (b->dim == 0) return LS_OK;
+        b->used.add(as_stream(stream));
         if (d_reps_out)
             LS_HIP_CHECK(hipMemcpyAsync(d_reps_out, b->d_reps, b->dim * sizeof(uint64_t), hipMemcpyDeviceToDevice,
                                         as_stream(stream)));
@@ -148,11 +197,7 @@ ls_status ls_basis_copy(const ls_basis *b, uint64_t *d_reps_out, uint16_t *d_sta
     });
 }
 
-void ls_basis_destroy(ls_basis *b) {
-    if (!b) return;
-    hipDeviceSynchronize();
-    free_basis(b);
-}
+void ls_basis_destroy(ls_basis *b) { free_basis(b); }
 
 ls_status ls_state_info(const ls_basis *b, uint64_t n, const uint64_t *d_states, uint64_t *d_reps, double *d_chi,
                         double *d_norm, void *stream) {
@@ -160,6 +205,7 @@ ls_status ls_state_info(const ls_basis *b, uint64_t n, const uint64_t *d_states,
         LS_REQUIRE(b != nullptr, "basis must not be NULL");
         if (n == 0) return LS_OK;
         LS_REQUIRE(d_states && d_reps && d_chi && d_norm, "device pointers must not be NULL");
+        b->used.add(as_stream(stream));
         ls::launch_state_info(b, n, d_states, d_reps, d_chi, d_norm, as_stream(stream));
         return LS_OK;
     });
@@ -170,6 +216,7 @@ ls_status ls_index_lookup(const ls_basis *b, uint64_t n, const uint64_t *d_keys,
         LS_REQUIRE(b != nullptr, "basis must not be NULL");
         if (n == 0) return LS_OK;
         LS_REQUIRE(d_keys && d_index, "device pointers must not be NULL");
+        b->used.add(as_stream(stream));
         ls::launch_index_lookup(b, n, d_keys, d_index, as_stream(stream));
         return LS_OK;
     });
@@ -182,50 +229,35 @@ ls_status ls_operator_create(const ls_basis *b, uint32_t n_terms, const ls_term 
         op = new ls_operator();
         op->basis = b;
         ls::compile_terms(b, n_terms, terms, op);
+        // created without a stream: the default stream, waited for here
+        hipStream_t st0 = nullptr;
+        op->used.add(st0);
         const size_t bytes = std::max<size_t>(op->host_terms.size(), 1) * sizeof(ls_term_dev);
-        LS_HIP_CHECK(hipMalloc(&op->d_terms, bytes));
+        op->d_terms = ls::dev_alloc_n<ls_term_dev>(std::max<size_t>(op->host_terms.size(), 1), st0);
         if (!op->host_terms.empty())
-            LS_HIP_CHECK(hipMemcpy(op->d_terms, op->host_terms.data(), op->host_terms.size() * sizeof(ls_term_dev),
-                                   hipMemcpyHostToDevice));
+            LS_HIP_CHECK(hipMemcpyAsync(op->d_terms, op->host_terms.data(), bytes, hipMemcpyHostToDevice, st0));
         if (!op->host_cflip.empty()) {
-            LS_HIP_CHECK(hipMalloc(&op->d_cflip, op->host_cflip.size() * sizeof(uint64_t)));
-            LS_HIP_CHECK(hipMemcpy(op->d_cflip, op->host_cflip.data(), op->host_cflip.size() * sizeof(uint64_t),
-                                   hipMemcpyHostToDevice));
+            op->d_cflip = ls::dev_alloc_n<uint64_t>(op->host_cflip.size(), st0);
+            LS_HIP_CHECK(hipMemcpyAsync(op->d_cflip, op->host_cflip.data(), op->host_cflip.size() * sizeof(uint64_t),
+                                        hipMemcpyHostToDevice, st0));
         }
-        LS_HIP_CHECK(hipMalloc(&op->d_err, sizeof(uint32_t)));
+        op->d_err = ls::dev_alloc_n<uint32_t>(1, st0);
         const uint32_t zero = 0;
-        LS_HIP_CHECK(hipMemcpy(op->d_err, &zero, sizeof(uint32_t), hipMemcpyHostToDevice));
+        LS_HIP_CHECK(hipMemcpyAsync(op->d_err, &zero, sizeof(uint32_t), hipMemcpyHostToDevice, st0));
+        LS_HIP_CHECK(hipStreamSynchronize(st0));
         *out = op;
         return LS_OK;
     });
-    if (st != LS_OK && op) {
-        hipFree(op->d_terms);
-        hipFree(op->d_cflip);
-        hipFree(op->d_err);
-        delete op;
-    }
+    if (st != LS_OK && op) free_operator(op);
     return st;
 }
 
-void ls_operator_destroy(ls_operator *op) {
-    if (!op) return;
-    hipDeviceSynchronize();
-    hipFree(op->d_terms);
-    hipFree(op->d_cflip);
-    hipFree(op->d_err);
-    hipFree(op->d_st_off);
-    hipFree(op->d_st_width);
-    hipFree(op->d_st_cols);
-    hipFree(op->d_st_vals);
-    hipFree(op->d_st_codes);
-    hipFree(op->d_st_vtab);
-    hipFree(op->d_st_diag);
-    delete op;
-}
+void ls_operator_destroy(ls_operator *op) { free_operator(op); }
 
 ls_status ls_operator_store(ls_operator *op, uint64_t max_bytes, void *stream, uint64_t *bytes) {
     return guarded([&] {
         LS_REQUIRE(op != nullptr, "operator must not be NULL");
+        ls::touch(op, as_stream(stream));
         const uint64_t b = ls::store_elements(op, max_bytes, as_stream(stream));
         if (bytes) *bytes = b;
         return LS_OK;
@@ -244,6 +276,7 @@ ls_status ls_operator_info(const ls_operator *op, int *is_complex, uint64_t *dim
 ls_status ls_operator_count(const ls_operator *op, uint64_t *n_offdiag, void *stream) {
     return guarded([&] {
         LS_REQUIRE(op != nullptr && n_offdiag != nullptr, "operator and output must not be NULL");
+        ls::touch(op, as_stream(stream));
         *n_offdiag = ls::count_elements(op, as_stream(stream));
         return LS_OK;
     });
@@ -252,6 +285,7 @@ ls_status ls_operator_count(const ls_operator *op, uint64_t *n_offdiag, void *st
 ls_status ls_operator_check(const ls_operator *op, void *stream) {
     return guarded([&] {
         LS_REQUIRE(op != nullptr, "operator must not be NULL");
+        ls::touch(op, as_stream(stream));
         ls::check_operator(op, as_stream(stream));
         return LS_OK;
     });
@@ -261,6 +295,7 @@ ls_status ls_basis_test_drop_key(ls_basis *b, uint64_t index, void *stream) {
     return guarded([&] {
         LS_REQUIRE(b != nullptr, "basis must not be NULL");
         LS_REQUIRE(index < b->dim, "index must be below the dimension");
+        b->used.add(as_stream(stream));
         ls::drop_key(b, index, as_stream(stream));
         return LS_OK;
     });
@@ -287,6 +322,7 @@ ls_status ls_matvec(const ls_operator *op, uint32_t nrhs, const void *d_x, void 
         const char *xb = static_cast<const char *>(d_x);
         const char *yb = static_cast<const char *>(d_y);
         LS_REQUIRE(xb + bytes <= yb || yb + bytes <= xb, "x and y must not overlap");
+        ls::touch(op, as_stream(stream));
         ls::launch_matvec(op, nrhs, d_x, d_y, as_stream(stream));
         return LS_OK;
     });
@@ -302,6 +338,7 @@ ls_status ls_matvec_push(const ls_operator *op, uint32_t nrhs, const void *d_x, 
         const char *xb = static_cast<const char *>(d_x);
         const char *yb = static_cast<const char *>(d_y);
         LS_REQUIRE(xb + bytes <= yb || yb + bytes <= xb, "x and y must not overlap");
+        ls::touch(op, as_stream(stream));
         ls::launch_matvec_push(op, nrhs, d_x, d_y, as_stream(stream));
         return LS_OK;
     });
@@ -357,6 +394,7 @@ ls_status ls_solver_create(const ls_operator *op, const ls_lanczos_opts *opts, v
         LS_REQUIRE(opts->reorth <= 2, "reorth must be 0, 1 or 2");
         LS_REQUIRE(std::isfinite(opts->tol) && opts->tol >= 0, "tol must be >= 0");
         LS_REQUIRE(op->basis->dim > 0, "the basis is empty");
+        ls::touch(op, as_stream(stream));
         *out = ls::solver_create(op, opts, as_stream(stream));
         return LS_OK;
     });
@@ -394,6 +432,7 @@ ls_status ls_lanczos(const ls_operator *op, const ls_lanczos_opts *opts, void *s
         LS_REQUIRE(opts->reorth <= 2, "reorth must be 0, 1 or 2");
         LS_REQUIRE(std::isfinite(opts->tol) && opts->tol >= 0, "tol must be >= 0");
         LS_REQUIRE(op->basis->dim > 0, "the basis is empty");
+        ls::touch(op, as_stream(stream));
         return ls::run_lanczos(op, opts, as_stream(stream), e0, iters, resid_bound);
     });
 }

@@ -449,8 +449,7 @@ void enumerate_impl(ls_basis *b, hipStream_t st, uint64_t total, uint64_t **out_
         LS_HIP_CHECK(hipMemcpyAsync(&dim, d_total, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
         LS_HIP_CHECK(hipStreamSynchronize(st));
     }
-    uint64_t *reps = nullptr;
-    LS_HIP_CHECK(hipMalloc(&reps, std::max<uint64_t>(dim, 1) * sizeof(uint64_t)));
+    uint64_t *reps = dev_alloc_n<uint64_t>(std::max<uint64_t>(dim, 1), st);
     a.reps = reps;
     hipError_t e = hipSuccess;
     if (dim > 0) {
@@ -459,7 +458,7 @@ void enumerate_impl(ls_basis *b, hipStream_t st, uint64_t total, uint64_t **out_
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
-        (void)hipFree(reps);
+        dev_free(reps, st);
         LS_HIP_CHECK(e);
     }
     *out_reps = reps;
@@ -542,30 +541,32 @@ void fill_plan_dev(const GroupPlan &gp, PlanDev &pd) {
 
 }  // namespace
 
-void upload_plan(ls_basis *b) {
+void upload_plan(ls_basis *b, hipStream_t st) {
     const GroupPlan &gp = b->plan;
     const PlanTables t = plan_tables();
-    LS_HIP_CHECK(hipMalloc(&b->d_binom, t.binom.size() * sizeof(uint64_t)));
-    LS_HIP_CHECK(hipMemcpy(b->d_binom, t.binom.data(), t.binom.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    b->d_binom = dev_alloc_n<uint64_t>(t.binom.size(), st);
+    LS_HIP_CHECK(hipMemcpyAsync(b->d_binom, t.binom.data(), t.binom.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
     const size_t ncos = gp.cosets.size();
-    LS_HIP_CHECK(hipMalloc(&b->d_cosets, ncos * sizeof(CosetRep)));
-    LS_HIP_CHECK(hipMemcpy(b->d_cosets, gp.cosets.data(), ncos * sizeof(CosetRep), hipMemcpyHostToDevice));
-    LS_HIP_CHECK(hipMalloc(&b->d_chi, gp.n_elements * sizeof(double2)));
-    LS_HIP_CHECK(hipMemcpy(b->d_chi, gp.chi.data(), gp.n_elements * sizeof(double2), hipMemcpyHostToDevice));
-    LS_HIP_CHECK(hipMalloc(&b->d_chi_one, gp.chi_one.size() * sizeof(uint32_t)));
-    LS_HIP_CHECK(hipMemcpy(b->d_chi_one, gp.chi_one.data(), gp.chi_one.size() * sizeof(uint32_t),
-                           hipMemcpyHostToDevice));
+    b->d_cosets = dev_alloc_n<CosetRep>(ncos, st);
+    LS_HIP_CHECK(hipMemcpyAsync(b->d_cosets, gp.cosets.data(), ncos * sizeof(CosetRep), hipMemcpyHostToDevice, st));
+    b->d_chi = dev_alloc_n<double2>(gp.n_elements, st);
+    LS_HIP_CHECK(hipMemcpyAsync(b->d_chi, gp.chi.data(), gp.n_elements * sizeof(double2), hipMemcpyHostToDevice, st));
+    b->d_chi_one = dev_alloc_n<uint32_t>(gp.chi_one.size(), st);
+    LS_HIP_CHECK(hipMemcpyAsync(b->d_chi_one, gp.chi_one.data(), gp.chi_one.size() * sizeof(uint32_t),
+                                hipMemcpyHostToDevice, st));
     PlanDev &pd = b->plan_dev;
     fill_plan_dev(gp, pd);
     pd.cosets = b->d_cosets;
     pd.chi = b->d_chi;
     pd.chi_one = b->d_chi_one;
     if (gp.torus) {
-        LS_HIP_CHECK(hipMalloc(&b->d_pair_lut, gp.pair_lut.size() * sizeof(uint32_t)));
-        LS_HIP_CHECK(hipMemcpy(b->d_pair_lut, gp.pair_lut.data(), gp.pair_lut.size() * sizeof(uint32_t),
-                               hipMemcpyHostToDevice));
+        b->d_pair_lut = dev_alloc_n<uint32_t>(gp.pair_lut.size(), st);
+        LS_HIP_CHECK(hipMemcpyAsync(b->d_pair_lut, gp.pair_lut.data(), gp.pair_lut.size() * sizeof(uint32_t),
+                                    hipMemcpyHostToDevice, st));
         pd.pair_lut = b->d_pair_lut;
     }
+    // the host tables are released on return: the copies complete first
+    LS_HIP_CHECK(hipStreamSynchronize(st));
 }
 
 uint64_t candidate_count(const ls_basis *b) {
@@ -718,7 +719,7 @@ uint64_t count_members_noalloc(const GroupPlan &gp, int32_t weight, uint64_t beg
 void build_basis(ls_basis *b, hipStream_t st) {
     const GroupPlan &gp = b->plan;
     const uint32_t n = gp.n_sites;
-    upload_plan(b);
+    upload_plan(b, st);
 
     // candidates
     const uint64_t total = candidate_count(b);
@@ -726,7 +727,7 @@ void build_basis(ls_basis *b, hipStream_t st) {
     else enumerate_impl<uint64_t>(b, st, total, &b->d_reps, &b->dim);
     if (b->dim >= 0xFFFFFFFFull) throw Error{LS_EINVAL, "basis dimension must be below 2^32 - 1"};
 
-    LS_HIP_CHECK(hipMalloc(&b->d_stab, std::max<uint64_t>(b->dim, 1) * sizeof(uint16_t)));
+    b->d_stab = dev_alloc_n<uint16_t>(std::max<uint64_t>(b->dim, 1), st);
     if (n <= 32) stab_impl<uint32_t>(b, st);
     else stab_impl<uint64_t>(b, st);
 
@@ -744,8 +745,9 @@ void build_basis(ls_basis *b, hipStream_t st) {
     } else {
         uint64_t kmin = 0, kmax = 0;
         if (b->dim > 0) {
-            LS_HIP_CHECK(hipMemcpy(&kmin, b->d_reps, sizeof(uint64_t), hipMemcpyDeviceToHost));
-            LS_HIP_CHECK(hipMemcpy(&kmax, b->d_reps + (b->dim - 1), sizeof(uint64_t), hipMemcpyDeviceToHost));
+            LS_HIP_CHECK(hipMemcpyAsync(&kmin, b->d_reps, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+            LS_HIP_CHECK(hipMemcpyAsync(&kmax, b->d_reps + (b->dim - 1), sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+            LS_HIP_CHECK(hipStreamSynchronize(st));
         }
         S.kmin = kmin;
         S.kmax = kmax;
@@ -759,7 +761,7 @@ void build_basis(ls_basis *b, hipStream_t st) {
             S.hash_mask = cap - 1;
             S.hash_shift = 64;
             for (uint64_t c = cap; c > 1; c >>= 1) --S.hash_shift;
-            LS_HIP_CHECK(hipMalloc(&b->d_table, cap * sizeof(HashSlot)));
+            b->d_table = dev_alloc_n<HashSlot>(cap, st);
             LS_HIP_CHECK(hipMemsetAsync(b->d_table, 0xFF, cap * sizeof(HashSlot), st));
             if (b->dim > 0)
                 hipLaunchKernelGGL(k_hash_insert, dim3(grid_for(b->dim)), dim3(kBlock), 0, st, b->d_reps, b->d_stab,
@@ -779,7 +781,7 @@ void build_basis(ls_basis *b, hipStream_t st) {
         S.bits = bits;
         S.shift = len > bits ? len - bits : 0;
         const uint64_t nb = (range >> S.shift) + 1;   // buckets 0 .. nb-1
-        LS_HIP_CHECK(hipMalloc(&b->d_buckets, (nb + 1) * sizeof(uint32_t)));
+        b->d_buckets = dev_alloc_n<uint32_t>(nb + 1, st);
         hipLaunchKernelGGL(k_buckets, dim3(grid_for(nb + 1)), dim3(kBlock), 0, st, b->d_reps, b->dim, kmin, S.shift,
                            nb, b->d_buckets);
         LS_HIP_CHECK(hipGetLastError());

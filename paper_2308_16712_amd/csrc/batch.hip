@@ -147,9 +147,8 @@ void build_tiles(Group &g, hipStream_t st) {
     std::vector<Tile> tiles;
     for (uint32_t j : order)
         for (uint64_t r = 0; r < g.jobs[j].dim; r += rows_per_tile) tiles.push_back(Tile{j, 0, r});
-    if (g.d_tiles) hipFree(g.d_tiles);
-    g.d_tiles = nullptr;
-    LS_HIP_CHECK(hipMalloc(&g.d_tiles, std::max<size_t>(tiles.size(), 1) * sizeof(Tile)));
+    dev_free(g.d_tiles, st);
+    g.d_tiles = dev_alloc_n<Tile>(std::max<size_t>(tiles.size(), 1), st);
     if (!tiles.empty())
         LS_HIP_CHECK(hipMemcpyAsync(g.d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
     LS_HIP_CHECK(hipStreamSynchronize(st));
@@ -246,6 +245,7 @@ struct ls_batch {
     std::vector<uint32_t *> own_buckets;     // tuned search layouts (one per basis)
     std::vector<ls::SearchDev> search;       // per item
     hipStream_t cap = nullptr;               // stream used for graph capture
+    ls::StreamSet used;                      // streams of its products
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool use_graph = true;
@@ -275,14 +275,13 @@ SearchDev tuned_search(ls_batch *B, const ls_basis *b, hipStream_t st) {
     auto build = [&](uint32_t nbits, uint32_t **out, uint32_t *shift) {
         *shift = len > nbits ? len - nbits : 0;
         const uint64_t nb = (range >> *shift) + 1;
-        LS_HIP_CHECK(hipMalloc(out, (nb + 1) * sizeof(uint32_t)));
+        *out = dev_alloc_n<uint32_t>(nb + 1, st);
         hipLaunchKernelGGL(k_buckets_tuned, dim3(static_cast<uint32_t>((nb + 1 + 255) / 256)), dim3(256), 0, st,
                            b->d_reps, b->dim, S.kmin, *shift, nb, *out);
         LS_HIP_CHECK(hipGetLastError());
     };
     if (bits == 0) {
-        uint64_t *sink = nullptr;
-        LS_HIP_CHECK(hipMalloc(&sink, sizeof(uint64_t)));
+        uint64_t *sink = dev_alloc_n<uint64_t>(1, st);
         hipEvent_t e0, e1;
         LS_HIP_CHECK(hipEventCreate(&e0));
         LS_HIP_CHECK(hipEventCreate(&e1));
@@ -306,7 +305,7 @@ SearchDev tuned_search(ls_batch *B, const ls_basis *b, hipStream_t st) {
             LS_HIP_CHECK(hipEventSynchronize(e1));
             float ms = 0.f;
             LS_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-            hipFree(tab);
+            dev_free(tab, st);
             if (ms < best) {
                 best = ms;
                 bits = static_cast<uint32_t>(cand);
@@ -314,7 +313,7 @@ SearchDev tuned_search(ls_batch *B, const ls_basis *b, hipStream_t st) {
         }
         hipEventDestroy(e0);
         hipEventDestroy(e1);
-        hipFree(sink);
+        dev_free(sink, st);
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_bits_cache[key] = bits;
     }
@@ -329,12 +328,13 @@ SearchDev tuned_search(ls_batch *B, const ls_basis *b, hipStream_t st) {
 
 void free_batch(ls_batch *B) {
     if (!B) return;
+    B->used.drain();
     for (auto &g : B->groups) {
-        hipFree(g.d_jobs);
-        hipFree(g.d_tiles);
-        hipFree(g.d_counter);
+        dev_free(g.d_jobs);
+        dev_free(g.d_tiles);
+        dev_free(g.d_counter);
     }
-    for (auto *p : B->own_buckets) hipFree(p);
+    for (auto *p : B->own_buckets) dev_free(p);
     if (B->exec) hipGraphExecDestroy(B->exec);
     if (B->graph) hipGraphDestroy(B->graph);
     if (B->cap) hipStreamDestroy(B->cap);
@@ -366,10 +366,7 @@ void batch_create(uint32_t n, const ls_operator *const *ops, const uint32_t *nrh
     *out = B;
 }
 
-void batch_destroy(ls_batch *B) {
-    hipDeviceSynchronize();
-    free_batch(B);
-}
+void batch_destroy(ls_batch *B) { free_batch(B); }
 
 // First call: search layouts, grouping, tiles, tuning; later calls reuse them.
 static void batch_prepare(ls_batch *B, hipStream_t st) {
@@ -410,8 +407,8 @@ static void batch_prepare(ls_batch *B, hipStream_t st) {
         }
     }
     for (auto &g : B->groups) {
-        LS_HIP_CHECK(hipMalloc(&g.d_jobs, g.jobs.size() * sizeof(MatvecJob)));
-        LS_HIP_CHECK(hipMalloc(&g.d_counter, sizeof(uint32_t)));
+        g.d_jobs = dev_alloc_n<MatvecJob>(g.jobs.size(), st);
+        g.d_counter = dev_alloc_n<uint32_t>(1, st);
         upload_jobs(g, st);
         tune_group(g, st, B->n_cu);
     }
@@ -421,6 +418,8 @@ static void batch_prepare(ls_batch *B, hipStream_t st) {
 void batch_matvec(ls_batch *B, const void *const *xs, void *const *ys, hipStream_t st) {
     const uint32_t n = static_cast<uint32_t>(B->ops.size());
     LS_REQUIRE(xs != nullptr && ys != nullptr, "x and y arrays must not be NULL");
+    B->used.add(st);
+    for (const ls_operator *op : B->ops) touch(op, st);
     bool changed = false;
     for (uint32_t i = 0; i < n; ++i) {
         const uint64_t dim = B->ops[i]->basis->dim;

@@ -14,7 +14,9 @@
 // Dot products use a fixed grid and a fixed reduction tree, so results do
 // not depend on scheduling.  The m x m tridiagonal eigenproblem is solved on
 // the host (Sturm-sequence bisection for the lowest eigenvalue, inverse
-// iteration for the last component of its eigenvector).
+// iteration for the last component of its eigenvector).  ls_lanczos runs
+// one solve through the stepper below: alpha and beta stay on the device and
+// a step ends with one synchronisation.
 
 #include <algorithm>
 #include <cmath>
@@ -191,31 +193,6 @@ __global__ void k_reorth_pick(const int *gate, const double2 *w2n, double2 *nrm)
     if (*gate) nrm[0] = w2n[0];
 }
 
-// w -= alpha v + beta vp   (vp may be null)
-template <bool CPLX>
-__global__ void __launch_bounds__(kBlock) k_three_term(void *pw, const void *pv, const void *pvp, uint64_t n,
-                                                       double alpha, double beta) {
-    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
-    if (i >= n) return;
-    if constexpr (CPLX) {
-        double2 w = static_cast<double2 *>(pw)[i];
-        const double2 v = static_cast<const double2 *>(pv)[i];
-        w.x -= alpha * v.x;
-        w.y -= alpha * v.y;
-        if (pvp) {
-            const double2 u = static_cast<const double2 *>(pvp)[i];
-            w.x -= beta * u.x;
-            w.y -= beta * u.y;
-        }
-        static_cast<double2 *>(pw)[i] = w;
-    } else {
-        double w = static_cast<double *>(pw)[i];
-        w -= alpha * static_cast<const double *>(pv)[i];
-        if (pvp) w -= beta * static_cast<const double *>(pvp)[i];
-        static_cast<double *>(pw)[i] = w;
-    }
-}
-
 // dst = src / s (element-wise over doubles)
 __global__ void __launch_bounds__(kBlock) k_div(double *dst, const double *src, uint64_t n, double s) {
     const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
@@ -358,112 +335,7 @@ double tridiag_last_component(const std::vector<double> &a, const std::vector<do
     return std::fabs(z[m - 1]);
 }
 
-struct DevMem {
-    void *p = nullptr;
-    ~DevMem() { if (p) hipFree(p); }
-};
-
-template <bool CPLX>
-ls_status lanczos_impl(const ls_operator *op, const ls_lanczos_opts *o, hipStream_t st, double *e0_out,
-                       uint32_t *iters_out, double *resid_out) {
-    using T = typename V<CPLX>::T;
-    const uint64_t n = op->basis->dim;
-    const uint32_t m = static_cast<uint32_t>(std::min<uint64_t>(o->max_iter, n));
-    const size_t es = sizeof(T);
-    DevMem Vm, wm, part, scal, aux;
-    hipError_t err = hipMalloc(&Vm.p, static_cast<size_t>(m) * n * es);
-    if (err != hipSuccess) throw Error{LS_ENOMEM, "cannot allocate the Krylov vectors"};
-    LS_HIP_CHECK(hipMalloc(&wm.p, n * es));
-    LS_HIP_CHECK(hipMalloc(&part.p, static_cast<size_t>(kDotBlocks) * std::max<uint32_t>(m, 1) * sizeof(double2)));
-    LS_HIP_CHECK(hipMalloc(&scal.p, std::max<uint32_t>(m, 1) * sizeof(double2)));
-    LS_HIP_CHECK(hipMalloc(&aux.p, kAuxBytes));
-    T *Vb = static_cast<T *>(Vm.p);
-    T *w = static_cast<T *>(wm.p);
-    double2 *partial = static_cast<double2 *>(part.p);
-    double2 *hs = static_cast<double2 *>(scal.p);
-    const uint64_t nd = n * (CPLX ? 2 : 1);    // doubles per vector
-    const ReorthBufs rb = reorth_bufs(partial, hs, aux.p, static_cast<int>(m));
-
-    auto dot = [&](const T *x, const T *y) {
-        hipLaunchKernelGGL(k_dot_partial<CPLX>, dim3(kDotBlocks), dim3(kBlock), 0, st, x, y, n, partial);
-        hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, partial, kDotBlocks, 1, hs);
-        double2 r;
-        LS_HIP_CHECK(hipMemcpyAsync(&r, hs, sizeof(double2), hipMemcpyDeviceToHost, st));
-        LS_HIP_CHECK(hipStreamSynchronize(st));
-        return r;
-    };
-
-    // start vector
-    if (o->d_v0) {
-        LS_HIP_CHECK(hipMemcpyAsync(w, o->d_v0, n * es, hipMemcpyDeviceToDevice, st));
-    } else {
-        hipLaunchKernelGGL(k_fill_uniform, dim3(grid(nd)), dim3(kBlock), 0, st, reinterpret_cast<double *>(w), nd,
-                           o->seed);
-    }
-    LS_HIP_CHECK(hipGetLastError());
-    const double nrm0 = std::sqrt(dot(w, w).x);
-    if (!(nrm0 > 0.0)) throw Error{LS_EINVAL, "the start vector is zero"};
-    hipLaunchKernelGGL(k_div, dim3(grid(nd)), dim3(kBlock), 0, st, reinterpret_cast<double *>(Vb),
-                       reinterpret_cast<const double *>(w), nd, nrm0);
-
-    std::vector<double> alpha, beta;
-    double e0 = 0.0, resid = INFINITY, prev = 0.0;
-    bool have_prev = false, converged = false;
-    for (uint32_t k = 0; k < m; ++k) {
-        T *vk = Vb + static_cast<uint64_t>(k) * n;
-        launch_matvec(op, 1, vk, w, st);
-        const double a = dot(vk, w).x;
-        hipLaunchKernelGGL(k_three_term<CPLX>, dim3(grid(n)), dim3(kBlock), 0, st, w, vk,
-                           k > 0 ? Vb + static_cast<uint64_t>(k - 1) * n : nullptr, n, a,
-                           k > 0 ? beta[k - 1] : 0.0);
-        enqueue_reorth<CPLX>(Vb, n, static_cast<int>(k) + 1, static_cast<int>(o->reorth), w, rb, rb.nrm + 3, st);
-        LS_HIP_CHECK(hipGetLastError());
-        double2 wn;
-        uint32_t miss = 0;
-        LS_HIP_CHECK(hipMemcpyAsync(&wn, rb.nrm + 3, sizeof(double2), hipMemcpyDeviceToHost, st));
-        enqueue_flag_read(op, &miss, st);
-        LS_HIP_CHECK(hipStreamSynchronize(st));
-        if (miss)
-            throw Error{LS_EINTERNAL, "Lanczos step " + std::to_string(k) +
-                                          ": the product met a neighbour whose representative lies in the sector "
-                                          "but is missing from the basis"};
-        const double bnext = std::sqrt(wn.x);
-        alpha.push_back(a);
-        e0 = tridiag_lowest(alpha, beta);
-        resid = bnext * tridiag_last_component(alpha, beta, e0);
-        const double scale = std::max(1.0, std::fabs(e0));
-        if (o->tol > 0 && have_prev && std::fabs(e0 - prev) < o->tol * scale && resid < std::sqrt(o->tol) * scale) {
-            converged = true;
-            break;
-        }
-        prev = e0;
-        have_prev = true;
-        if (k + 1 < m) {
-            if (bnext == 0.0) break;
-            beta.push_back(bnext);
-            hipLaunchKernelGGL(k_div, dim3(grid(nd)), dim3(kBlock), 0, st,
-                               reinterpret_cast<double *>(Vb + static_cast<uint64_t>(k + 1) * n),
-                               reinterpret_cast<const double *>(w), nd, bnext);
-        }
-    }
-    LS_HIP_CHECK(hipStreamSynchronize(st));
-    if (o->alpha)
-        for (size_t k = 0; k < alpha.size(); ++k) o->alpha[k] = alpha[k];
-    if (o->beta)
-        for (size_t k = 0; k < beta.size(); ++k) o->beta[k] = beta[k];
-    if (e0_out) *e0_out = e0;
-    if (iters_out) *iters_out = static_cast<uint32_t>(alpha.size());
-    if (resid_out) *resid_out = resid;
-    return (o->tol > 0 && !converged) ? LS_WNOTCONV : LS_OK;
-}
-
 }  // namespace
-
-ls_status run_lanczos(const ls_operator *op, const ls_lanczos_opts *o, hipStream_t st, double *e0, uint32_t *iters,
-                      double *resid) {
-    if (op->is_complex) return lanczos_impl<true>(op, o, st, e0, iters, resid);
-    return lanczos_impl<false>(op, o, st, e0, iters, resid);
-}
 
 // ---- the stepper: one Lanczos iteration for many solves at once ----------
 //
@@ -531,8 +403,11 @@ struct ls_solver {
     double2 *dots = nullptr;      // [2]: <v_k, w>, <w, w>
     double *scal = nullptr;       // [2]: alpha_k, beta_{k+1}
     double *bprev = nullptr;      // beta_k (device copy)
-    double *host = nullptr;       // pinned [2]
-    uint32_t *hflag = nullptr;    // pinned: the operator's error flag after a step
+    double host_rows[2] = {0.0, 0.0};
+    uint32_t hflag_word = 0;
+    double *host = host_rows;     // [2] alpha, beta read back after a step
+    uint32_t *hflag = &hflag_word;   // the operator's error flag after a step
+    ls::StreamSet used;           // streams of its steps
     std::vector<double> alpha, beta;
     uint32_t k = 0;
     double e0 = 0.0, resid = INFINITY, prev = 0.0;
@@ -548,16 +423,15 @@ FusedState *g_fused = nullptr;
 
 void free_solver(ls_solver *s) {
     if (!s) return;
-    hipFree(s->V);
-    hipFree(s->w);
-    hipFree(s->partial);
-    hipFree(s->hs);
-    hipFree(s->aux);
-    hipFree(s->dots);
-    hipFree(s->scal);
-    hipFree(s->bprev);
-    if (s->host) hipHostFree(s->host);
-    if (s->hflag) hipHostFree(s->hflag);
+    s->used.drain();
+    dev_free(s->V);
+    dev_free(s->w);
+    dev_free(s->partial);
+    dev_free(s->hs);
+    dev_free(s->aux);
+    dev_free(s->dots);
+    dev_free(s->scal);
+    dev_free(s->bprev);
     delete s;
 }
 
@@ -636,19 +510,19 @@ ls_solver *solver_create(const ls_operator *op, const ls_lanczos_opts *o, hipStr
         s->tol = o->tol;
         s->reorth = static_cast<int>(o->reorth);
         const size_t es = s->cplx ? 16 : 8;
-        if (hipMalloc(&s->V, static_cast<size_t>(s->m) * s->n * es) != hipSuccess)
+        s->used.add(st);
+        try {
+            s->V = dev_alloc(static_cast<size_t>(s->m) * s->n * es, st);
+        } catch (const Error &) {
             throw Error{LS_ENOMEM, "cannot allocate the Krylov vectors"};
-        LS_HIP_CHECK(hipMalloc(&s->w, s->n * es));
-        LS_HIP_CHECK(hipMalloc(&s->partial, static_cast<size_t>(kDotBlocks) * std::max<uint32_t>(s->m, 1) *
-                                                sizeof(double2)));
-        LS_HIP_CHECK(hipMalloc(&s->hs, std::max<uint32_t>(s->m, 1) * sizeof(double2)));
-        LS_HIP_CHECK(hipMalloc(&s->aux, kAuxBytes));
-        LS_HIP_CHECK(hipMalloc(&s->dots, 2 * sizeof(double2)));
-        LS_HIP_CHECK(hipMalloc(&s->scal, 2 * sizeof(double)));
-        LS_HIP_CHECK(hipMalloc(&s->bprev, sizeof(double)));
-        LS_HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&s->host), 2 * sizeof(double)));
-        LS_HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&s->hflag), sizeof(uint32_t)));
-        *s->hflag = 0;
+        }
+        s->w = dev_alloc(s->n * es, st);
+        s->partial = dev_alloc_n<double2>(static_cast<size_t>(kDotBlocks) * std::max<uint32_t>(s->m, 1), st);
+        s->hs = dev_alloc_n<double2>(std::max<uint32_t>(s->m, 1), st);
+        s->aux = dev_alloc(kAuxBytes, st);
+        s->dots = dev_alloc_n<double2>(2, st);
+        s->scal = dev_alloc_n<double>(2, st);
+        s->bprev = dev_alloc_n<double>(1, st);
         // start vector, normalised exactly as run_lanczos does
         const uint64_t nd = s->n * (s->cplx ? 2 : 1);
         if (o->d_v0)
@@ -674,10 +548,7 @@ ls_solver *solver_create(const ls_operator *op, const ls_lanczos_opts *o, hipStr
     return s;
 }
 
-void solver_destroy(ls_solver *s) {
-    hipDeviceSynchronize();
-    free_solver(s);
-}
+void solver_destroy(ls_solver *s) { free_solver(s); }
 
 // ---- batched step: the work after the products of several solves, one
 // launch per kernel for all of them ------------------------------------------
@@ -1083,6 +954,10 @@ void solver_step(ls_solver *const *ss, uint32_t n, hipStream_t st) {
     for (uint32_t i = 0; i < n; ++i)
         if (ss[i] && !ss[i]->done) act.push_back(ss[i]);
     if (act.empty()) return;
+    for (ls_solver *s : act) {
+        s->used.add(st);
+        touch(s->op, st);
+    }
     // one fused launch for every active solve's product w = H v_k
     std::vector<const ls_operator *> ops;
     std::vector<const void *> xs;
@@ -1179,6 +1054,33 @@ void solver_step(ls_solver *const *ss, uint32_t n, hipStream_t st) {
 }
 
 bool solver_failed(const ls_solver *s) { return s->failed; }
+
+// ls_lanczos: one solve driven by the stepper, so a step costs one
+// synchronisation (alpha and beta stay on the device until the step's single
+// read-back) instead of the two of the host-side recurrence; the arithmetic
+// is the same kernel for kernel.
+ls_status run_lanczos(const ls_operator *op, const ls_lanczos_opts *o, hipStream_t st, double *e0_out,
+                      uint32_t *iters_out, double *resid_out) {
+    ls_solver *s = solver_create(op, o, st);
+    try {
+        while (!s->done) solver_step(&s, 1, st);
+    } catch (...) {
+        hipStreamSynchronize(st);
+        free_solver(s);
+        throw;
+    }
+    if (o->alpha)
+        for (size_t k = 0; k < s->alpha.size(); ++k) o->alpha[k] = s->alpha[k];
+    if (o->beta)
+        for (size_t k = 0; k < s->beta.size(); ++k) o->beta[k] = s->beta[k];
+    if (e0_out) *e0_out = s->e0;
+    if (iters_out) *iters_out = static_cast<uint32_t>(s->alpha.size());
+    if (resid_out) *resid_out = s->resid;
+    const bool conv = s->converged;
+    LS_HIP_CHECK(hipStreamSynchronize(st));
+    free_solver(s);
+    return (o->tol > 0 && !conv) ? LS_WNOTCONV : LS_OK;
+}
 
 void solver_result(const ls_solver *s, double *e0, uint32_t *iters, double *resid, int *done, int *converged) {
     if (e0) *e0 = s->e0;

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -33,6 +34,33 @@ struct Error {
     do {                                                                              \
         if (!(cond)) throw ::ls::Error{LS_EINVAL, (msg)};                             \
     } while (0)
+
+// ---------------------------------------------------------------- handle memory
+//
+// Device memory of library handles is allocated in stream order
+// (hipMallocAsync) on the stream of the call that creates it, and released
+// with hipFreeAsync on the null stream once every stream the handle was used
+// on has drained.  hipFree would wait for the whole device: a handle retired
+// beside work on other streams (a build, another solve) would wait for it.
+
+// Allocates `bytes` (at least 1) on `stream`; throws LS_ENOMEM.
+void *dev_alloc(size_t bytes, hipStream_t stream);
+template <class T>
+T *dev_alloc_n(size_t count, hipStream_t stream) {
+    return static_cast<T *>(dev_alloc(count * sizeof(T), stream));
+}
+// Stream-ordered release on `stream` (the null stream once the handle's
+// streams have drained); null pointers are ignored.
+void dev_free(void *p, hipStream_t stream = nullptr);
+
+// The streams a handle's device work was enqueued on.
+struct StreamSet {
+    std::mutex mu;
+    std::vector<hipStream_t> streams;
+    void add(hipStream_t s);
+    // Waits for each recorded stream (the caller's streams must still exist).
+    void drain();
+};
 
 // ---------------------------------------------------------------- group plan
 //
@@ -139,6 +167,7 @@ struct SearchDev {
 
 struct ls_basis {
     ls::GroupPlan plan;
+    mutable ls::StreamSet used;        // streams of the calls that read it
     std::vector<uint16_t> perm_copy;   // the descriptor's group, [nG][N]
     std::vector<uint8_t> flip_copy;    // [nG]
     int32_t weight = -1;
@@ -165,6 +194,7 @@ struct ls_term_dev {
 
 struct ls_operator {
     const ls_basis *basis = nullptr;
+    mutable ls::StreamSet used;        // streams of the calls that ran its products
     bool is_complex = false;
     uint32_t n_diag = 0, n_off = 0;
     ls_term_dev *d_terms = nullptr;     // diagonal terms first, then off-diagonal
@@ -192,7 +222,7 @@ struct ls_operator {
 namespace ls {
 
 // basis.hip
-void upload_plan(ls_basis *b);
+void upload_plan(ls_basis *b, hipStream_t stream);
 // Test hook: the representative at `index` is taken out of the hash index
 // (its slot keeps a key no lookup asks for), so lookups of it miss.
 void drop_key(ls_basis *b, uint64_t index, hipStream_t stream);
@@ -213,6 +243,9 @@ void launch_index_lookup(const ls_basis *b, uint64_t n, const uint64_t *keys, in
 
 // terms.cpp
 void compile_terms(const ls_basis *b, uint32_t n_terms, const ls_term *terms, ls_operator *op);
+
+// Records `stream` as used by op and its basis.
+void touch(const ls_operator *op, hipStream_t stream);
 
 // matvec.hip
 uint32_t matvec_max_terms();   // the term table is staged in LDS

@@ -109,8 +109,7 @@ __global__ void __launch_bounds__(256) k_count_elements(const uint64_t *reps, ui
 uint64_t count_elements(const ls_operator *op, hipStream_t st) {
     const ls_basis *b = op->basis;
     if (b->dim == 0) return 0;
-    unsigned long long *d = nullptr;
-    LS_HIP_CHECK(hipMalloc(&d, sizeof(unsigned long long)));
+    unsigned long long *d = dev_alloc_n<unsigned long long>(1, st);
     unsigned long long h = 0;
     hipError_t e = hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
@@ -120,7 +119,7 @@ uint64_t count_elements(const ls_operator *op, hipStream_t st) {
     }
     if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(d);
+    dev_free(d, st);
     LS_HIP_CHECK(e);
     return h;
 }

@@ -247,21 +247,24 @@ void launch_spmv_nr(const ls_operator *op, int nr, uint32_t nrhs, uint32_t col, 
 #undef LS_SPMV
 }
 
-// Device buffers of a store attempt, released unless handed to the operator.
+// Device buffers of a store attempt, released in stream order on the
+// store's stream unless handed to the operator.
 struct StoreBufs {
+    hipStream_t st;
     uint32_t *width = nullptr, *cols = nullptr, *overflow = nullptr;
     uint64_t *off = nullptr, *vtab = nullptr;
     void *vals = nullptr, *diag = nullptr;
     uint8_t *codes = nullptr;
+    explicit StoreBufs(hipStream_t s) : st(s) {}
     ~StoreBufs() {
-        hipFree(width);
-        hipFree(off);
-        hipFree(cols);
-        hipFree(vals);
-        hipFree(codes);
-        hipFree(vtab);
-        hipFree(overflow);
-        hipFree(diag);
+        dev_free(width, st);
+        dev_free(off, st);
+        dev_free(cols, st);
+        dev_free(vals, st);
+        dev_free(codes, st);
+        dev_free(vtab, st);
+        dev_free(overflow, st);
+        dev_free(diag, st);
     }
 };
 
@@ -273,11 +276,11 @@ uint64_t store_elements(ls_operator *op, uint64_t max_bytes, hipStream_t st) {
     const uint64_t dim = b->dim;
     const uint64_t slices = (dim + kSlice - 1) / kSlice;
     const size_t es = op->is_complex ? sizeof(double2) : sizeof(double);
-    StoreBufs B;
+    StoreBufs B(st);
     std::vector<uint32_t> width(slices, 0);
     std::vector<uint64_t> off(slices, 0);
     if (slices > 0) {
-        LS_HIP_CHECK(hipMalloc(&B.width, slices * sizeof(uint32_t)));
+        B.width = dev_alloc_n<uint32_t>(slices, st);
         hipLaunchKernelGGL(k_slice_width, dim3(static_cast<uint32_t>((dim + 255) / 256)), dim3(256), 0, st, b->d_reps,
                            dim, op->d_terms, op->n_diag, op->n_diag + op->n_off, B.width);
         LS_HIP_CHECK(hipGetLastError());
@@ -295,10 +298,7 @@ uint64_t store_elements(ls_operator *op, uint64_t max_bytes, hipStream_t st) {
     bool coded = !op->is_complex;
     uint64_t bytes = coded ? coded_bytes : full_bytes;
     if (bytes > max_bytes) throw Error{LS_ENOMEM, "the stored elements would exceed max_bytes"};
-    auto alloc = [](void **p, uint64_t n) {
-        if (hipMalloc(p, std::max<uint64_t>(n, 1)) != hipSuccess)
-            throw Error{LS_ENOMEM, "device allocation for the stored elements failed"};
-    };
+    auto alloc = [&](void **p, uint64_t n) { *p = dev_alloc(n, st); };
     alloc(reinterpret_cast<void **>(&B.off), slices * sizeof(uint64_t));
     alloc(reinterpret_cast<void **>(&B.cols), slots * sizeof(uint32_t));
     alloc(&B.diag, dim * es);
@@ -331,9 +331,9 @@ uint64_t store_elements(ls_operator *op, uint64_t max_bytes, hipStream_t st) {
         LS_HIP_CHECK(hipMemcpyAsync(&over, B.overflow, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         LS_HIP_CHECK(hipStreamSynchronize(st));
         if (!over) break;
-        hipFree(B.codes);
-        hipFree(B.vtab);
-        hipFree(B.overflow);
+        dev_free(B.codes, st);
+        dev_free(B.vtab, st);
+        dev_free(B.overflow, st);
         B.codes = nullptr;
         B.vtab = nullptr;
         B.overflow = nullptr;
