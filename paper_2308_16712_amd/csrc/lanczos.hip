@@ -1055,15 +1055,98 @@ void solver_step(ls_solver *const *ss, uint32_t n, hipStream_t st) {
 
 bool solver_failed(const ls_solver *s) { return s->failed; }
 
-// ls_lanczos: one solve driven by the stepper, so a step costs one
-// synchronisation (alpha and beta stay on the device until the step's single
-// read-back) instead of the two of the host-side recurrence; the arithmetic
-// is the same kernel for kernel.
+namespace {
+
+// Pinned read-back rows of solver_run: (alpha, beta) and the flag word of
+// every step of a chunk.
+struct ChunkRows {
+    double *rows = nullptr;     // [cap][2]
+    uint32_t *flags = nullptr;  // [cap]
+    size_t cap = 0;
+};
+ChunkRows g_chunk;
+
+// Up to `count` steps of one solve enqueued back to back with a single
+// synchronisation at the end.  The kernels of a step read alpha and beta on
+// the device, so the steps need nothing from the host in between; the host
+// bookkeeping then replays the steps in order, exactly as after single
+// steps, and stops where single steps would have stopped.  Steps enqueued
+// past that point (convergence or breakdown inside the chunk) only write
+// Krylov vectors and device scalars that the finished solve never reads.
+template <bool CPLX>
+void solver_run(ls_solver *s, uint32_t count, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_step_mu);
+    if (s->done) return;
+    s->used.add(st);
+    touch(s->op, st);
+    const uint32_t k0 = s->k;
+    const uint32_t c = std::min(count, s->m - k0);
+    if (g_chunk.cap < c) {
+        if (g_chunk.rows) LS_HIP_CHECK(hipHostFree(g_chunk.rows));
+        if (g_chunk.flags) LS_HIP_CHECK(hipHostFree(g_chunk.flags));
+        g_chunk = ChunkRows{};
+        const size_t cap = std::max<size_t>(c, 64);
+        LS_HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&g_chunk.rows), cap * 2 * sizeof(double)));
+        LS_HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&g_chunk.flags), cap * sizeof(uint32_t)));
+        g_chunk.cap = cap;
+    }
+    double *const own_host = s->host;
+    uint32_t *const own_flag = s->hflag;
+    using T = typename V<CPLX>::T;
+    try {
+        for (uint32_t i = 0; i < c; ++i) {
+            s->k = k0 + i;
+            s->host = g_chunk.rows + 2 * i;
+            s->hflag = g_chunk.flags + i;
+            launch_matvec(s->op, 1, static_cast<const T *>(s->V) + static_cast<size_t>(s->k) * s->n, s->w, st);
+            enqueue_after_product<CPLX>(s, st);
+        }
+        LS_HIP_CHECK(hipStreamSynchronize(st));
+    } catch (...) {
+        s->k = k0;
+        s->host = own_host;
+        s->hflag = own_flag;
+        throw;
+    }
+    s->k = k0;
+    bool failed = false;
+    for (uint32_t i = 0; i < c && !s->done; ++i) {
+        s->host = g_chunk.rows + 2 * i;
+        if (g_chunk.flags[i]) {
+            s->failed = true;
+            s->done = true;
+            failed = true;
+            break;
+        }
+        finish_step(s);
+    }
+    s->host = own_host;
+    s->hflag = own_flag;
+    if (failed)
+        throw Error{LS_EINTERNAL,
+                    "the solve met a neighbour whose representative lies in the sector but is missing from the "
+                    "basis"};
+}
+
+}  // namespace
+
+// ls_lanczos: one solve driven by the stepper kernels (alpha and beta stay on
+// the device), run in chunks of steps with one synchronisation per chunk.
+// With a tolerance, sectors of up to 2^20 states run chunks of 8 steps (there
+// a synchronisation costs about as much as a step; at most 7 steps run past
+// convergence) and larger ones single steps; without a tolerance every step
+// up to max_iter is needed and chunks hold 32 steps.  The arithmetic is that
+// of single steps, kernel for kernel, so the results are those of
+// ls_solver_step.
 ls_status run_lanczos(const ls_operator *op, const ls_lanczos_opts *o, hipStream_t st, double *e0_out,
                       uint32_t *iters_out, double *resid_out) {
     ls_solver *s = solver_create(op, o, st);
+    const uint32_t chunk = o->tol > 0 ? (s->n <= (1u << 20) ? 8u : 1u) : 32u;
     try {
-        while (!s->done) solver_step(&s, 1, st);
+        while (!s->done) {
+            if (s->cplx) solver_run<true>(s, chunk, st);
+            else solver_run<false>(s, chunk, st);
+        }
     } catch (...) {
         hipStreamSynchronize(st);
         free_solver(s);
