@@ -239,12 +239,31 @@ def batched_vs_plain(count: int, nrhs: int, reps_timed: int = 3):
     t_batch = timed(lambda: batch.matvec(xs, ys))
     t_plain = timed(plain)
     t_multi = timed(plain_multi)
+    # the same batch with every search layout fixed to the largest bucket
+    # table staged in LDS (2^13 buckets), for comparison with the tuned choice
+    staged = ls.Batch(ops, [nrhs] * count, search=("staged", 13))
+    ys_st = [torch.empty_like(x) for x in xs]
+    staged.matvec(xs, ys_st)
+    t_staged = timed(lambda: staged.matvec(xs, ys_st))
     for op in ops:
         op.check()
     # same results (the row arithmetic is shared)
     same = all(torch.equal(ys[k][:, q], yp[k][q]) for k in range(count) for q in range(nrhs))
-    same = same and all(torch.equal(ys[k], ym[k]) for k in range(count))
+    same = same and all(torch.equal(ys[k], ym[k]) and torch.equal(ys[k], ys_st[k]) for k in range(count))
     dims = [op.dim for op in ops]
+    layouts = [batch.search(k) for k in range(count)]
+    chosen = {}
+    for lay in layouts:
+        chosen[lay["mode"]] = chosen.get(lay["mode"], 0) + 1
+    med = lambda v: float(np.median(v)) if v else None
+    search = {"chosen": chosen,
+              "median_ns_per_lookup": {"own": med([l["own_ns"] for l in layouts if l["own_ns"] > 0]),
+                                       "chosen": med([l["chosen_ns"] for l in layouts if l["chosen_ns"] > 0]),
+                                       "best_staged": med([l["staged_ns"] for l in layouts if l["staged_ns"] > 0])},
+              "all_staged_13_bits_ms": t_staged,
+              "note": "per basis the tuner times lookup sweeps of its own layout (hash index), bucket tables "
+                      "in global memory and bucket tables staged in LDS, and keeps the fastest"}
+    staged.close()
     return {"sectors": count, "nrhs": nrhs, "dtype": "c128", "dim_min": min(dims), "dim_max": max(dims),
             "dim_total": int(sum(dims)), "element_applications": elements,
             "batched_ms": t_batch, "plain_ms": t_plain, "speedup": t_plain / t_batch,
@@ -252,6 +271,7 @@ def batched_vs_plain(count: int, nrhs: int, reps_timed: int = 3):
             "batched_elements_per_s": elements / (t_batch * 1e-3),
             "plain_elements_per_s": elements / (t_plain * 1e-3),
             "identical_results": bool(same), "launches_batched": batch.info()["launches"],
+            "search_layout": search,
             "launches_plain": count * nrhs, "launches_plain_multi_rhs": count, "basis_build_s": build_s,
             "note": "plain: one single-column ls_matvec per sector and column; plain_multi_rhs: one "
                     f"{nrhs}-column ls_matvec per sector (the columns share each orbit search, as in the batch)"}

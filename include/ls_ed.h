@@ -308,9 +308,13 @@ ls_status ls_matvec_push(const ls_operator *op, uint32_t nrhs, const void *d_x, 
  * the launch sequence is captured in a HIP graph and replayed.
  * On the first ls_batch_matvec the library tunes, per variant, the tile size
  * and grid size (timing candidates on the caller's buffers; y is written
- * during tuning) and, for a basis that uses the bucket search layout, the
- * bucket bits of a batch-owned copy of it (hash layouts are used as built);
- * the choices are cached per process.  Elements are always generated (a
+ * during tuning) and, per basis, the search layout (stateToIndex, Section
+ * 5.3): the fastest by a timed lookup sweep of the basis's own layout (hash
+ * index or bucket search), bucket tables of several sizes over the keys'
+ * high bits searched in global memory, and bucket tables staged in LDS by
+ * every workgroup (the prefix-bucketed search of the sorted representatives
+ * with its first level in LDS), owned by the batch; the choices are cached
+ * per process.  Elements are always generated (a
  * stored form is not used); results equal ls_matvec's bit for bit.  The
  * batch borrows the operators, which must outlive it.                       */
 typedef struct ls_batch ls_batch;
@@ -329,6 +333,29 @@ ls_status ls_batch_matvec(ls_batch *batch, const void *const *d_x, void *const *
 /* Launches per call (one per variant and column width), tiles, and whether
  * a captured graph is in use.  Any output may be NULL.                     */
 ls_status ls_batch_info(const ls_batch *batch, uint32_t *n_launches, uint32_t *n_tiles, uint32_t *graph);
+
+/* The search layout the batch uses for operator `item` (valid after the
+ * first ls_batch_matvec; before it, or for a basis without a search, the
+ * basis's own layout with zero times):
+ *   mode       0 bucket search in global memory, 1 colex rank, 2 identity,
+ *              3 hash index, 4 bucket table staged in LDS;
+ *   bits       bucket bits (modes 0 and 4);
+ *   own_ns     lookup sweep time per key of the basis's own layout;
+ *   chosen_ns  the same for the chosen layout;
+ *   staged_ns  the best staged candidate's (0 when none fit in LDS).
+ * Any output may be NULL.  Errors: LS_EINVAL for item >= n.               */
+ls_status ls_batch_search(const ls_batch *batch, uint32_t item, uint32_t *mode, uint32_t *bits, double *own_ns,
+                          double *chosen_ns, double *staged_ns);
+
+/* Fixes the search layout of every basis of the batch instead of tuning it,
+ * before the first ls_batch_matvec: mode -1 tunes (default), 0 a bucket
+ * table of 2^bits buckets in global memory (bits 1..30), 3 each basis's own
+ * layout, 4 a bucket table of 2^bits buckets staged in LDS (bits 1..13).
+ * Bases without a search (colex rank, identity) keep theirs.  Errors:
+ * LS_EINVAL for other values or after the first product; a staged table
+ * that does not fit in LDS beside a job's tables fails the first
+ * ls_batch_matvec with LS_EINVAL.                                          */
+ls_status ls_batch_set_search(ls_batch *batch, int mode, uint32_t bits);
 
 /* Turns graph capture on (default) or off (direct launches) before the
  * first ls_batch_matvec.                                                   */

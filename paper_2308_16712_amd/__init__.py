@@ -17,9 +17,10 @@ from ._lib import (EXPORTS, LIB_PATH, LSError, Basis, Batch, Operator, Solver, l
                    sector_count)  # noqa: F401
 
 
-def ls_batch_create(ops, nrhs, graph: bool = True) -> Batch:
-    """Many products in one persistent launch per kernel variant."""
-    return Batch(ops, nrhs, graph)
+def ls_batch_create(ops, nrhs, graph: bool = True, search=None) -> Batch:
+    """Many products in one persistent launch per kernel variant; `search`
+    fixes the search layout instead of tuning it (ls_batch_set_search)."""
+    return Batch(ops, nrhs, graph, search)
 
 
 def ls_batch_matvec(batch: Batch, xs, ys, stream=None):

@@ -23,7 +23,9 @@ EXPORTS = ["ls_sector_check", "ls_sector_count", "ls_sector_count_noalloc", "ls_
            "ls_index_lookup", "ls_operator_create", "ls_operator_destroy", "ls_operator_info",
            "ls_operator_count", "ls_operator_store", "ls_operator_search_kind", "ls_operator_check",
            "ls_basis_test_drop_key", "ls_matvec", "ls_matvec_push",
-           "ls_batch_create", "ls_batch_matvec", "ls_batch_info", "ls_batch_set_graph", "ls_batch_destroy",
+           "ls_batch_create", "ls_batch_matvec", "ls_batch_info", "ls_batch_search", "ls_batch_set_search",
+           "ls_batch_set_graph",
+           "ls_batch_destroy",
            "ls_lanczos", "ls_solver_footprint", "ls_solver_create", "ls_solver_step", "ls_solver_result",
            "ls_solver_destroy", "ls_last_error", "ls_version"]
 
@@ -87,6 +89,8 @@ def load(path: str = LIB_PATH):
         "ls_batch_create": ([u32, P, P, P], i32),
         "ls_batch_matvec": ([P, P, P, P], i32),
         "ls_batch_info": ([P, P, P, P], i32),
+        "ls_batch_search": ([P, ctypes.c_uint32, P, P, P, P, P], i32),
+        "ls_batch_set_search": ([P, ctypes.c_int, ctypes.c_uint32], i32),
         "ls_batch_set_graph": ([P, ctypes.c_int], i32),
         "ls_batch_destroy": ([P], None),
         "ls_lanczos": ([P, P, P, P, P, P], i32),
@@ -467,7 +471,7 @@ class Batch:
     with its own number of right-hand sides, in one persistent launch per
     kernel variant, replayed from a HIP graph."""
 
-    def __init__(self, ops, nrhs, graph: bool = True):
+    def __init__(self, ops, nrhs, graph: bool = True, search=None):
         L = load()
         self.ops = list(ops)
         self.nrhs = [int(v) for v in nrhs]
@@ -481,6 +485,11 @@ class Batch:
         self._h = h
         if not graph:
             _check(L.ls_batch_set_graph(h, 0))
+        if search is not None:
+            # ("buckets", bits), ("staged", bits) or "own": ls_batch_set_search
+            mode, bits = (search, 0) if isinstance(search, str) else search
+            code = {"buckets": 0, "own": 3, "staged": 4}[mode]
+            _check(L.ls_batch_set_search(h, code, int(bits)))
 
     def matvec(self, xs, ys, stream=None):
         """ys[k] = H_k xs[k] for every k (torch tensors [dim_k][nrhs_k])."""
@@ -500,6 +509,18 @@ class Batch:
         a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
         _check(load().ls_batch_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return dict(launches=a.value, tiles=b.value, graph=bool(c.value))
+
+    SEARCH_MODES = {0: "buckets", 1: "rank", 2: "identity", 3: "hash", 4: "staged"}
+
+    def search(self, item: int) -> dict:
+        """Search layout used for operator `item` and the lookup sweep times
+        behind the choice (ls_batch_search)."""
+        m, b = ctypes.c_uint32(), ctypes.c_uint32()
+        o, c, s = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(load().ls_batch_search(self._h, int(item), ctypes.byref(m), ctypes.byref(b), ctypes.byref(o),
+                                      ctypes.byref(c), ctypes.byref(s)))
+        return dict(mode=self.SEARCH_MODES.get(m.value, str(m.value)), bits=b.value, own_ns=o.value,
+                    chosen_ns=c.value, staged_ns=s.value)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -367,6 +367,23 @@ ls_status ls_batch_info(const ls_batch *batch, uint32_t *n_launches, uint32_t *n
     });
 }
 
+ls_status ls_batch_search(const ls_batch *batch, uint32_t item, uint32_t *mode, uint32_t *bits, double *own_ns,
+                          double *chosen_ns, double *staged_ns) {
+    return guarded([&] {
+        LS_REQUIRE(batch != nullptr, "batch must not be NULL");
+        ls::batch_search(batch, item, mode, bits, own_ns, chosen_ns, staged_ns);
+        return LS_OK;
+    });
+}
+
+ls_status ls_batch_set_search(ls_batch *batch, int mode, uint32_t bits) {
+    return guarded([&] {
+        LS_REQUIRE(batch != nullptr, "batch must not be NULL");
+        ls::batch_set_search(batch, mode, bits);
+        return LS_OK;
+    });
+}
+
 ls_status ls_batch_set_graph(ls_batch *batch, int enabled) {
     return guarded([&] {
         LS_REQUIRE(batch != nullptr, "batch must not be NULL");

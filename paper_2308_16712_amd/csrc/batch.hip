@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(batch_block(KIND, CPLX))
             __syncthreads();
             cur = jid;
         }
-        run_rows<W, KIND, CHI, CPLX, NR, LX, LY, NZ>(a, L, T.row0 + threadIdx.x, BLOCK, rpl);
+        run_rows<W, KIND, CHI, CPLX, NR, LX, LY, NZ, true>(a, L, T.row0 + threadIdx.x, BLOCK, rpl);
     }
 }
 
@@ -91,15 +91,34 @@ __global__ void k_buckets_tuned(const uint64_t *reps, uint64_t d, uint64_t kmin,
 constexpr int nr_cap(bool word64, int kind) { return kind != kOrbitTorus ? 8 : word64 ? 1 : 2; }
 int batch_nr_cap(const Variant &v) { return nr_cap(v.word64 != 0, v.kind); }
 
-// Lookup sweep used to time a search layout: keys are representatives taken
-// in a scattered order; the sum of indices defeats dead-code elimination.
-__global__ void k_lookup_sweep(SearchDev S, uint64_t n, uint64_t magic, uint64_t *sink) {
-    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (i >= n) return;
-    const uint64_t j = (i * 0x9E3779B97F4A7C15ULL) % S.dim;
-    const int64_t idx = lookup_index(S, S.reps[j]);
-    // magic is a value no index takes; the store keeps the lookup live
-    if (static_cast<uint64_t>(idx) == magic) *sink = j;
+// Lookup sweep used to time a search layout, in the shape of the batched
+// launch (a persistent grid of 1024-thread workgroups, each staging a staged
+// layout's bucket table once): keys are representatives taken in a scattered
+// order, and every lookup also yields the stabilizer size, as in a product.
+constexpr int kSweepBlock = 1024;
+__global__ void __launch_bounds__(kSweepBlock)
+    k_lookup_sweep(SearchDev S, const uint16_t *stab, uint64_t n, uint64_t magic, uint64_t *sink) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *lb = reinterpret_cast<uint32_t *>(smem);
+    if (S.mode == kLookupStaged) {
+        for (uint32_t q = threadIdx.x; q < S.n_bkt; q += kSweepBlock) lb[q] = S.buckets[q];
+        __syncthreads();
+    }
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kSweepBlock;
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kSweepBlock + threadIdx.x; i < n; i += stride) {
+        const uint64_t j = __umul64hi(i * 0x9E3779B97F4A7C15ULL, S.dim);
+        const uint64_t key = S.reps[j];
+        uint32_t st = 0;
+        int64_t idx;
+        if (S.mode == kLookupStaged) {
+            idx = lookup_staged(S, lb, key);
+            if (idx >= 0) st = stab[idx];
+        } else {
+            idx = lookup_index_stab(S, key, stab, st);
+        }
+        // magic is a value no sum takes; the store keeps the lookup live
+        if (static_cast<uint64_t>(idx) + st == magic) *sink = j;
+    }
 }
 
 struct Group {
@@ -163,7 +182,9 @@ void upload_jobs(Group &g, hipStream_t st) {
 using TuneKey = std::tuple<int, int, int, uint32_t, uint32_t, int, int, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<uint32_t, uint32_t>> g_tune_cache;   // -> (rpl, workgroups per CU)
-std::map<std::tuple<uint64_t, uint64_t, uint64_t>, uint32_t> g_bits_cache;   // (dim, kmin, kmax) -> bits
+// (dim, kmin, kmax, LDS free) -> (mode, bits, own, chosen, best staged ns per lookup)
+std::map<std::tuple<uint64_t, uint64_t, uint64_t, uint64_t>, std::tuple<uint32_t, uint32_t, double, double, double>>
+    g_search_cache;
 
 TuneKey tune_key(const Group &g) {
     uint64_t rows = 0;
@@ -236,6 +257,15 @@ void tune_group(Group &g, hipStream_t st, int n_cu) {
 
 }  // namespace ls
 
+namespace ls {
+// A batch's search layout for one basis and the lookup sweep times behind
+// the choice (ns per lookup; 0 when no sweep ran).
+struct SearchChoice {
+    SearchDev S;
+    double own_ns = 0.0, chosen_ns = 0.0, staged_ns = 0.0;
+};
+}  // namespace ls
+
 struct ls_batch {
     std::vector<const ls_operator *> ops;
     std::vector<uint32_t> nrhs;
@@ -243,11 +273,13 @@ struct ls_batch {
     std::vector<const void *> cur_x;
     std::vector<void *> cur_y;
     std::vector<uint32_t *> own_buckets;     // tuned search layouts (one per basis)
-    std::vector<ls::SearchDev> search;       // per item
+    std::vector<ls::SearchChoice> search;    // per item
     hipStream_t cap = nullptr;               // stream used for graph capture
     ls::StreamSet used;                      // streams of its products
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int force_mode = -1;                     // ls_batch_set_search (-1: tune)
+    uint32_t force_bits = 0;
     bool use_graph = true;
     bool ready = false;
     int n_cu = 256;
@@ -257,73 +289,127 @@ namespace ls {
 
 namespace {
 
-// Tune the bucket bits of one basis by timing lookup sweeps; returns a
-// batch-owned search layout (or the basis's own when it is not a search).
-SearchDev tuned_search(ls_batch *B, const ls_basis *b, hipStream_t st) {
-    SearchDev S = b->search_dev;
-    if (S.mode != kLookupSearch || b->dim < 4096) return S;
-    const auto key = std::make_tuple(b->dim, S.kmin, S.kmax);
-    uint32_t bits = 0;
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_bits_cache.find(key);
-        if (it != g_bits_cache.end()) bits = it->second;
-    }
-    const uint64_t range = S.kmax - S.kmin;
+// A bucket table of 2^nbits buckets over the keys' range of basis b (the
+// build's bucket rule), in a batch-owned allocation *out.
+SearchDev bucket_layout(const ls_basis *b, uint32_t mode, uint32_t nbits, uint32_t **out, hipStream_t st) {
+    SearchDev T = b->search_dev;
+    const uint64_t range = T.kmax - T.kmin;
     uint32_t len = 0;
     while (len < 64 && (range >> len) != 0) ++len;
-    auto build = [&](uint32_t nbits, uint32_t **out, uint32_t *shift) {
-        *shift = len > nbits ? len - nbits : 0;
-        const uint64_t nb = (range >> *shift) + 1;
-        *out = dev_alloc_n<uint32_t>(nb + 1, st);
-        hipLaunchKernelGGL(k_buckets_tuned, dim3(static_cast<uint32_t>((nb + 1 + 255) / 256)), dim3(256), 0, st,
-                           b->d_reps, b->dim, S.kmin, *shift, nb, *out);
-        LS_HIP_CHECK(hipGetLastError());
-    };
-    if (bits == 0) {
+    T.mode = mode;
+    T.bits = nbits;
+    T.shift = len > nbits ? len - nbits : 0;
+    const uint64_t nb = (range >> T.shift) + 1;
+    *out = dev_alloc_n<uint32_t>(nb + 1, st);
+    hipLaunchKernelGGL(k_buckets_tuned, dim3(static_cast<uint32_t>((nb + 1 + 255) / 256)), dim3(256), 0, st,
+                       b->d_reps, b->dim, T.kmin, T.shift, nb, *out);
+    LS_HIP_CHECK(hipGetLastError());
+    T.buckets = *out;
+    T.n_bkt = static_cast<uint32_t>(nb + 1);
+    return T;
+}
+
+bool staged_fits(uint32_t nbits, size_t lds_free) {
+    return nbits <= kMaxStagedBits && ((1ULL << nbits) + 2) * sizeof(uint32_t) <= lds_free;
+}
+
+// Search layout of one basis for the batch: the fastest, by a timed lookup
+// sweep, of the basis's own layout (hash index or bucket search, as built),
+// bucket tables of several sizes read from global memory, and bucket tables
+// staged in LDS (when they fit beside the jobs' own LDS tables: lds_free
+// bytes); or the layout ls_batch_set_search forced.  The batch owns the
+// tables it builds; the basis is not modified.  Tuning results are cached
+// per process by (dim, kmin, kmax, lds_free).
+SearchChoice tuned_search(ls_batch *B, const ls_basis *b, size_t lds_free, hipStream_t st) {
+    SearchChoice C;
+    C.S = b->search_dev;
+    const SearchDev &own = b->search_dev;
+    if (own.mode != kLookupSearch && own.mode != kLookupHash) return C;
+    if (B->force_mode >= 0) {
+        if (B->force_mode == static_cast<int>(kLookupHash)) return C;   // the basis's own
+        const uint32_t mode = static_cast<uint32_t>(B->force_mode);
+        if (mode == kLookupStaged && !staged_fits(B->force_bits, lds_free))
+            throw Error{LS_EINVAL, "the forced staged bucket table does not fit in LDS beside the jobs' tables"};
+        uint32_t *tab = nullptr;
+        C.S = bucket_layout(b, mode, B->force_bits, &tab, st);
+        B->own_buckets.push_back(tab);
+        return C;
+    }
+    if (b->dim < 4096) return C;
+    const auto key = std::make_tuple(b->dim, own.kmin, own.kmax, static_cast<uint64_t>(lds_free));
+    auto table = [&](uint32_t mode, uint32_t nbits, uint32_t **out) { return bucket_layout(b, mode, nbits, out, st); };
+    std::tuple<uint32_t, uint32_t, double, double, double> pick;   // mode, bits, own, chosen, staged (ns/key)
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_search_cache.find(key);
+        if (it != g_search_cache.end()) {
+            pick = it->second;
+            cached = true;
+        }
+    }
+    if (!cached) {
+        // candidates: the basis's own layout, then (mode, bits) tables around
+        // the build rule of about 4 keys per bucket
+        uint32_t b0 = 8;
+        while (b0 < 22 && (1ULL << b0) * 4 < b->dim) ++b0;
+        std::vector<std::pair<uint32_t, uint32_t>> cands = {{own.mode, own.mode == kLookupSearch ? own.bits : 0u}};
+        for (int d : {-2, 0, 2}) {
+            const int nb = static_cast<int>(b0) + d;
+            if (nb >= 8 && nb <= 24 && !(own.mode == kLookupSearch && static_cast<uint32_t>(nb) == own.bits))
+                cands.push_back({kLookupSearch, static_cast<uint32_t>(nb)});
+        }
+        const uint32_t sb = std::min(b0, kMaxStagedBits);
+        for (uint32_t nb : {sb, sb - 2})
+            if (nb >= 8 && staged_fits(nb, lds_free)) cands.push_back({kLookupStaged, nb});
         uint64_t *sink = dev_alloc_n<uint64_t>(1, st);
         hipEvent_t e0, e1;
         LS_HIP_CHECK(hipEventCreate(&e0));
         LS_HIP_CHECK(hipEventCreate(&e1));
-        float best = 1e30f;
         const uint64_t n = std::min<uint64_t>(b->dim, 1u << 22);
-        for (int d = -4; d <= 4; d += 2) {
-            const int cand = static_cast<int>(S.bits) + d;
-            if (cand < 8 || cand > 24) continue;
-            uint32_t *tab = nullptr, shift = 0;
-            build(static_cast<uint32_t>(cand), &tab, &shift);
-            SearchDev T = S;
-            T.bits = static_cast<uint32_t>(cand);
-            T.shift = shift;
-            T.buckets = tab;
-            hipLaunchKernelGGL(k_lookup_sweep, dim3(static_cast<uint32_t>((n + 255) / 256)), dim3(256), 0, st, T, n,
-                               ~0ULL - 1, sink);
-            LS_HIP_CHECK(hipEventRecord(e0, st));
-            hipLaunchKernelGGL(k_lookup_sweep, dim3(static_cast<uint32_t>((n + 255) / 256)), dim3(256), 0, st, T, n,
-                               ~0ULL - 1, sink);
+        const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(
+            static_cast<uint64_t>(B->n_cu) * 2, (n + kSweepBlock - 1) / kSweepBlock));
+        double best = 1e30, own_ns = 0.0, staged_ns = 0.0;
+        uint32_t best_mode = own.mode, best_bits = cands[0].second;
+        for (size_t c = 0; c < cands.size(); ++c) {
+            uint32_t *tab = nullptr;
+            const SearchDev T = c == 0 ? own : table(cands[c].first, cands[c].second, &tab);
+            const size_t lds = T.mode == kLookupStaged ? static_cast<size_t>(T.n_bkt) * sizeof(uint32_t) : 0;
+            for (int rep = 0; rep < 2; ++rep) {   // warm, then timed
+                if (rep == 1) LS_HIP_CHECK(hipEventRecord(e0, st));
+                hipLaunchKernelGGL(k_lookup_sweep, dim3(grid), dim3(kSweepBlock), lds, st, T, b->d_stab, n,
+                                   ~0ULL - 1, sink);
+            }
             LS_HIP_CHECK(hipEventRecord(e1, st));
             LS_HIP_CHECK(hipEventSynchronize(e1));
             float ms = 0.f;
             LS_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
-            dev_free(tab, st);
-            if (ms < best) {
-                best = ms;
-                bits = static_cast<uint32_t>(cand);
+            if (tab) dev_free(tab, st);
+            const double ns = static_cast<double>(ms) * 1e6 / static_cast<double>(n);
+            if (c == 0) own_ns = ns;
+            if (cands[c].first == kLookupStaged && (staged_ns == 0.0 || ns < staged_ns)) staged_ns = ns;
+            if (ns < best) {
+                best = ns;
+                best_mode = cands[c].first;
+                best_bits = cands[c].second;
             }
         }
         hipEventDestroy(e0);
         hipEventDestroy(e1);
         dev_free(sink, st);
+        pick = std::make_tuple(best_mode, best_bits, own_ns, best, staged_ns);
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_bits_cache[key] = bits;
+        g_search_cache[key] = pick;
     }
-    uint32_t *tab = nullptr, shift = 0;
-    build(bits, &tab, &shift);
+    C.own_ns = std::get<2>(pick);
+    C.chosen_ns = std::get<3>(pick);
+    C.staged_ns = std::get<4>(pick);
+    const uint32_t mode = std::get<0>(pick), nbits = std::get<1>(pick);
+    if (mode == own.mode && (mode == kLookupHash || nbits == own.bits)) return C;   // the basis's own
+    uint32_t *tab = nullptr;
+    C.S = table(mode, nbits, &tab);
     B->own_buckets.push_back(tab);
-    S.bits = bits;
-    S.shift = shift;
-    S.buckets = tab;
-    return S;
+    return C;
 }
 
 void free_batch(ls_batch *B) {
@@ -371,13 +457,25 @@ void batch_destroy(ls_batch *B) { free_batch(B); }
 // First call: search layouts, grouping, tiles, tuning; later calls reuse them.
 static void batch_prepare(ls_batch *B, hipStream_t st) {
     const uint32_t n = static_cast<uint32_t>(B->ops.size());
-    // one tuned search layout per distinct basis
-    std::map<const ls_basis *, SearchDev> by_basis;
+    // one tuned search layout per distinct basis; a staged bucket table must
+    // fit beside the LDS tables of every job on that basis
+    std::map<const ls_basis *, size_t> lds_free;
+    for (uint32_t i = 0; i < n; ++i) {
+        const ls_operator *op = B->ops[i];
+        const int kind = variant_of(op).kind;
+        const size_t own = lds_bytes(kind, op->n_diag + op->n_off, op->n_off, op->basis->plan.lx) +
+                           (kind == kOrbitTorus ? kPairTableBytes : 0);
+        const size_t fr = own + 16 <= kMaxLds ? kMaxLds - own - 16 : 0;
+        auto it = lds_free.find(op->basis);
+        if (it == lds_free.end()) lds_free.emplace(op->basis, fr);
+        else it->second = std::min(it->second, fr);
+    }
+    std::map<const ls_basis *, SearchChoice> by_basis;
     B->search.resize(n);
     for (uint32_t i = 0; i < n; ++i) {
         const ls_basis *b = B->ops[i]->basis;
         auto it = by_basis.find(b);
-        if (it == by_basis.end()) it = by_basis.emplace(b, tuned_search(B, b, st)).first;
+        if (it == by_basis.end()) it = by_basis.emplace(b, tuned_search(B, b, lds_free[b], st)).first;
         B->search[i] = it->second;
     }
     for (uint32_t i = 0; i < n; ++i) {
@@ -397,12 +495,14 @@ static void batch_prepare(ls_batch *B, hipStream_t st) {
                 g->nr = nr;
             }
             MatvecJob j = job_of(op, B->cur_x[i], B->cur_y[i], B->nrhs[i], col);
-            j.search = B->search[i];
+            j.search = B->search[i].S;
             g->jobs.push_back(j);
             g->item_col.push_back({i, col});
             const double nterm = static_cast<double>(op->n_off) + 1.0;
             g->cost.push_back(static_cast<double>(op->basis->dim) * nterm * op->basis->plan.n_elements);
-            g->lds = std::max(g->lds, lds_bytes(v.kind, op->n_diag + op->n_off, op->n_off, op->basis->plan.lx));
+            size_t lds = lds_bytes(v.kind, op->n_diag + op->n_off, op->n_off, op->basis->plan.lx);
+            if (j.search.mode == kLookupStaged) lds += static_cast<size_t>(j.search.n_bkt) * sizeof(uint32_t);
+            g->lds = std::max(g->lds, lds);
             col += static_cast<uint32_t>(nr);
         }
     }
@@ -482,6 +582,31 @@ void batch_info(const ls_batch *B, uint32_t *n_launches, uint32_t *n_tiles, uint
 }
 
 void batch_set_graph(ls_batch *B, bool on) { B->use_graph = on; }
+
+void batch_set_search(ls_batch *B, int mode, uint32_t bits) {
+    LS_REQUIRE(!B->ready, "the search layout is fixed by the first ls_batch_matvec");
+    LS_REQUIRE(mode == -1 || mode == static_cast<int>(kLookupSearch) || mode == static_cast<int>(kLookupHash) ||
+                   mode == static_cast<int>(kLookupStaged),
+               "mode must be -1 (tune), 0 (buckets), 3 (the basis's own) or 4 (staged)");
+    if (mode == static_cast<int>(kLookupSearch) || mode == static_cast<int>(kLookupStaged))
+        LS_REQUIRE(bits >= 1 && bits <= (mode == static_cast<int>(kLookupStaged) ? kMaxStagedBits : 30u),
+                   "bucket bits out of range (1..30, staged 1..13)");
+    B->force_mode = mode;
+    B->force_bits = bits;
+}
+
+void batch_search(const ls_batch *B, uint32_t item, uint32_t *mode, uint32_t *bits, double *own_ns, double *chosen_ns,
+                  double *staged_ns) {
+    LS_REQUIRE(item < B->ops.size(), "item must be below the number of operators");
+    SearchChoice C;
+    if (item < B->search.size()) C = B->search[item];
+    else C.S = B->ops[item]->basis->search_dev;
+    if (mode) *mode = C.S.mode;
+    if (bits) *bits = (C.S.mode == kLookupSearch || C.S.mode == kLookupStaged) ? C.S.bits : 0u;
+    if (own_ns) *own_ns = C.own_ns;
+    if (chosen_ns) *chosen_ns = C.chosen_ns;
+    if (staged_ns) *staged_ns = C.staged_ns;
+}
 
 // ---- fused products for the Lanczos stepper --------------------------------
 //

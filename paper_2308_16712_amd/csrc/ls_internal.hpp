@@ -134,7 +134,17 @@ struct PlanDev {
     uint64_t col_ge[8];
 };
 
-enum LookupMode : uint32_t { kLookupSearch = 0, kLookupRank = 1, kLookupIdentity = 2, kLookupHash = 3 };
+// kLookupStaged: the bucket search with its bucket table staged in LDS by
+// every workgroup (a layout the batched launch may pick; never built by a
+// basis itself).
+enum LookupMode : uint32_t {
+    kLookupSearch = 0,
+    kLookupRank = 1,
+    kLookupIdentity = 2,
+    kLookupHash = 3,
+    kLookupStaged = 4
+};
+constexpr uint32_t kMaxStagedBits = 13;   // staged tables: at most 2^13 + 1 entries (32 KiB)
 
 // One slot of the hash index: a representative, its position in the sorted
 // array and its stabilizer size, read with one 16-byte load.
@@ -152,6 +162,7 @@ struct SearchDev {
     int32_t weight;     // for rank / identity validation
     uint32_t n_sites;
     uint32_t hash_shift;        // slot = (key * golden) >> hash_shift (hash mode)
+    uint32_t n_bkt;             // entries of the bucket table (staged mode)
     uint64_t dim;
     uint64_t kmin, kmax;
     const uint64_t *reps;       // device [dim]
@@ -272,6 +283,9 @@ void batch_destroy(ls_batch *b);
 void batch_matvec(ls_batch *b, const void *const *xs, void *const *ys, hipStream_t stream);
 void batch_info(const ls_batch *b, uint32_t *n_launches, uint32_t *n_tiles, uint32_t *graph);
 void batch_set_graph(ls_batch *b, bool on);
+void batch_set_search(ls_batch *b, int mode, uint32_t bits);
+void batch_search(const ls_batch *b, uint32_t item, uint32_t *mode, uint32_t *bits, double *own_ns, double *chosen_ns,
+                  double *staged_ns);
 
 // fused products over a changing set of operators (batch.hip)
 struct FusedState;

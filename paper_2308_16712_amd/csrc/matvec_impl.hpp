@@ -123,8 +123,8 @@ __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~size
 // col_ge | flip images (torus only) | terms.
 constexpr uint32_t kPairTableEntries = 1u << 12;   // 4^lx for lx <= 6
 
-// Dynamic LDS bytes of a launch.
-inline size_t lds_bytes(int kind, uint32_t n_terms, uint32_t n_off, uint32_t lx) {
+// Dynamic LDS bytes of a launch (a staged bucket table goes after them).
+__host__ __device__ inline size_t lds_bytes(int kind, uint32_t n_terms, uint32_t n_off, uint32_t lx) {
     (void)lx;
     size_t b = align16((n_terms > 0 ? n_terms : 1) * sizeof(ls_term_dev));
     if (kind == kOrbitTorus) b += 64 + static_cast<size_t>(n_off) * kTorusCosetSlots * sizeof(uint64_t);
@@ -139,6 +139,7 @@ struct LdsTables {
     uint32_t *lut;
     uint64_t *col;
     uint64_t *cflip;   // [slot][n_off]
+    uint32_t *bkt;     // staged bucket table (kLookupStaged)
 };
 
 template <int KIND, uint32_t LX, int BLOCK>
@@ -157,6 +158,7 @@ __device__ __forceinline__ LdsTables lds_tables(const MatvecJob &a, unsigned cha
         L.cflip = nullptr;
         L.terms = reinterpret_cast<ls_term_dev *>(smem);
     }
+    L.bkt = reinterpret_cast<uint32_t *>(smem + lds_bytes(KIND, a.n_terms, a.n_terms - a.n_diag, LX));
     return L;
 }
 
@@ -174,6 +176,8 @@ __device__ __forceinline__ void stage_tables(const MatvecJob &a, const LdsTables
             L.cflip[p * n_off + k] = a.cflip[q];   // transposed: lanes spread over banks
         }
     }
+    if (a.search.mode == kLookupStaged)
+        for (uint32_t q = threadIdx.x; q < a.search.n_bkt; q += BLOCK) L.bkt[q] = a.search.buckets[q];
 }
 
 // Sum of the diagonal terms acting on r: dre + i dim_.
@@ -236,13 +240,26 @@ __device__ __forceinline__ void lookup_miss(const MatvecJob &a, W rep) {
     atomicOr(a.err, 1u);
 }
 
+// stateToIndex of a neighbour with its stabilizer size, in the job's layout.
+template <bool STAGED>
+__device__ __forceinline__ int64_t lookup_stab(const MatvecJob &a, const LdsTables &L, uint64_t key, uint32_t &st) {
+    if constexpr (STAGED) {
+        if (a.search.mode == kLookupStaged) {
+            const int64_t j = lookup_staged(a.search, L.bkt, key);
+            if (j >= 0) st = a.stab[j];
+            return j;
+        }
+    }
+    return lookup_index_stab(a.search, key, a.stab, st);
+}
+
 // Rows as run_rows, for the searches that are cheap next to the memory
 // latency of the lookup (rings and the generic walk): the element loop is
 // software-pipelined one element deep.  An iteration searches element e+1 and
 // issues the load of its home hash slot, then finishes element e, whose slot
 // load was issued one search earlier.  Elements are still accumulated one by
 // one in term order, so the sums (and their bits) are those of run_rows.
-template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
+template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ, bool STAGED>
 __device__ __forceinline__ void run_rows_ahead(const MatvecJob &a, const LdsTables &L, uint64_t row0,
                                                uint64_t step, uint32_t count) {
     constexpr bool TRACK = CHI != kChiTrivial;
@@ -324,7 +341,7 @@ __device__ __forceinline__ void run_rows_ahead(const MatvecJob &a, const LdsTabl
                     e = *reinterpret_cast<const uint4 *>(S.table + sl);
                 }
             } else {
-                j = lookup_index_stab(S, p_rep, a.stab, st_j);
+                j = lookup_stab<STAGED>(a, L, p_rep, st_j);
             }
             if (j >= 0) {
                 const T c = element_value<CHI, CPLX>(sterm[p_t], r, st_j, st_i, a.plan, p_code);
@@ -355,13 +372,16 @@ __device__ __forceinline__ void run_rows_ahead(const MatvecJob &a, const LdsTabl
 }
 
 // Rows row0, row0 + step, ... (count of them, below dim) of one job.
-template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
+// STAGED: the job's search layout may be a bucket table staged in LDS (the
+// batched launch); the other launches never meet one.
+template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ,
+          bool STAGED = false>
 __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L, uint64_t row0, uint64_t step,
                                          uint32_t count) {
     // the pipelined loop pays off where one or two columns leave registers
     // for the element in flight; wider products keep the plain loop
     if constexpr (KIND != kOrbitTorus && NR <= 2) {
-        run_rows_ahead<W, KIND, CHI, CPLX, NR, LX, LY, NZ>(a, L, row0, step, count);
+        run_rows_ahead<W, KIND, CHI, CPLX, NR, LX, LY, NZ, STAGED>(a, L, row0, step, count);
         return;
     }
     constexpr bool TRACK = CHI != kChiTrivial;
@@ -408,7 +428,7 @@ __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L,
         const W rep = neighbour_rep<W, KIND, TRACK, LX, LY, NZ>(a, L, r, pr, t, code);
         ++t;
         uint32_t st_j = 0;
-        const int64_t j = lookup_index_stab(a.search, static_cast<uint64_t>(rep), a.stab, st_j);
+        const int64_t j = lookup_stab<STAGED>(a, L, static_cast<uint64_t>(rep), st_j);
         if (j < 0) {
             lookup_miss<W, KIND, CHI>(a, rep);
             continue;

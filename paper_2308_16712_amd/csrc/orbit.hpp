@@ -534,6 +534,16 @@ __device__ __forceinline__ int64_t lookup_hash(const SearchDev &S, uint64_t key,
     }
 }
 
+// Binary search for key among reps[lo, end) (one bucket of the sorted array).
+__device__ __forceinline__ int64_t search_bucket(const uint64_t *reps, uint32_t lo, uint32_t end, uint64_t key) {
+    uint32_t hi = end;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (reps[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return (lo < end && reps[lo] == key) ? static_cast<int64_t>(lo) : -1;
+}
+
 // stateToIndex: hash index, or bucket of the key's high bits then binary
 // search, or the colex rank (U(1) without lattice symmetry).
 __device__ __forceinline__ int64_t lookup_index(const SearchDev &S, uint64_t key) {
@@ -550,14 +560,16 @@ __device__ __forceinline__ int64_t lookup_index(const SearchDev &S, uint64_t key
     }
     if (key < S.kmin || key > S.kmax) return -1;
     const uint64_t b = (key - S.kmin) >> S.shift;
-    uint32_t lo = S.buckets[b];
-    const uint32_t end = S.buckets[b + 1];
-    uint32_t hi = end;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (S.reps[mid] < key) lo = mid + 1; else hi = mid;
-    }
-    return (lo < end && S.reps[lo] == key) ? static_cast<int64_t>(lo) : -1;
+    return search_bucket(S.reps, S.buckets[b], S.buckets[b + 1], key);
+}
+
+// The bucket search with the bucket table staged in LDS (lb, S.n_bkt
+// entries): the bucket's bounds are LDS reads, only the search inside the
+// bucket reads reps.
+__device__ __forceinline__ int64_t lookup_staged(const SearchDev &S, const uint32_t *lb, uint64_t key) {
+    if (key < S.kmin || key > S.kmax) return -1;
+    const uint32_t b = static_cast<uint32_t>((key - S.kmin) >> S.shift);
+    return search_bucket(S.reps, lb[b], lb[b + 1], key);
 }
 
 // Index and stabilizer size of a key (the hash index holds both in one slot).

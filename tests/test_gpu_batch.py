@@ -109,3 +109,62 @@ def test_batch_rejects_bad_input():
         batch.matvec([xs[0], xs[1]], [xs[0], ys[1]])   # y overlaps x
     with pytest.raises(ValueError):
         ls.Batch(ops, [1])
+
+
+@pytest.mark.parametrize("search", [("buckets", 6), ("buckets", 12), ("staged", 5), ("staged", 8), ("staged", 11),
+                                    "own"], ids=lambda s: s if isinstance(s, str) else f"{s[0]}{s[1]}")
+def test_batch_forced_search_layouts_equal_single_products(search):
+    """Every search layout the batch can use (bucket tables in global memory,
+    bucket tables staged in LDS, each basis's own) gives the single
+    products' bits: the layout changes how an index is found, not which."""
+    sectors = _mixed_sectors()
+    nrhs = [4, 1, 3, 2, 5, 1, 4, 8]
+    ops, xs, ys, refs = _setup(sectors, nrhs)
+    batch = ls.Batch(ops, nrhs, search=search)
+    batch.matvec(xs, ys)
+    torch.cuda.synchronize()
+    want_mode = search if isinstance(search, str) else search[0]
+    for k, (op, x, y, (sec, b, _)) in enumerate(zip(ops, xs, ys, refs)):
+        assert torch.equal(op.matvec(x), y), (sec.name, search)
+        got = batch.search(k)
+        own = op.search_kind()
+        if sec.name == "ring16_sz0_nosym":
+            assert got["mode"] == "rank"
+        elif want_mode == "own":
+            assert got["mode"] == "hash"
+        else:
+            assert got["mode"] == want_mode and got["bits"] == search[1], (sec.name, got, own)
+    for op in ops:
+        op.check()
+
+
+def test_batch_staged_table_too_large_for_lds_is_refused():
+    """A staged bucket table that does not fit beside the 6x6 torus jobs'
+    LDS tables (pair table, flip images, terms) is refused with LS_EINVAL."""
+    sec = _mixed_sectors()[6]
+    ops, xs, ys, _ = _setup([sec], [1])
+    batch = ls.Batch(ops, [1], search=("staged", 13))
+    with pytest.raises(ls.LSError) as e:
+        batch.matvec(xs, ys)
+    assert e.value.status == ls._lib.LS_EINVAL
+    with pytest.raises(ls.LSError):
+        ls.Batch(ops, [1], search=("staged", 14))
+
+
+def test_batch_tuner_picks_a_measured_layout():
+    """The tuner times the basis's own layout against global and staged
+    bucket tables and keeps the fastest; the choice and the times are
+    reported per operator, and the products stay bit-identical."""
+    sectors = _mixed_sectors()
+    nrhs = [1] * len(sectors)
+    ops, xs, ys, refs = _setup(sectors, nrhs)
+    batch = ls.Batch(ops, nrhs)
+    batch.matvec(xs, ys)
+    torch.cuda.synchronize()
+    for k, (op, x, y, (sec, b, _)) in enumerate(zip(ops, xs, ys, refs)):
+        assert torch.equal(op.matvec(x), y), sec.name
+        got = batch.search(k)
+        print(f"[gpu] tuner {sec.name} dim {b.dim}: {got}", flush=True)
+        assert got["mode"] in ("hash", "buckets", "staged", "rank")
+        if got["mode"] != "rank" and b.dim >= 4096:
+            assert got["own_ns"] > 0 and 0 < got["chosen_ns"] <= got["own_ns"]
