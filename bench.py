@@ -464,7 +464,7 @@ def stored_product(basis, sector, x, y, fly_ms: float, elements: int, n_off: int
     roof.update(counter_fields(counter_record("k_spmv", workload), ms, elements, alg))
     return {"bytes": nbytes, "store_s": store_s, "ms_per_product": ms, "elements_per_s": elements / (ms * 1e-3),
             "speedup_vs_on_the_fly": fly_ms / ms, "identical_to_on_the_fly": same, "roofline": roof,
-            "layout": "sliced ELLPACK, 64-row slices, uint32 column + value per slot"}
+            "layout": layout}
 
 
 def chain_products(ns, steps: int = 3):
@@ -709,7 +709,7 @@ def main():
             "algorithmic_model": f"{ALG_ROW_BYTES} B per row (representative, x_i, y_i) + {ALG_ELEMENT_BYTES} B "
                                  "per off-diagonal element (x_j, matched key)"}
     roof.update(counter_fields(counter_record("k_matvec", args.workload), kernel_ms, elements, alg_bytes))
-    # the exhaustive-search model of round one, kept under its own name: one
+    # the exhaustive-search model, kept under its own name: one
     # compare-select per group image and 32-bit word for every element
     words = (sector.n_sites + 31) // 32
     dense_ops = float(n_off) * sector.group.size * words

@@ -187,13 +187,16 @@ __global__ void __launch_bounds__(256) k_spmv(const uint64_t *off, const uint32_
     const uint32_t w = width[g];      // the same for the whole wavefront
     const uint64_t base = off[g] + (row & (kSlice - 1));
     auto value = [&](uint64_t slot) -> T {
-        if constexpr (CODED) return vtab[codes[slot]];
+        if constexpr (CODED) return vtab[__builtin_nontemporal_load(&codes[slot])];
         else return vals[slot];
     };
     // U elements per step: their columns, values and x gathers are all issued
     // before the first add, so U gathers per lane are in flight at once; the
-    // adds keep the element order (same bits as the one-by-one loop).
-    constexpr int U = NR == 1 ? (CPLX ? 8 : 16) : NR == 2 ? 4 : 1;
+    // adds keep the element order (same bits as the one-by-one loop).  The
+    // stored form is read once, with non-temporal loads, so that it displaces
+    // less of x from the caches.  (A masked last step in place of the
+    // one-by-one tail measured 11.3 ms against 7.4 ms on the 6x6 sector.)
+    constexpr int U = NR == 1 ? (CPLX ? 16 : 32) : NR == 2 ? 4 : 1;
     uint32_t k = 0;
     for (; k + U <= w; k += U) {
         uint32_t j[U];
@@ -201,7 +204,7 @@ __global__ void __launch_bounds__(256) k_spmv(const uint64_t *off, const uint32_
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint64_t slot = base + static_cast<uint64_t>(k + u) * kSlice;
-            j[u] = cols[slot];
+            j[u] = __builtin_nontemporal_load(&cols[slot]);
             v[u] = value(slot);
         }
 #pragma unroll
@@ -219,7 +222,7 @@ __global__ void __launch_bounds__(256) k_spmv(const uint64_t *off, const uint32_
     }
     for (; k < w; ++k) {
         const uint64_t slot = base + static_cast<uint64_t>(k) * kSlice;
-        const uint32_t j = cols[slot];
+        const uint32_t j = __builtin_nontemporal_load(&cols[slot]);
         if (j == kNoCol) continue;
         const T v = value(slot);
 #pragma unroll
