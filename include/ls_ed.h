@@ -33,11 +33,12 @@
  * overlap; a handle may be shared by concurrent calls.
  *
  * Destruction: handle memory is stream-ordered (hipMallocAsync).  Each
- * handle records the streams it was used on (a basis and an operator also
- * those of the calls that used an operator or solver built on them);
- * *_destroy waits for those streams only, never the whole device, and then
- * releases the memory.  Those streams must still exist when the handle is
- * destroyed; destroy a handle before the streams it ran on.
+ * call that uses a handle records, on its stream, an event after the work it
+ * enqueued (a basis and an operator also for the calls that used an
+ * operator, solver or batch built on them); *_destroy waits for those events
+ * only -- the handle's own work, not the whole device nor later work on the
+ * same streams -- and then releases the memory.  Destroy a handle before the
+ * streams it ran on.
  *
  * Errors: every call returns ls_status.  No exception crosses this boundary.
  * On LS_EINVAL nothing has been enqueued and out-parameters are untouched.
@@ -172,7 +173,7 @@ ls_status ls_basis_info(const ls_basis *basis, uint64_t *dim, int *is_real,
  * buffers on `stream`.  Either destination may be NULL.                   */
 ls_status ls_basis_copy(const ls_basis *basis, uint64_t *d_reps_out, uint16_t *d_stab_out, void *stream);
 
-/* Waits for the streams the basis was used on, then frees it. */
+/* Waits for the basis's work on every stream it was used on, then frees it. */
 void ls_basis_destroy(ls_basis *basis);
 
 /* Test hook for the lookup-miss error path (host-forced fault injection):
@@ -211,7 +212,7 @@ ls_status ls_index_lookup(const ls_basis *basis, uint64_t n, const uint64_t *d_k
  * must outlive it.                                                         */
 ls_status ls_operator_create(const ls_basis *basis, uint32_t n_terms, const ls_term *terms,
                              ls_operator **out);
-/* Waits for the streams the operator was used on, then frees it. */
+/* Waits for the operator's work on every stream it was used on, then frees it. */
 void ls_operator_destroy(ls_operator *op);
 
 /* Whether the operator acts on complex vectors (complex characters or
@@ -361,7 +362,7 @@ ls_status ls_batch_set_search(ls_batch *batch, int mode, uint32_t bits);
  * first ls_batch_matvec.                                                   */
 ls_status ls_batch_set_graph(ls_batch *batch, int enabled);
 
-/* Waits for the streams of the batch's products, then frees it. */
+/* Waits for the batch's products, then frees it. */
 void ls_batch_destroy(ls_batch *batch);
 
 /* Lanczos ground-state solve on top of ls_matvec.  FP64 throughout, Krylov
@@ -427,6 +428,17 @@ ls_status ls_solver_create(const ls_operator *op, const ls_lanczos_opts *opts, v
  * were stopped (ls_solver_result tells which).                             */
 ls_status ls_solver_step(ls_solver *const *solvers, uint32_t n, void *stream);
 
+/* Up to `steps` (1..1024) iterations of each of the n solvers, enqueued back
+ * to back with one synchronisation at the end (the kernels of a step read
+ * alpha and beta on the device, so the steps need nothing from the host in
+ * between).  The host bookkeeping then replays the steps in order and stops
+ * every solve where single ls_solver_step calls would have stopped, with the
+ * same numbers; a solve that stops inside the chunk has had the rest of the
+ * chunk's steps computed and discarded (at most steps - 1 products).  The
+ * chunk is cut short to the fewest steps any listed solve has left before
+ * max_iter.  Errors as ls_solver_step.                                     */
+ls_status ls_solver_step_n(ls_solver *const *solvers, uint32_t n, uint32_t steps, void *stream);
+
 /* Current lowest Ritz value, steps taken, residual bound, whether the solve
  * is finished (converged, max_iter reached, Krylov space exhausted, or
  * stopped) and whether the tolerance was met.  Any output may be NULL.
@@ -435,7 +447,7 @@ ls_status ls_solver_step(ls_solver *const *solvers, uint32_t n, void *stream);
 ls_status ls_solver_result(const ls_solver *solver, double *e0, uint32_t *iters, double *resid_bound, int *done,
                            int *converged);
 
-/* Waits for the streams the solver stepped on, then frees it. */
+/* Waits for the solver's steps, then frees it. */
 void ls_solver_destroy(ls_solver *solver);
 
 /* Thread-local description of the last non-OK status. */

@@ -26,7 +26,8 @@ EXPORTS = ["ls_sector_check", "ls_sector_count", "ls_sector_count_noalloc", "ls_
            "ls_batch_create", "ls_batch_matvec", "ls_batch_info", "ls_batch_search", "ls_batch_set_search",
            "ls_batch_set_graph",
            "ls_batch_destroy",
-           "ls_lanczos", "ls_solver_footprint", "ls_solver_create", "ls_solver_step", "ls_solver_result",
+           "ls_lanczos", "ls_solver_footprint", "ls_solver_create", "ls_solver_step", "ls_solver_step_n",
+           "ls_solver_result",
            "ls_solver_destroy", "ls_last_error", "ls_version"]
 
 
@@ -97,6 +98,7 @@ def load(path: str = LIB_PATH):
         "ls_solver_footprint": ([P, u32, P], i32),
         "ls_solver_create": ([P, P, P, P], i32),
         "ls_solver_step": ([P, u32, P], i32),
+        "ls_solver_step_n": ([P, u32, u32, P], i32),
         "ls_solver_result": ([P, P, P, P, P, P], i32),
         "ls_solver_destroy": ([P], None),
         "ls_last_error": ([], ctypes.c_char_p),
@@ -438,12 +440,17 @@ class Solver:
         return int(b.value)
 
     @staticmethod
-    def step_all(solvers, stream=None):
+    def step_all(solvers, stream=None, steps: int = 1):
+        """One iteration of every solver (ls_solver_step), or up to `steps`
+        with one synchronisation (ls_solver_step_n)."""
         n = len(solvers)
         if n == 0:
             return
         arr = (ctypes.c_void_p * n)(*[s._h.value for s in solvers])
-        _check(load().ls_solver_step(arr, n, _stream_ptr(stream)))
+        if steps == 1:
+            _check(load().ls_solver_step(arr, n, _stream_ptr(stream)))
+        else:
+            _check(load().ls_solver_step_n(arr, n, int(steps), _stream_ptr(stream)))
 
     def result(self) -> dict:
         e0, res = ctypes.c_double(), ctypes.c_double()

@@ -25,17 +25,50 @@ void dev_free(void *p, hipStream_t stream) {
     if (p) (void)hipFreeAsync(p, stream);
 }
 
+namespace {
+thread_local std::vector<std::pair<StreamSet *, hipStream_t>> t_pending;   // marks of the current call
+}
+
 void StreamSet::add(hipStream_t st) {
+    for (const auto &p : t_pending)
+        if (p.first == this && p.second == st) return;
+    t_pending.push_back({this, st});
+}
+
+void StreamSet::mark(hipStream_t st) {
     std::lock_guard<std::mutex> lk(mu);
-    for (hipStream_t x : streams)
-        if (x == st) return;
-    streams.push_back(st);
+    hipEvent_t ev = nullptr;
+    for (const auto &m : marks)
+        if (m.first == st) ev = m.second;
+    if (!ev) {
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            (void)hipStreamSynchronize(st);   // no event: wait for the stream now
+            return;
+        }
+        marks.push_back({st, ev});
+    }
+    if (hipEventRecord(ev, st) != hipSuccess) (void)hipStreamSynchronize(st);
+}
+
+void flush_marks() {
+    std::vector<std::pair<StreamSet *, hipStream_t>> p;
+    p.swap(t_pending);
+    for (const auto &m : p) m.first->mark(m.second);
 }
 
 void StreamSet::drain() {
+    std::vector<std::pair<StreamSet *, hipStream_t>> keep;
+    for (const auto &p : t_pending) {
+        if (p.first == this) mark(p.second);
+        else keep.push_back(p);
+    }
+    t_pending.swap(keep);
     std::lock_guard<std::mutex> lk(mu);
-    for (hipStream_t x : streams) (void)hipStreamSynchronize(x);
-    streams.clear();
+    for (const auto &m : marks) {
+        (void)hipEventSynchronize(m.second);
+        (void)hipEventDestroy(m.second);
+    }
+    marks.clear();
 }
 
 void touch(const ls_operator *op, hipStream_t st) {
@@ -47,8 +80,13 @@ void touch(const ls_operator *op, hipStream_t st) {
 
 namespace {
 
+// Runs an entry point's body: exceptions become statuses, and the handles'
+// use marks noted during the call are recorded once its work is enqueued.
 template <typename F>
 ls_status guarded(F &&f) {
+    struct Flush {
+        ~Flush() { ls::flush_marks(); }
+    } flush;
     try {
         return f();
     } catch (const ls::Error &e) {
@@ -420,7 +458,16 @@ ls_status ls_solver_create(const ls_operator *op, const ls_lanczos_opts *opts, v
 ls_status ls_solver_step(ls_solver *const *solvers, uint32_t n, void *stream) {
     return guarded([&] {
         LS_REQUIRE(n == 0 || solvers != nullptr, "solvers must not be NULL");
-        ls::solver_step(solvers, n, as_stream(stream));
+        ls::solver_step(solvers, n, 1, as_stream(stream));
+        return LS_OK;
+    });
+}
+
+ls_status ls_solver_step_n(ls_solver *const *solvers, uint32_t n, uint32_t steps, void *stream) {
+    return guarded([&] {
+        LS_REQUIRE(n == 0 || solvers != nullptr, "solvers must not be NULL");
+        LS_REQUIRE(steps >= 1 && steps <= 1024, "steps must be in 1..1024");
+        ls::solver_step(solvers, n, steps, as_stream(stream));
         return LS_OK;
     });
 }

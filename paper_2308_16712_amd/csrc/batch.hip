@@ -39,7 +39,8 @@ constexpr int batch_block(int kind, bool cplx) { return (kind == kOrbitTorus && 
 
 template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
 __global__ void __launch_bounds__(batch_block(KIND, CPLX))
-    k_matvec_batch(const MatvecJob *jobs, const Tile *tiles, uint32_t n_tiles, uint32_t *counter, uint32_t rpl) {
+    k_matvec_batch(const MatvecJob *jobs, const Tile *tiles, uint32_t n_tiles, uint32_t *counter, uint32_t rpl,
+                   uint32_t tile_rows) {
     constexpr int BLOCK = batch_block(KIND, CPLX);
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t s_tile;
@@ -60,7 +61,10 @@ __global__ void __launch_bounds__(batch_block(KIND, CPLX))
             __syncthreads();
             cur = jid;
         }
-        run_rows<W, KIND, CHI, CPLX, NR, LX, LY, NZ, true>(a, L, T.row0 + threadIdx.x, BLOCK, rpl);
+        // a tile is rows row0 + t + k * tile_rows (t < tile_rows, k < rpl);
+        // tile_rows < BLOCK spreads small jobs over more workgroups
+        if (threadIdx.x < tile_rows)
+            run_rows<W, KIND, CHI, CPLX, NR, LX, LY, NZ, true>(a, L, T.row0 + threadIdx.x, tile_rows, rpl);
     }
 }
 
@@ -132,6 +136,7 @@ struct Group {
     uint32_t *d_counter = nullptr;
     uint32_t n_tiles = 0;
     uint32_t rpl = 4;
+    uint32_t tile_rows = 0;   // rows per tile step (0: the workgroup size)
     uint32_t grid = 0;
     size_t lds = 0;
     bool tuned = false;
@@ -150,7 +155,8 @@ struct BatchLaunch {
             constexpr int BLOCK = batch_block(KIND, CPLX);
             hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, g->d_counter);
             hipLaunchKernelGGL((k_matvec_batch<W, KIND, CHI, CPLX, NR, LX, LY, NZ>), dim3(g->grid), dim3(BLOCK),
-                               g->lds, st, g->d_jobs, g->d_tiles, g->n_tiles, g->d_counter, g->rpl);
+                               g->lds, st, g->d_jobs, g->d_tiles, g->n_tiles, g->d_counter, g->rpl,
+                               g->tile_rows ? g->tile_rows : static_cast<uint32_t>(BLOCK));
         }
     }
 };
@@ -159,7 +165,7 @@ int block_for(const Variant &v) { return batch_block(v.kind, v.cplx); }
 
 // Tiles for the current rows-per-lane, ordered by decreasing job cost.
 void build_tiles(Group &g, hipStream_t st) {
-    const uint64_t rows_per_tile = static_cast<uint64_t>(block_for(g.v)) * g.rpl;
+    const uint64_t rows_per_tile = static_cast<uint64_t>(g.tile_rows ? g.tile_rows : block_for(g.v)) * g.rpl;
     std::vector<uint32_t> order(g.jobs.size());
     for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return g.cost[a] > g.cost[b]; });
@@ -653,7 +659,7 @@ void ensure_capacity(T **p, size_t *cap, size_t need) {
 }  // namespace
 
 void fused_matvec(FusedState *f, uint32_t n, const ls_operator *const *ops, const void *const *xs, void *const *ys,
-                  hipStream_t st) {
+                  hipStream_t st, HostKeep *keep) {
     for (auto &g : f->groups) {
         g.jobs.clear();
         g.cost.clear();
@@ -691,7 +697,22 @@ void fused_matvec(FusedState *f, uint32_t n, const ls_operator *const *ops, cons
                 wpc = it->second.second;
             }
         }
-        const uint64_t rows_per_tile = static_cast<uint64_t>(block_for(g.v)) * g.rpl;
+        // few rows in all (small solves): one row per lane and tiles of whole
+        // waves, so that the rows spread over every resident workgroup
+        uint64_t total = 0;
+        for (const auto &j : g.jobs) total += j.dim;
+        const uint64_t block = static_cast<uint64_t>(block_for(g.v));
+        const uint64_t slots = static_cast<uint64_t>(f->n_cu) * wpc;
+        g.tile_rows = 0;
+        if (total < slots * block) {
+            g.rpl = 1;
+            const uint64_t per = (total + slots - 1) / slots;
+            g.tile_rows = static_cast<uint32_t>(std::min<uint64_t>(block, std::max<uint64_t>(64, (per + 63) / 64 * 64)));
+        } else {
+            // at least one tile per resident workgroup
+            g.rpl = static_cast<uint32_t>(std::min<uint64_t>(g.rpl, std::max<uint64_t>(1, total / (slots * block))));
+        }
+        const uint64_t rows_per_tile = static_cast<uint64_t>(g.tile_rows ? g.tile_rows : block) * g.rpl;
         std::vector<uint32_t> order(g.jobs.size());
         for (uint32_t j = 0; j < order.size(); ++j) order[j] = j;
         std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return g.cost[a] > g.cost[b]; });
@@ -701,10 +722,13 @@ void fused_matvec(FusedState *f, uint32_t n, const ls_operator *const *ops, cons
             for (uint64_t r = 0; r < g.jobs[j].dim; r += rows_per_tile) tiles.push_back(Tile{j, 0, r});
         ensure_capacity(&g.d_jobs, &g.cap_jobs, g.jobs.size());
         ensure_capacity(&g.d_tiles, &g.cap_tiles, tiles.size());
-        LS_HIP_CHECK(hipMemcpyAsync(g.d_jobs, g.jobs.data(), g.jobs.size() * sizeof(MatvecJob),
-                                    hipMemcpyHostToDevice, st));
-        LS_HIP_CHECK(hipMemcpyAsync(g.d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice,
+        // with `keep`, the tables are uploaded from copies that outlive this
+        // call (the caller enqueues more work before synchronising)
+        const MatvecJob *src_jobs = keep ? keep_copy(*keep, g.jobs.data(), g.jobs.size()) : g.jobs.data();
+        const Tile *src_tiles = keep ? keep_copy(*keep, tiles.data(), tiles.size()) : tiles.data();
+        LS_HIP_CHECK(hipMemcpyAsync(g.d_jobs, src_jobs, g.jobs.size() * sizeof(MatvecJob), hipMemcpyHostToDevice,
                                     st));
+        LS_HIP_CHECK(hipMemcpyAsync(g.d_tiles, src_tiles, tiles.size() * sizeof(Tile), hipMemcpyHostToDevice, st));
         g.n_tiles = static_cast<uint32_t>(tiles.size());
         g.grid = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(f->n_cu) * wpc, g.n_tiles));
         BatchLaunch L{&g, st};

@@ -800,8 +800,9 @@ __global__ void kb_decide(const StepJob *jobs, uint32_t count, int stage) {
 }
 
 // per solve: alpha, beta (k_alpha_beta), beta_k for the next step, and the
-// staging row read back by the host (alpha, beta, lookup-miss flag, which
-// is cleared)
+// staging row read back by the host (alpha, beta, lookup-miss flag; the
+// flags are cleared before the next step's products, so solves sharing an
+// operator all see its flag)
 __global__ void kb_alpha_beta(const StepJob *jobs, uint32_t count) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= count) return;
@@ -811,7 +812,15 @@ __global__ void kb_alpha_beta(const StepJob *jobs, uint32_t count) {
     J.row[0] = J.scal[0];
     J.row[1] = J.scal[1];
     J.row[2] = static_cast<double>(*J.err);
-    *J.err = 0u;
+}
+
+// Clears up to 32 operators' lookup-miss flags (a fill kernel, not a memset).
+struct FlagList {
+    uint32_t *p[32];
+    uint32_t n;
+};
+__global__ void k_clear_flags(FlagList L) {
+    if (threadIdx.x < L.n) *L.p[threadIdx.x] = 0u;
 }
 
 // V_{k+1} = w / beta_{k+1} elementwise over doubles (k_div_dev), and beta_k
@@ -835,8 +844,7 @@ struct StepTables {
     RedTask *tasks = nullptr;
     uint32_t *offs = nullptr;     // prefix tables, packed
     double *staging = nullptr;    // [count][4] device side of the read-back
-    double *host = nullptr;       // pinned [count][4]
-    size_t cap_jobs = 0, cap_tasks = 0, cap_offs = 0, cap_staging = 0, cap_host = 0;
+    size_t cap_jobs = 0, cap_tasks = 0, cap_offs = 0, cap_staging = 0;
 };
 StepTables g_tables;
 
@@ -855,9 +863,9 @@ void grow(X **p, size_t *cap, size_t need) {
 // The after-product work of step k for every solve in `act`, batched: all
 // of one element type, and either all reorthogonalising (full or selective,
 // mixed) or none.  Each solve's (alpha, beta, flag) row lands in host_rows
-// ([act][4], pinned) on `st`.
+// ([act][4], pinned) on `st`; the host tables it uploads go to `keep`.
 template <bool CPLX>
-void batched_after_products(const std::vector<ls_solver *> &act, hipStream_t st, double *host_rows) {
+void batched_after_products(const std::vector<ls_solver *> &act, hipStream_t st, double *host_rows, HostKeep &keep) {
     const uint32_t S = static_cast<uint32_t>(act.size());
     StepTables &G = g_tables;   // sized by the caller for the whole step
     std::vector<StepJob> jobs(S);
@@ -909,9 +917,13 @@ void batched_after_products(const std::vector<ls_solver *> &act, hipStream_t st,
                                        J.mode == kReorthSelective ? J.nrm + 2 : J.dots + 1});
     std::vector<uint32_t> offs;
     for (auto *L : {&off_dot, &off_el, &off_div, &o_one, &o_h}) offs.insert(offs.end(), L->begin(), L->end());
-    LS_HIP_CHECK(hipMemcpyAsync(G.jobs, jobs.data(), S * sizeof(StepJob), hipMemcpyHostToDevice, st));
-    LS_HIP_CHECK(hipMemcpyAsync(G.tasks, tasks.data(), tasks.size() * sizeof(RedTask), hipMemcpyHostToDevice, st));
-    LS_HIP_CHECK(hipMemcpyAsync(G.offs, offs.data(), offs.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    // uploaded from copies that live until the caller's synchronisation
+    LS_HIP_CHECK(hipMemcpyAsync(G.jobs, keep_copy(keep, jobs.data(), jobs.size()), S * sizeof(StepJob),
+                                hipMemcpyHostToDevice, st));
+    LS_HIP_CHECK(hipMemcpyAsync(G.tasks, keep_copy(keep, tasks.data(), tasks.size()), tasks.size() * sizeof(RedTask),
+                                hipMemcpyHostToDevice, st));
+    LS_HIP_CHECK(hipMemcpyAsync(G.offs, keep_copy(keep, offs.data(), offs.size()), offs.size() * sizeof(uint32_t),
+                                hipMemcpyHostToDevice, st));
     const uint32_t *d_dot = G.offs, *d_el = d_dot + (S + 1), *d_div = d_el + (S + 1), *d_one = d_div + (S + 1),
                    *d_h = d_one + (S + 1);
     const RedTask *T_alpha = G.tasks, *T_h = T_alpha + S, *T_before = T_h + S, *T_after = T_before + S,
@@ -947,188 +959,192 @@ void batched_after_products(const std::vector<ls_solver *> &act, hipStream_t st,
     LS_HIP_CHECK(hipMemcpyAsync(host_rows, G.staging, S * 4 * sizeof(double), hipMemcpyDeviceToHost, st));
 }
 
-void solver_step(ls_solver *const *ss, uint32_t n, hipStream_t st) {
+namespace {
+
+// Pinned read-back of a chunk of steps: [steps][solves][4] doubles (alpha,
+// beta, flag) and [steps] flag words of a single solve.
+struct StepRows {
+    double *rows = nullptr;
+    uint32_t *flags = nullptr;
+    size_t cap_rows = 0, cap_flags = 0;
+};
+StepRows g_rows;
+
+void ensure_rows(size_t n_rows, size_t n_flags) {
+    if (g_rows.cap_rows < n_rows) {
+        if (g_rows.rows) LS_HIP_CHECK(hipHostFree(g_rows.rows));
+        g_rows.rows = nullptr;
+        g_rows.cap_rows = 0;
+        const size_t c = std::max<size_t>(n_rows, 2 * g_rows.cap_rows + 256);
+        LS_HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&g_rows.rows), c * 4 * sizeof(double)));
+        g_rows.cap_rows = c;
+    }
+    if (g_rows.cap_flags < n_flags) {
+        if (g_rows.flags) LS_HIP_CHECK(hipHostFree(g_rows.flags));
+        g_rows.flags = nullptr;
+        g_rows.cap_flags = 0;
+        const size_t c = std::max<size_t>(n_flags, 256);
+        LS_HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&g_rows.flags), c * sizeof(uint32_t)));
+        g_rows.cap_flags = c;
+    }
+}
+
+}  // namespace
+
+// Up to `steps` iterations of every listed solve that is not done, enqueued
+// back to back with one synchronisation at the end.  Every kernel of a step
+// reads alpha and beta on the device, so the steps need nothing from the
+// host in between; each step's (alpha, beta, flag) rows land in pinned
+// memory, and the host bookkeeping then replays the steps in order exactly
+// as after single steps, stopping each solve where single steps would have
+// stopped.  Steps enqueued past a solve's stop (convergence or breakdown
+// inside the chunk) only write Krylov vectors and device scalars that the
+// finished solve never reads.
+void solver_step(ls_solver *const *ss, uint32_t n, uint32_t steps, hipStream_t st) {
     std::lock_guard<std::mutex> lk(g_step_mu);
     if (!g_fused) g_fused = fused_create();
     std::vector<ls_solver *> act;
     for (uint32_t i = 0; i < n; ++i)
         if (ss[i] && !ss[i]->done) act.push_back(ss[i]);
-    if (act.empty()) return;
+    if (act.empty() || steps == 0) return;
+    uint32_t c = steps;
     for (ls_solver *s : act) {
         s->used.add(st);
         touch(s->op, st);
+        c = std::min(c, s->m - s->k);   // k < m while a solve is not done
     }
-    // one fused launch for every active solve's product w = H v_k
-    std::vector<const ls_operator *> ops;
-    std::vector<const void *> xs;
-    std::vector<void *> ys;
-    for (ls_solver *s : act) {
-        const size_t es = s->cplx ? 16 : 8;
-        ops.push_back(s->op);
-        xs.push_back(static_cast<const char *>(s->V) + static_cast<size_t>(s->k) * s->n * es);
-        ys.push_back(s->w);
-    }
-    // a solve whose operator holds stored elements takes its stored product;
-    // the others share one fused launch, or take the single launch when
-    // alone (its tuned shape).  The row arithmetic, and so every result bit,
-    // is the same in all three.
-    std::vector<const ls_operator *> fops;
-    std::vector<const void *> fxs;
-    std::vector<void *> fys;
-    for (size_t i = 0; i < ops.size(); ++i) {
-        if (ops[i]->stored) {
-            launch_matvec(ops[i], 1, xs[i], ys[i], st);
-        } else {
-            fops.push_back(ops[i]);
-            fxs.push_back(xs[i]);
-            fys.push_back(ys[i]);
-        }
-    }
-    if (fops.size() == 1) launch_matvec(fops[0], 1, fxs[0], fys[0], st);
-    else if (fops.size() > 1)
-        fused_matvec(g_fused, static_cast<uint32_t>(fops.size()), fops.data(), fxs.data(), fys.data(), st);
+    const size_t A = act.size();
+    const bool batched = A >= 2;
+    std::vector<uint32_t> k0(A);
+    for (size_t a = 0; a < A; ++a) k0[a] = act[a]->k;
+    // operators' lookup-miss flags (cleared before each batched step's products)
+    std::vector<uint32_t *> flags;
+    for (ls_solver *s : act)
+        if (std::find(flags.begin(), flags.end(), s->op->d_err) == flags.end()) flags.push_back(s->op->d_err);
+    ensure_rows(A * c, c);
     // the work after the products: per solve for a single solve, else
     // batched by element type and reorthogonalisation (identical numbers)
-    const bool batched = act.size() >= 2;
-    std::vector<size_t> row_of(act.size(), 0);
-    if (!batched) {
-        for (ls_solver *s : act) {
-            if (s->cplx) enqueue_after_product<true>(s, st);
-            else enqueue_after_product<false>(s, st);
-        }
-    } else {
+    std::vector<ls_solver *> groups[4];   // (complex, without reorthogonalisation)
+    std::vector<size_t> row_of(A, 0);
+    if (batched) {
         StepTables &G = g_tables;
-        const size_t A = act.size();
         grow(&G.jobs, &G.cap_jobs, A);
         grow(&G.staging, &G.cap_staging, 4 * A);
         grow(&G.tasks, &G.cap_tasks, 5 * A);
         grow(&G.offs, &G.cap_offs, 5 * (A + 1));
-        if (G.cap_host < 4 * A) {
-            if (G.host) LS_HIP_CHECK(hipHostFree(G.host));
-            G.host = nullptr;
-            LS_HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&G.host), 4 * A * sizeof(double) * 2));
-            G.cap_host = 8 * A;
-        }
-        std::vector<ls_solver *> groups[4];   // (complex, without reorthogonalisation)
         std::vector<size_t> where[4];
-        for (size_t i = 0; i < A; ++i) {
-            const int g = (act[i]->cplx ? 2 : 0) + (act[i]->reorth == kReorthNone ? 1 : 0);
-            groups[g].push_back(act[i]);
-            where[g].push_back(i);
+        for (size_t a = 0; a < A; ++a) {
+            const int g = (act[a]->cplx ? 2 : 0) + (act[a]->reorth == kReorthNone ? 1 : 0);
+            groups[g].push_back(act[a]);
+            where[g].push_back(a);
         }
         size_t r = 0;
         for (int g = 0; g < 4; ++g) {
-            if (groups[g].empty()) continue;
-            if (g >= 2) batched_after_products<true>(groups[g], st, G.host + 4 * r);
-            else batched_after_products<false>(groups[g], st, G.host + 4 * r);
             for (size_t q = 0; q < groups[g].size(); ++q) row_of[where[g][q]] = r + q;
             r += groups[g].size();
         }
     }
-    LS_HIP_CHECK(hipStreamSynchronize(st));
-    if (batched) {
-        for (size_t i = 0; i < act.size(); ++i) {
-            const double *row = g_tables.host + 4 * row_of[i];
-            act[i]->host[0] = row[0];
-            act[i]->host[1] = row[1];
-            *act[i]->hflag = row[2] != 0.0 ? 1u : 0u;
+    double *const own_host = act[0]->host;
+    uint32_t *const own_flag = act[0]->hflag;
+    auto restore = [&]() {
+        for (size_t a = 0; a < A; ++a) act[a]->k = k0[a];
+        act[0]->host = own_host;
+        act[0]->hflag = own_flag;
+    };
+    HostKeep keep;   // host sources of this chunk's uploads
+    try {
+        for (uint32_t i = 0; i < c; ++i) {
+            for (size_t a = 0; a < A; ++a) act[a]->k = k0[a] + i;
+            if (batched)
+                for (size_t f = 0; f < flags.size(); f += 32) {
+                    FlagList L{};
+                    L.n = static_cast<uint32_t>(std::min<size_t>(32, flags.size() - f));
+                    for (uint32_t q = 0; q < L.n; ++q) L.p[q] = flags[f + q];
+                    hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(32), 0, st, L);
+                }
+            // products w = H v_k: a solve whose operator holds stored elements
+            // takes its stored product; the others share one fused launch, or
+            // take the single launch when alone (its tuned shape).  The row
+            // arithmetic, and so every result bit, is the same in all three.
+            std::vector<const ls_operator *> fops;
+            std::vector<const void *> fxs;
+            std::vector<void *> fys;
+            for (ls_solver *s : act) {
+                const size_t es = s->cplx ? 16 : 8;
+                const void *x = static_cast<const char *>(s->V) + static_cast<size_t>(s->k) * s->n * es;
+                if (s->op->stored) {
+                    launch_matvec(s->op, 1, x, s->w, st);
+                } else {
+                    fops.push_back(s->op);
+                    fxs.push_back(x);
+                    fys.push_back(s->w);
+                }
+            }
+            if (fops.size() == 1) launch_matvec(fops[0], 1, fxs[0], fys[0], st);
+            else if (fops.size() > 1)
+                fused_matvec(g_fused, static_cast<uint32_t>(fops.size()), fops.data(), fxs.data(), fys.data(), st,
+                             &keep);
+            if (!batched) {
+                ls_solver *s = act[0];
+                s->host = g_rows.rows + 4 * static_cast<size_t>(i);
+                s->hflag = g_rows.flags + i;
+                if (s->cplx) enqueue_after_product<true>(s, st);
+                else enqueue_after_product<false>(s, st);
+            } else {
+                double *rows = g_rows.rows + 4 * A * static_cast<size_t>(i);
+                size_t r = 0;
+                for (int g = 0; g < 4; ++g) {
+                    if (groups[g].empty()) continue;
+                    if (g >= 2) batched_after_products<true>(groups[g], st, rows + 4 * r, keep);
+                    else batched_after_products<false>(groups[g], st, rows + 4 * r, keep);
+                    r += groups[g].size();
+                }
+            }
         }
+        LS_HIP_CHECK(hipStreamSynchronize(st));
+    } catch (...) {
+        hipStreamSynchronize(st);   // the enqueued copies still read `keep`
+        restore();
+        throw;
     }
-    // a solve whose product met a lookup miss stops here (its step is not
-    // taken); the others finish theirs
+    restore();
+    // replay: a solve whose product met a lookup miss stops at that step
+    // (the step is not taken); the others finish theirs
     uint32_t failed = 0;
-    for (ls_solver *s : act) {
-        if (*s->hflag) {
-            *s->hflag = 0;
-            s->failed = true;
-            s->done = true;
-            ++failed;
-        } else {
-            finish_step(s);
+    double row2[2];
+    for (uint32_t i = 0; i < c; ++i) {
+        for (size_t a = 0; a < A; ++a) {
+            ls_solver *s = act[a];
+            if (s->done) continue;
+            bool flag;
+            double *saved = s->host;
+            if (batched) {
+                const double *row = g_rows.rows + 4 * (A * static_cast<size_t>(i) + row_of[a]);
+                row2[0] = row[0];
+                row2[1] = row[1];
+                s->host = row2;
+                flag = row[2] != 0.0;
+            } else {
+                s->host = g_rows.rows + 4 * static_cast<size_t>(i);
+                flag = g_rows.flags[i] != 0;
+            }
+            if (flag) {
+                s->failed = true;
+                s->done = true;
+                ++failed;
+            } else {
+                finish_step(s);
+            }
+            s->host = saved;
         }
     }
     if (failed)
-        throw Error{LS_EINTERNAL, std::to_string(failed) + " of " + std::to_string(act.size()) +
+        throw Error{LS_EINTERNAL, std::to_string(failed) + " of " + std::to_string(A) +
                                       " solves met a neighbour whose representative lies in the sector but is "
                                       "missing from the basis; they are stopped (ls_solver_result reports them)"};
 }
 
 bool solver_failed(const ls_solver *s) { return s->failed; }
-
-namespace {
-
-// Pinned read-back rows of solver_run: (alpha, beta) and the flag word of
-// every step of a chunk.
-struct ChunkRows {
-    double *rows = nullptr;     // [cap][2]
-    uint32_t *flags = nullptr;  // [cap]
-    size_t cap = 0;
-};
-ChunkRows g_chunk;
-
-// Up to `count` steps of one solve enqueued back to back with a single
-// synchronisation at the end.  The kernels of a step read alpha and beta on
-// the device, so the steps need nothing from the host in between; the host
-// bookkeeping then replays the steps in order, exactly as after single
-// steps, and stops where single steps would have stopped.  Steps enqueued
-// past that point (convergence or breakdown inside the chunk) only write
-// Krylov vectors and device scalars that the finished solve never reads.
-template <bool CPLX>
-void solver_run(ls_solver *s, uint32_t count, hipStream_t st) {
-    std::lock_guard<std::mutex> lk(g_step_mu);
-    if (s->done) return;
-    s->used.add(st);
-    touch(s->op, st);
-    const uint32_t k0 = s->k;
-    const uint32_t c = std::min(count, s->m - k0);
-    if (g_chunk.cap < c) {
-        if (g_chunk.rows) LS_HIP_CHECK(hipHostFree(g_chunk.rows));
-        if (g_chunk.flags) LS_HIP_CHECK(hipHostFree(g_chunk.flags));
-        g_chunk = ChunkRows{};
-        const size_t cap = std::max<size_t>(c, 64);
-        LS_HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&g_chunk.rows), cap * 2 * sizeof(double)));
-        LS_HIP_CHECK(hipHostMalloc(reinterpret_cast<void **>(&g_chunk.flags), cap * sizeof(uint32_t)));
-        g_chunk.cap = cap;
-    }
-    double *const own_host = s->host;
-    uint32_t *const own_flag = s->hflag;
-    using T = typename V<CPLX>::T;
-    try {
-        for (uint32_t i = 0; i < c; ++i) {
-            s->k = k0 + i;
-            s->host = g_chunk.rows + 2 * i;
-            s->hflag = g_chunk.flags + i;
-            launch_matvec(s->op, 1, static_cast<const T *>(s->V) + static_cast<size_t>(s->k) * s->n, s->w, st);
-            enqueue_after_product<CPLX>(s, st);
-        }
-        LS_HIP_CHECK(hipStreamSynchronize(st));
-    } catch (...) {
-        s->k = k0;
-        s->host = own_host;
-        s->hflag = own_flag;
-        throw;
-    }
-    s->k = k0;
-    bool failed = false;
-    for (uint32_t i = 0; i < c && !s->done; ++i) {
-        s->host = g_chunk.rows + 2 * i;
-        if (g_chunk.flags[i]) {
-            s->failed = true;
-            s->done = true;
-            failed = true;
-            break;
-        }
-        finish_step(s);
-    }
-    s->host = own_host;
-    s->hflag = own_flag;
-    if (failed)
-        throw Error{LS_EINTERNAL,
-                    "the solve met a neighbour whose representative lies in the sector but is missing from the "
-                    "basis"};
-}
-
-}  // namespace
 
 // ls_lanczos: one solve driven by the stepper kernels (alpha and beta stay on
 // the device), run in chunks of steps with one synchronisation per chunk.
@@ -1143,10 +1159,7 @@ ls_status run_lanczos(const ls_operator *op, const ls_lanczos_opts *o, hipStream
     ls_solver *s = solver_create(op, o, st);
     const uint32_t chunk = o->tol > 0 ? (s->n <= (1u << 20) ? 8u : 1u) : 32u;
     try {
-        while (!s->done) {
-            if (s->cplx) solver_run<true>(s, chunk, st);
-            else solver_run<false>(s, chunk, st);
-        }
+        while (!s->done) solver_step(&s, 1, chunk, st);
     } catch (...) {
         hipStreamSynchronize(st);
         free_solver(s);

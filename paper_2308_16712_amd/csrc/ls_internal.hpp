@@ -53,14 +53,23 @@ T *dev_alloc_n(size_t count, hipStream_t stream) {
 // streams have drained); null pointers are ignored.
 void dev_free(void *p, hipStream_t stream = nullptr);
 
-// The streams a handle's device work was enqueued on.
+// Where a handle's device work ends on each stream it was used on: one
+// event per stream, recorded after the last call's work on it.  add() notes
+// the stream during a call; the event is recorded when the library call
+// returns (flush_marks, after all of the call's work is enqueued), so a
+// destroy waits for the handle's own work only, not for what other handles
+// enqueue on the same streams later.
 struct StreamSet {
     std::mutex mu;
-    std::vector<hipStream_t> streams;
-    void add(hipStream_t s);
-    // Waits for each recorded stream (the caller's streams must still exist).
+    std::vector<std::pair<hipStream_t, hipEvent_t>> marks;
+    void add(hipStream_t s);          // during a call: mark s when it returns
+    void mark(hipStream_t s);         // record s's event now
+    // Records this thread's pending marks of the set, then waits for every
+    // event and releases them.
     void drain();
 };
+// Records the marks noted by add() during the calling thread's library call.
+void flush_marks();
 
 // ---------------------------------------------------------------- group plan
 //
@@ -291,14 +300,23 @@ void batch_search(const ls_batch *b, uint32_t item, uint32_t *mode, uint32_t *bi
 struct FusedState;
 FusedState *fused_create();
 void fused_destroy(FusedState *f);
+// Host bytes of uploads enqueued before a synchronisation, kept alive (and
+// unchanged) until it: the copies read them in stream order.
+using HostKeep = std::vector<std::vector<unsigned char>>;
+template <class T>
+const T *keep_copy(HostKeep &keep, const T *data, size_t count) {
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(data);
+    keep.emplace_back(b, b + count * sizeof(T));
+    return reinterpret_cast<const T *>(keep.back().data());
+}
 void fused_matvec(FusedState *f, uint32_t n, const ls_operator *const *ops, const void *const *xs,
-                  void *const *ys, hipStream_t stream);
+                  void *const *ys, hipStream_t stream, HostKeep *keep = nullptr);
 
 // Lanczos stepper (lanczos.hip)
 uint64_t solver_footprint(const ls_operator *op, uint32_t max_iter);
 ls_solver *solver_create(const ls_operator *op, const ls_lanczos_opts *o, hipStream_t stream);
 void solver_destroy(ls_solver *s);
-void solver_step(ls_solver *const *solvers, uint32_t n, hipStream_t stream);
+void solver_step(ls_solver *const *solvers, uint32_t n, uint32_t steps, hipStream_t stream);
 void solver_result(const ls_solver *s, double *e0, uint32_t *iters, double *resid, int *done, int *converged);
 bool solver_failed(const ls_solver *s);   // stopped by a lookup miss in its product
 

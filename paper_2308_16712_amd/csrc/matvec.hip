@@ -26,27 +26,37 @@ constexpr int waves_per_simd(int kind, int chi, bool cplx, int nr, uint32_t lx) 
                : 1;
 }
 
+// The first rows_per_wg threads of a workgroup take rows (lane = workgroup
+// * rows_per_wg + thread, then strides of n_lanes); the others only help to
+// stage the LDS tables.  A sector with fewer rows than the lanes that fill
+// the GPU runs with fewer rows per workgroup, so that its rows spread over
+// every CU instead of a few full workgroups.  A row's elements are summed by
+// one lane in term order whatever the mapping, so the results do not depend
+// on it.
 template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
 __global__ void __launch_bounds__(block_of(KIND)) __attribute__((amdgpu_waves_per_eu(waves_per_simd(KIND, CHI, CPLX, NR, LX))))
-k_matvec(MatvecJob a, uint64_t n_lanes, uint32_t rows_per_lane) {
+k_matvec(MatvecJob a, uint64_t n_lanes, uint32_t rows_per_lane, uint32_t rows_per_wg) {
     constexpr int BLOCK = block_of(KIND);
     extern __shared__ __align__(16) unsigned char smem[];
     const LdsTables L = lds_tables<KIND, LX, BLOCK>(a, smem);
     stage_tables<KIND, LX, BLOCK>(a, L);
     __syncthreads();
-    const uint64_t lane = static_cast<uint64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+    if (threadIdx.x >= rows_per_wg) return;
+    const uint64_t lane = static_cast<uint64_t>(blockIdx.x) * rows_per_wg + threadIdx.x;
     run_rows<W, KIND, CHI, CPLX, NR, LX, LY, NZ>(a, L, lane, n_lanes, rows_per_lane);
 }
 
 // Push form (comparison variant): same launch shape as k_matvec.
 template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
-__global__ void __launch_bounds__(block_of(KIND)) k_matvec_push(MatvecJob a, uint64_t n_lanes, uint32_t rows_per_lane) {
+__global__ void __launch_bounds__(block_of(KIND))
+    k_matvec_push(MatvecJob a, uint64_t n_lanes, uint32_t rows_per_lane, uint32_t rows_per_wg) {
     constexpr int BLOCK = block_of(KIND);
     extern __shared__ __align__(16) unsigned char smem[];
     const LdsTables L = lds_tables<KIND, LX, BLOCK>(a, smem);
     stage_tables<KIND, LX, BLOCK>(a, L);
     __syncthreads();
-    const uint64_t lane = static_cast<uint64_t>(blockIdx.x) * BLOCK + threadIdx.x;
+    if (threadIdx.x >= rows_per_wg) return;
+    const uint64_t lane = static_cast<uint64_t>(blockIdx.x) * rows_per_wg + threadIdx.x;
     push_rows<W, KIND, CHI, CPLX, NR, LX, LY, NZ>(a, L, lane, n_lanes, rows_per_lane);
 }
 
@@ -65,22 +75,32 @@ struct SingleLaunch {
     template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
     void run() {
         constexpr int BLOCK = block_of(KIND);
-        const uint64_t fill = 256ull * 4 * 8 * 64;   // 256 CUs x 4 SIMDs x 8 waves
+        constexpr uint64_t kCUs = 256;
+        const uint64_t fill = kCUs * 4 * 8 * 64;   // 256 CUs x 4 SIMDs x 8 waves
         const uint32_t rpl =
             static_cast<uint32_t>(std::min<uint64_t>(16, std::max<uint64_t>(1, job.dim / fill)));
+        // rows per workgroup: whole workgroups, unless the rows are too few
+        // to give every CU one (then whole waves, spread over the CUs)
+        uint64_t wg_rows = BLOCK;
+        if (job.dim < kCUs * BLOCK) {
+            const uint64_t per_cu = (job.dim + kCUs - 1) / kCUs;
+            wg_rows = std::min<uint64_t>(BLOCK, std::max<uint64_t>(64, (per_cu + 63) / 64 * 64));
+        }
         uint64_t lanes = (job.dim + rpl - 1) / rpl;
-        lanes = (lanes + BLOCK - 1) / BLOCK * BLOCK;
+        lanes = (lanes + wg_rows - 1) / wg_rows * wg_rows;
+        const dim3 grid(static_cast<uint32_t>(lanes / wg_rows));
+        const uint32_t rows_per_wg = static_cast<uint32_t>(wg_rows);
         const size_t lds = lds_bytes(KIND, job.n_terms, job.n_terms - job.n_diag, job.plan.lx);
         if (push) {
             // the push form runs one column per launch
             if constexpr (NR == 1)
-                hipLaunchKernelGGL((k_matvec_push<W, KIND, CHI, CPLX, 1, LX, LY, NZ>),
-                                   dim3(static_cast<uint32_t>(lanes / BLOCK)), dim3(BLOCK), lds, st, job, lanes, rpl);
+                hipLaunchKernelGGL((k_matvec_push<W, KIND, CHI, CPLX, 1, LX, LY, NZ>), grid, dim3(BLOCK), lds, st,
+                                   job, lanes, rpl, rows_per_wg);
             else
                 throw Error{LS_EINTERNAL, "push products run one column per launch"};
         } else
-            hipLaunchKernelGGL((k_matvec<W, KIND, CHI, CPLX, NR, LX, LY, NZ>),
-                               dim3(static_cast<uint32_t>(lanes / BLOCK)), dim3(BLOCK), lds, st, job, lanes, rpl);
+            hipLaunchKernelGGL((k_matvec<W, KIND, CHI, CPLX, NR, LX, LY, NZ>), grid, dim3(BLOCK), lds, st, job, lanes,
+                               rpl, rows_per_wg);
     }
 };
 

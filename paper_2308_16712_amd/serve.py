@@ -155,6 +155,24 @@ def _wait_until(t0: float, t: float):
 
 
 SMALL_DIM = 1 << 20   # below this a single product cannot fill the GPU
+# Steps of a lone small solve per synchronisation (ls_solver_step_n): a step
+# of a small solve costs about as much as a synchronisation, and ls_lanczos
+# runs the same chunks, so a lone small solve is served at the one-at-a-time
+# pace; an arrival waits at most one chunk to join.
+SMALL_CHUNK = 8
+
+
+def _steps_per_sync(step) -> int:
+    """Iterations per synchronisation for the solves advanced together: a
+    lone small solve takes SMALL_CHUNK; a fused step of a few small solves
+    takes fewer, since every solve that converges inside a chunk has the
+    rest of the chunk computed and discarded; many solves, or a large one,
+    take single steps (their step already outweighs the synchronisation)."""
+    if any(lv.rec.dim >= SMALL_DIM for lv in step):
+        return 1
+    if len(step) == 1:
+        return SMALL_CHUNK
+    return 4 if len(step) <= 3 else 1
 
 
 def _pick(live, policy: str):
@@ -344,7 +362,7 @@ def serve(trace, hbm_budget: int, max_iter: int = 150, tol: float = 1e-10, log=N
                     step = _pick(live, policy)
                     ts = time.perf_counter()
                     try:
-                        Solver.step_all([lv.solver for lv in step])
+                        Solver.step_all([lv.solver for lv in step], steps=_steps_per_sync(step))
                     except LSError as e:
                         # the stopped solves report LS_EINTERNAL in their result;
                         # anything else is not a per-request condition

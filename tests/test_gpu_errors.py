@@ -138,3 +138,31 @@ def test_drop_key_rejects_other_layouts(monkeypatch):
     with pytest.raises(ls.LSError):
         b.test_drop_key(b.dim)
     b.close()
+
+
+def test_chunked_steps_stop_only_the_failing_solve():
+    """As above with four steps per synchronisation (ls_solver_step_n), the
+    two solves sharing one operator: both read its flag, both stop."""
+    sec = CASES["ringT20_k3"]()
+    b1 = ls.ls_basis_build(sec)
+    op1 = ls.ls_operator_create(b1, sec.terms)
+    b2 = ls.ls_basis_build(sec)
+    op2 = ls.ls_operator_create(b2, sec.terms)
+    b2.test_drop_key(b2.dim // 3)
+    alone = op1.lanczos(60, tol=1e-10, seed=6)
+    s1 = ls.Solver(op1, 60, tol=1e-10, seed=6)
+    s2 = ls.Solver(op2, 60, tol=1e-10, seed=6)
+    s3 = ls.Solver(op2, 60, tol=1e-10, seed=7)
+    with pytest.raises(ls.LSError) as e:
+        ls.Solver.step_all([s1, s2, s3], steps=4)
+    assert _is_einternal(e.value)
+    for s in (s2, s3):
+        with pytest.raises(ls.LSError) as e:
+            s.result()
+        assert _is_einternal(e.value)
+    while not s1.result()["done"]:
+        ls.Solver.step_all([s1, s2, s3], steps=4)     # the stopped solves are skipped
+    r1 = s1.result()
+    assert (r1["e0"], r1["iters"], r1["converged"]) == (alone["e0"], alone["iters"], alone["converged"]), (r1, alone)
+    for h in (s1, s2, s3, op1, op2, b1, b2):
+        h.close()

@@ -203,3 +203,37 @@ def test_batched_step_all_modes_match_lanczos_alone():
         assert r["iters"] == a["iters"], m
         assert r["e0"] == a["e0"], (m, r["e0"], a["e0"])
         assert r["resid"] == a["resid"], m
+
+
+@pytest.mark.parametrize("steps", [3, 8])
+def test_chunked_steps_match_single_steps(steps):
+    """ls_solver_step_n: several solves (real and complex, full and
+    selective reorthogonalisation, different tolerances and step limits,
+    one that converges inside a chunk) advanced `steps` iterations per
+    synchronisation end exactly where single steps end, with the same
+    numbers, and agree with ls_lanczos alone."""
+    secs = [configs.ring16_u1(), configs.ring_symmetric(20, 0, 1, 1, 0.3, seed=7),
+            configs.ring_symmetric(18, 3, 0, 0, 0.2, seed=8), configs.square_j1j2(4, 4, 0.4, seed=9)]
+    ops = [ls.ls_operator_create(ls.ls_basis_build(s), s.terms) for s in secs]
+    kw = [dict(max_iter=60, tol=1e-10, reorth=True), dict(max_iter=37, tol=0.0, reorth="selective"),
+          dict(max_iter=50, tol=1e-8, reorth=True), dict(max_iter=45, tol=1e-10, reorth="selective")]
+
+    def make():
+        return [ls.Solver(op, k["max_iter"], tol=k["tol"], seed=s.seed, reorth=k["reorth"])
+                for op, s, k in zip(ops, secs, kw)]
+
+    single, chunked = make(), make()
+    while not all(s.result()["done"] for s in single):
+        ls.Solver.step_all(single)
+    rounds = 0
+    while not all(s.result()["done"] for s in chunked):
+        ls.Solver.step_all(chunked, steps=steps)
+        rounds += 1
+    for op, s, k, a, c in zip(ops, secs, kw, single, chunked):
+        ra, rc = a.result(), c.result()
+        assert ra == rc, (s.name, ra, rc)
+        alone = op.lanczos(k["max_iter"], tol=k["tol"], seed=s.seed, reorth=k["reorth"])
+        assert rc["e0"] == alone["e0"] and rc["iters"] == alone["iters"], s.name
+    assert rounds < max(r.result()["iters"] for r in single)
+    for h in single + chunked + ops:
+        h.close()

@@ -90,3 +90,44 @@ def test_destroy_waits_only_for_its_own_streams():
     assert torch.equal(got[0], want[0]) and torch.equal(got[1], want[1]) and got[2] == want[2]
     bop.close()
     bb.close()
+
+
+def test_destroy_waits_for_its_own_work_not_later_work_on_its_stream():
+    """A basis built and used on stream A is destroyed while products of
+    another operator, enqueued on A after that use, are still running: the
+    destroy waits for the basis's own work only."""
+    big = configs.ring32_symmetric()
+    bb = ls.ls_basis_build(big)
+    bop = ls.ls_operator_create(bb, big.terms)
+    bx = torch.from_numpy(rng.vector(11, bb.dim, complex_=bop.is_complex)).cuda()
+    by = torch.empty_like(bx)
+    sa = torch.cuda.Stream()
+    sec = _small()
+    want = _small_cycle(sec, sa)          # warm; reference results
+    b = ls.ls_basis_build(sec, stream=sa)
+    op = ls.ls_operator_create(b, sec.terms)
+    with torch.cuda.stream(sa):
+        x = torch.from_numpy(rng.vector(7, b.dim)).cuda()
+        y = op.matvec(x, stream=sa)
+    for _ in range(3):
+        bop.matvec(bx, by, stream=sa)
+    sa.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        bop.matvec(bx, by, stream=sa)
+    sa.synchronize()
+    per = (time.perf_counter() - t0) / 10
+    reps = int(min(4000, max(50, 1.5 / max(per, 1e-6))))
+    for _ in range(reps):
+        bop.matvec(bx, by, stream=sa)     # later work on the same stream
+    t1 = time.perf_counter()
+    op.close()
+    b.close()
+    busy = not sa.query()
+    t_close = time.perf_counter() - t1
+    sa.synchronize()
+    _say(f"[gpu] streams: destroy {t_close * 1e3:.1f} ms with {reps} later products queued, busy={busy}")
+    assert busy, "the destroy waited for work enqueued after the basis's own"
+    assert torch.equal(y.cpu(), want[0])
+    bop.close()
+    bb.close()
