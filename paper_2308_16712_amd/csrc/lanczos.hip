@@ -1063,16 +1063,17 @@ void solver_step(ls_solver *const *ss, uint32_t n, uint32_t steps, hipStream_t s
                     hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(32), 0, st, L);
                 }
             // products w = H v_k: a solve whose operator holds stored elements
-            // takes its stored product; the others share one fused launch, or
-            // take the single launch when alone (its tuned shape).  The row
-            // arithmetic, and so every result bit, is the same in all three.
+            // takes its stored product, a small sector its own row-group
+            // launch; the others share one fused launch, or take the single
+            // launch when alone.  Every form sums a row in term order, so
+            // every result bit is the same in all of them.
             std::vector<const ls_operator *> fops;
             std::vector<const void *> fxs;
             std::vector<void *> fys;
             for (ls_solver *s : act) {
                 const size_t es = s->cplx ? 16 : 8;
                 const void *x = static_cast<const char *>(s->V) + static_cast<size_t>(s->k) * s->n * es;
-                if (s->op->stored) {
+                if (s->op->stored || grouped_product(s->op)) {
                     launch_matvec(s->op, 1, x, s->w, st);
                 } else {
                     fops.push_back(s->op);

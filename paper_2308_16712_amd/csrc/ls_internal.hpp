@@ -280,6 +280,9 @@ uint64_t count_elements(const ls_operator *op, hipStream_t stream);
 // search runs with a compile-time shape.
 void search_kind(const ls_operator *op, uint32_t *kind, uint32_t *fixed_shape);
 void launch_matvec(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t stream);
+// Whether a single-column product of op runs in the row-group form (a small
+// sector: several lanes per row); such products are not fused.
+bool grouped_product(const ls_operator *op);
 // Push (transposed, atomic) form of the product; y is zeroed first.
 void launch_matvec_push(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t stream);
 // Stores the operator's elements (at most max_bytes); returns the bytes held.

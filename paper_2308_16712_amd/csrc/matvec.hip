@@ -46,6 +46,19 @@ k_matvec(MatvecJob a, uint64_t n_lanes, uint32_t rows_per_lane, uint32_t rows_pe
     run_rows<W, KIND, CHI, CPLX, NR, LX, LY, NZ>(a, L, lane, n_lanes, rows_per_lane);
 }
 
+// Small sectors, single column: kGroupLanes lanes per row (run_rows_group),
+// 256-thread workgroups; the tables are staged per workgroup as in k_matvec.
+constexpr int kGroupBlock = 256;
+template <typename W, int KIND, int CHI, bool CPLX, uint32_t LX, uint32_t LY, uint32_t NZ>
+__global__ void __launch_bounds__(kGroupBlock) k_matvec_group(MatvecJob a, uint64_t n_groups) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const LdsTables L = lds_tables<KIND, LX, kGroupBlock>(a, smem);
+    stage_tables<KIND, LX, kGroupBlock>(a, L);
+    __syncthreads();
+    const uint64_t group = (static_cast<uint64_t>(blockIdx.x) * kGroupBlock + threadIdx.x) / kGroupLanes;
+    run_rows_group<W, KIND, CHI, CPLX, LX, LY, NZ>(a, L, group, n_groups);
+}
+
 // Push form (comparison variant): same launch shape as k_matvec.
 template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ>
 __global__ void __launch_bounds__(block_of(KIND))
@@ -67,6 +80,10 @@ __global__ void __launch_bounds__(256) k_zero(double *y, uint64_t n) {
     const uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (i < n) y[i] = 0.0;
 }
+
+// Single-column products of sectors below this many rows take the row-group
+// form (several lanes per row).
+constexpr uint64_t group_rows_below(int kind) { return kind == kOrbitTorus ? 256ull * 1024 : 65536ull; }
 
 struct SingleLaunch {
     MatvecJob job;
@@ -91,6 +108,21 @@ struct SingleLaunch {
         const dim3 grid(static_cast<uint32_t>(lanes / wg_rows));
         const uint32_t rows_per_wg = static_cast<uint32_t>(wg_rows);
         const size_t lds = lds_bytes(KIND, job.n_terms, job.n_terms - job.n_diag, job.plan.lx);
+        // a single column of a sector with fewer rows than the GPU has lanes:
+        // several lanes per row (run_rows_group), so that each lane's chain
+        // of searches and lookups is short.  The ring searches are cheap next
+        // to the exchanges, so rings take it only below 2^16 rows (4x6 torus,
+        // 15,578 rows: 645 -> 200 us; 26-site ring, 101,340 rows: slower).
+        if constexpr (NR == 1) {
+            if (!push && job.ld == 1 && job.dim < group_rows_below(KIND)) {
+                const uint64_t groups_per_wg = kGroupBlock / kGroupLanes;
+                const uint64_t wgs = (job.dim + groups_per_wg - 1) / groups_per_wg;
+                hipLaunchKernelGGL((k_matvec_group<W, KIND, CHI, CPLX, LX, LY, NZ>),
+                                   dim3(static_cast<uint32_t>(wgs)), dim3(kGroupBlock), lds, st, job,
+                                   wgs * groups_per_wg);
+                return;
+            }
+        }
         if (push) {
             // the push form runs one column per launch
             if constexpr (NR == 1)
@@ -233,6 +265,10 @@ void launch_matvec(const ls_operator *op, uint32_t nrhs, const void *x, void *y,
         LS_HIP_CHECK(hipGetLastError());
         col += static_cast<uint32_t>(nr);
     }
+}
+
+bool grouped_product(const ls_operator *op) {
+    return !op->stored && op->basis->dim > 0 && op->basis->dim < group_rows_below(variant_of(op).kind);
 }
 
 void launch_matvec_push(const ls_operator *op, uint32_t nrhs, const void *x, void *y, hipStream_t st) {

@@ -439,6 +439,100 @@ __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L,
     }
 }
 
+// Lanes per row of the row-group form.
+constexpr int kGroupLanes = 16;
+
+// One value from lane `src` of the wavefront (all lanes must be active).
+__device__ __forceinline__ double lane_value(double v, int src) { return __shfl(v, src, 64); }
+__device__ __forceinline__ double2 lane_value(double2 v, int src) {
+    return make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+}
+
+// Rows of a small sector, kGroupLanes lanes per row (a group of consecutive
+// lanes of a wavefront).  A row's acting terms are dealt out in term order:
+// lane q of the group generates the row's acting terms number q, q + T,
+// q + 2T, ... (T = kGroupLanes).  After each round of T elements every lane
+// of the group adds the round's elements to the row's sum in term order,
+// reading them from the group's lanes, so the sum is the chain of run_rows
+// (diagonal first, then one fma per element in term order) bit for bit,
+// while each lane's chain of searches and dependent loads is T times
+// shorter.  Groups take rows group, group + n_groups, ...  Single column.
+// Every lane of a wavefront stays active through the exchanges: the loops
+// run until no lane of the wavefront has work left.
+template <typename W, int KIND, int CHI, bool CPLX, uint32_t LX, uint32_t LY, uint32_t NZ>
+__device__ __forceinline__ void run_rows_group(const MatvecJob &a, const LdsTables &L, uint64_t group,
+                                               uint64_t n_groups) {
+    constexpr bool TRACK = CHI != kChiTrivial;
+    constexpr uint32_t T = kGroupLanes;
+    using V = typename Val<CPLX>::T;
+    const V *x = static_cast<const V *>(a.x);
+    V *y = static_cast<V *>(a.y);
+    const ls_term_dev *sterm = L.terms;
+    const uint32_t q = threadIdx.x % T;
+    const int lane0 = static_cast<int>((threadIdx.x & 63u) - q);   // the group's first lane in the wavefront
+    for (uint64_t row = group;; row += n_groups) {
+        const bool live = row < a.dim;
+        if (!__any(live)) break;
+        uint64_t r = 0;
+        double st_i = 1.0;
+        V acc{};
+        W pr[kTorusCosetSlots] = {};
+        if (live) {
+            r = a.search.reps[row];
+            st_i = static_cast<double>(a.stab[row]);
+            double dre, dim_;
+            diag_sum<CPLX>(sterm, a.n_diag, r, dre, dim_);
+            acc = diag_times<CPLX>(dre, dim_, x[row * a.ld + a.col]);
+            if constexpr (KIND == kOrbitTorus) row_images<W>(a.plan, r, pr);
+        }
+        uint32_t t = a.n_diag;   // scan position
+        uint32_t seen = 0;       // acting terms passed
+        for (uint32_t round = 0;; ++round) {
+            // this lane's acting term of the round: number round * T + q
+            const uint32_t want = round * T + q;
+            bool have = false;
+            if (live) {
+                while (t < a.n_terms) {
+                    if ((r & sterm[t].sel) == sterm[t].val) {
+                        if (seen == want) break;
+                        ++seen;
+                    }
+                    ++t;
+                }
+                have = t < a.n_terms;
+            }
+            if (!__any(have)) break;
+            bool present = false;
+            V c{}, xv{};
+            if (have) {
+                uint32_t code;
+                const W rep = neighbour_rep<W, KIND, TRACK, LX, LY, NZ>(a, L, r, pr, t, code);
+                uint32_t st_j = 0;
+                const int64_t j = lookup_index_stab(a.search, static_cast<uint64_t>(rep), a.stab, st_j);
+                if (j >= 0) {
+                    c = element_value<CHI, CPLX>(sterm[t], r, st_j, st_i, a.plan, code);
+                    xv = x[static_cast<uint64_t>(j) * a.ld + a.col];
+                    present = true;
+                } else {
+                    lookup_miss<W, KIND, CHI>(a, rep);
+                }
+                ++seen;
+                ++t;
+            }
+            // the round's elements in term order: lanes q = 0 .. T-1 of the group
+#pragma unroll
+            for (uint32_t s = 0; s < T; ++s) {
+                const int src = lane0 + static_cast<int>(s);
+                const bool ps = __shfl(present ? 1 : 0, src, 64) != 0;
+                const V cs = lane_value(c, src);
+                const V xs = lane_value(xv, src);
+                if (ps) accumulate(acc, cs, xs);
+            }
+        }
+        if (live && q == 0) y[row * a.ld + a.col] = acc;
+    }
+}
+
 // y_j += conj(v) x_i with device-scope atomic adds (push form)
 __device__ __forceinline__ void scatter_add(double *y, double v, double xi) { unsafeAtomicAdd(y, v * xi); }
 __device__ __forceinline__ void scatter_add(double2 *y, double2 v, double2 xi) {
