@@ -237,3 +237,36 @@ def test_chunked_steps_match_single_steps(steps):
     assert rounds < max(r.result()["iters"] for r in single)
     for h in single + chunked + ops:
         h.close()
+
+
+def test_breakdown_inside_a_chunk_stops_where_single_steps_stop():
+    """A start vector that spans an invariant subspace: a basis state under a
+    diagonal (Ising) Hamiltonian, so w = H v - alpha v is exactly zero and
+    beta_1 = 0.  ls_lanczos (chunks of 32 steps), ls_solver_step_n and single
+    steps all stop after one step with alpha_1 = the state's diagonal
+    element (the oracle's), although the chunks compute further steps on a
+    0/0 vector and discard them."""
+    n = 12
+    bonds = lattice.ring_bonds(n, 1.0, 0.4)
+    zz = terms.make_terms([(0.25 * J, 0, 0, 0, (1 << i) | (1 << j)) for i, j, J in bonds])
+    sec = configs.sector_from_arrays("ring12_ising", n, n // 2, lattice.trivial_group(n).perm,
+                                     lattice.trivial_group(n).flip, lattice.trivial_group(n).chi, zz)
+    b = ls.ls_basis_build(sec)
+    op = ls.ls_operator_create(b, sec.terms)
+    P = oracle.Problem(sec)
+    reps, stab = oracle.enumerate_basis(P)
+    e = np.zeros(len(reps))
+    e[5] = 1.0
+    d5 = float(oracle.matvec(P, reps, stab, e)[5])
+    v0 = torch.from_numpy(e).cuda()
+    res = op.lanczos(50, tol=0.0, v0=v0)
+    assert res["iters"] == 1 and res["alpha"].tolist() == [d5] and res["e0"] == d5
+    for steps in (1, 8):
+        s = ls.Solver(op, 50, v0=v0)
+        while not s.result()["done"]:
+            ls.Solver.step_all([s], steps=steps)
+        r = s.result()
+        assert r["iters"] == 1 and r["e0"] == d5 and not r["converged"], (steps, r)
+        s.close()
+    op.close()
+    b.close()
