@@ -343,6 +343,48 @@ def serving(count: int, rate: float, budget_gb: float, max_iter: int, tol: float
     return out
 
 
+def lookups(basis, sector, n_states: int = 1 << 22, reps_timed: int = 3):
+    """ls_state_info on seeded random states of the sector's weight (orbit
+    minimum, character and norm of each) and ls_index_lookup of every
+    representative (stateToIndex), timed on the launch stream."""
+    import torch
+    import paper_2308_16712_amd as ls
+
+    n = sector.n_sites
+    w = max(sector.weight, 0)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(17)
+    # a random weight-w state: the sites of the w smallest of n uniform draws
+    pos = torch.rand(n_states, n, device="cuda", generator=g).argsort(dim=1)[:, :w]
+    states = (torch.ones_like(pos) << pos).sum(dim=1)
+    del pos
+    reps, _ = basis.copy()
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        best = 1e30
+        for _ in range(reps_timed):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        return best
+
+    ls.ls_state_info(basis, states)
+    ms_si = timed(lambda: ls.ls_state_info(basis, states))
+    idx = ls.ls_index_lookup(basis, reps)
+    ok = bool(torch.equal(idx, torch.arange(basis.dim, device="cuda")))
+    ms_lu = timed(lambda: ls.ls_index_lookup(basis, reps))
+    return {"state_info": {"states": n_states, "ms": ms_si, "states_per_s": n_states / (ms_si * 1e-3),
+                           "what": "orbit minimum, character of the element reaching it and norm, per state"},
+            "index_lookup": {"keys": basis.dim, "ms": ms_lu, "keys_per_s": basis.dim / (ms_lu * 1e-3),
+                             "every_representative_found_at_its_index": ok}}
+
+
 def push_product(op, x, pull_ms: float, elements: int, steps: int):
     """The push (transposed, atomic-add) form of the same product on the same
     input: time per product on the launch stream, and its distance from the
@@ -739,6 +781,7 @@ def main():
         "copy_peak": cp,
     }
     op.check()
+    out["state_info_and_lookup"] = lookups(basis, sector)
     if not args.no_push:
         print("[bench] push form", file=sys.stderr, flush=True)
         out["push"] = push_product(op, x, kernel_ms, elements, args.steps)
