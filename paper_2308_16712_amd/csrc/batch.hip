@@ -620,7 +620,8 @@ void batch_search(const ls_batch *B, uint32_t item, uint32_t *mode, uint32_t *bi
 // there is no graph and no tuning here: tiles use the tuned parameters of a
 // matching batch when the cache has them, else 4 rows per lane and as many
 // workgroups per CU as occupancy allows.  Device tables grow by doubling and
-// are reused.
+// are reused; the state lives until the process ends (the stepper holds
+// one, under its lock).
 
 struct FusedState {
     std::vector<Group> groups;
@@ -634,16 +635,6 @@ FusedState *fused_create() {
     if (hipGetDevice(&dev) == hipSuccess)
         hipDeviceGetAttribute(&f->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     return f;
-}
-
-void fused_destroy(FusedState *f) {
-    if (!f) return;
-    for (auto &g : f->groups) {
-        hipFree(g.d_jobs);
-        hipFree(g.d_tiles);
-        hipFree(g.d_counter);
-    }
-    delete f;
 }
 
 namespace {

@@ -302,7 +302,6 @@ void batch_search(const ls_batch *b, uint32_t item, uint32_t *mode, uint32_t *bi
 // fused products over a changing set of operators (batch.hip)
 struct FusedState;
 FusedState *fused_create();
-void fused_destroy(FusedState *f);
 // Host bytes of uploads enqueued before a synchronisation, kept alive (and
 // unchanged) until it: the copies read them in stream order.
 using HostKeep = std::vector<std::vector<unsigned char>>;
