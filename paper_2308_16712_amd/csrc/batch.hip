@@ -619,7 +619,8 @@ void batch_search(const ls_batch *B, uint32_t item, uint32_t *mode, uint32_t *bi
 // The set of products changes from call to call (solves join and leave), so
 // there is no graph and no tuning here: tiles use the tuned parameters of a
 // matching batch when the cache has them, else 4 rows per lane and as many
-// workgroups per CU as occupancy allows.  Device tables grow by doubling and
+// workgroups per CU as occupancy allows; a group with few rows in all takes
+// one row per lane in tiles of whole waves, spread over every workgroup.  Device tables grow by doubling and
 // are reused; the state lives until the process ends (the stepper holds
 // one, under its lock).
 
