@@ -264,7 +264,11 @@ ls_status ls_operator_search_kind(const ls_operator *op, uint32_t *kind, uint32_
 
 /* y = H x (Section 5.3, the first listing's row-by-row ("pull") form: each
  * row's elements are generated from its representative, looked up, and
- * accumulated; no atomics, since H is Hermitian).
+ * accumulated; no atomics, since H is Hermitian).  Each row is summed in
+ * term order, diagonal first, whatever the launch shape: a single column of
+ * a small sector (below 2^18 rows on tori, 2^16 otherwise) gives each row
+ * several lanes that generate its elements in parallel and add them in that
+ * order, so the results are the same bits as the one-lane form.
  *   nrhs   1..64 right-hand sides.
  *   d_x    device [dim][nrhs], row-major; double, or complex128 as (re, im)
  *          pairs when the operator is complex.  (in)
@@ -407,10 +411,12 @@ ls_status ls_lanczos(const ls_operator *op, const ls_lanczos_opts *opts, void *s
  * and arithmetic of ls_lanczos) with its Krylov vectors resident in HBM.
  * ls_solver_step advances every listed solver that is not done by one
  * iteration: the products of several solves run as one fused launch (the
- * batched kernel; a single solve takes ls_matvec's launch; a solve whose
- * operator holds stored elements takes its stored product), alpha and beta
- * stay on the device, and the step ends with one synchronisation.  A solve stepped alone or among others produces the same
- * numbers.  Calls to ls_solver_step are serialised inside the library.     */
+ * batched kernel; a single solve takes ls_matvec's launch, as does a solve
+ * on a small sector, whose rows ls_matvec spreads over several lanes each;
+ * a solve whose operator holds stored elements takes its stored product),
+ * alpha and beta stay on the device, and the step ends with one
+ * synchronisation.  A solve stepped alone or among others produces the same
+ * numbers.  Calls to ls_solver_step(_n) are serialised inside the library. */
 typedef struct ls_solver ls_solver;
 
 /* Device bytes a solver for `op` with `max_iter` steps allocates.          */
