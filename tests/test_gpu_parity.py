@@ -483,3 +483,45 @@ def test_full_chain40_paper_workload():
     finally:
         b.close()
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("name", ["torus6x6_w8_full", "ring22_w11_k5"])
+def test_row_group_form_near_its_size_limit(name):
+    """Single-column products of small sectors run in the row-group form
+    (several lanes per row).  Near the largest sizes that take it -- a 6x6
+    torus sector of 105k rows, a 22-site ring sector of 32k rows -- the
+    whole representative list is checked by the oracle, the product matches
+    the oracle on sampled rows, and it equals bit for bit the batched launch,
+    which sums every row in one lane."""
+    sec = {
+        "torus6x6_w8_full": lambda: _sector("torus6x6_w8_full", 36, 8, lattice.torus_group(6, 6),
+                                           lattice.torus_bonds(6, 6, 1.0, 0.5)),
+        "ring22_w11_k5": lambda: _sector("ring22_w11_k5", 22, 11, lattice.ring_group(22, 5),
+                                         lattice.ring_bonds(22, 1.0, 0.35)),
+    }[name]()
+    _say(f"[gpu] row-group form near its limit: {name}")
+    b = ls.ls_basis_build(sec)
+    reps_t, stab_t = b.copy()
+    reps = _u64(reps_t)
+    stab = stab_t.cpu().numpy().view(np.uint16)
+    P = oracle.Problem(sec)
+    assert b.dim == ref.character_dimension(sec.group, sec.weight)    # with the list check: set equality
+    _whole_list_check(P, sec, reps, stab)
+    op = ls.ls_operator_create(b, sec.terms)
+    x = rng.state_values(13, reps, complex_=op.is_complex)
+    xt = torch.from_numpy(x).cuda()
+    y = op.matvec(xt)
+    op.check()
+    batch = ls.Batch([op], [1], search="own")
+    yb = torch.empty_like(xt)
+    batch.matvec([xt], [yb])
+    torch.cuda.synchronize()
+    assert torch.equal(y, yb)
+    d = b.dim
+    rows = np.unique(np.concatenate([
+        (rng.counter_u64(9, np.arange(3000, dtype=np.uint64)) % np.uint64(d)).astype(np.int64),
+        np.array([0, d - 1], dtype=np.int64)]))
+    _rows_check(P, reps, y.cpu().numpy(), rows, 13, op.is_complex)
+    batch.close()
+    op.close()
+    b.close()
