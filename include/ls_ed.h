@@ -108,8 +108,8 @@ typedef struct {
  * products (stateToIndex, Section 5.3): a hash index of 16-byte slots
  * (key, index, stabilizer size; linear probing from the key's Fibonacci
  * hash, the top bits of key * 0x9E3779B97F4A7C15; load factor at most 1/8
- * while the table fits 8 GiB, else the lowest of 1/4, 1/2, 3/4 that fits
- * 64 GiB), or, where it would pass 64 GiB or the
+ * while the table fits 8 GiB, else 1/4 within 64 GiB, else 1/2 or 3/4
+ * within 128 GiB), or, where it would pass 128 GiB or the
  * environment variable LS_ED_SEARCH is "buckets" at build time, a bucket
  * table over the keys' high bits with binary search in reps.  A group of
  * one element needs neither (colex rank, or the state itself).

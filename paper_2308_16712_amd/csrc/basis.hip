@@ -488,15 +488,17 @@ uint64_t host_binom(uint32_t n, uint32_t k) {
 
 // Binomial table and the compiled group in device memory (PlanDev).
 // Slots of the hash index, a power of two: load factor at most 1/8 while the
-// table fits 8 GiB, else the lowest of 1/4, 1/2, 3/4 that fits 64 GiB; 0
-// above that.  A sparse table makes a second probe (a second dependent
+// table fits 8 GiB, else 1/4 within 64 GiB, else 1/2 or 3/4 within 128 GiB;
+// 0 above that.  A sparse table makes a second probe (a second dependent
 // memory round trip) rare: load 1/2 -> 1/8 took the 6x6 product from 40.0 to
-// 36.7 ms, load 0.4 -> 0.2 the 40-spin chain product from 442 to 421 ms.
+// 36.7 ms, load 0.4 -> 0.2 the 40-spin chain product from 442 to 421 ms, and
+// load 0.75 -> 0.37 (a 128 GiB table) the 42-spin chain product from 2425
+// to 1756 ms.
 uint64_t hash_capacity(uint64_t dim) {
     struct Tier {
         uint64_t num, den, limit;   // slots >= dim * num / den while slots * 16 <= limit
     };
-    const Tier tiers[] = {{8, 1, 8ULL << 30}, {4, 1, 64ULL << 30}, {2, 1, 64ULL << 30}, {4, 3, 64ULL << 30}};
+    const Tier tiers[] = {{8, 1, 8ULL << 30}, {4, 1, 64ULL << 30}, {2, 1, 128ULL << 30}, {4, 3, 128ULL << 30}};
     for (const Tier &t : tiers) {
         uint64_t cap = 1024;
         while (cap * t.den < t.num * dim) cap <<= 1;
@@ -751,7 +753,7 @@ void build_basis(ls_basis *b, hipStream_t st) {
         }
         S.kmin = kmin;
         S.kmax = kmax;
-        // Hash index (hash_capacity); when it would pass 64 GiB, or when asked
+        // Hash index (hash_capacity); when it would pass 128 GiB, or when asked
         // for, the bucket search.
         const char *env = std::getenv("LS_ED_SEARCH");
         const bool want_buckets = env != nullptr && std::string(env) == "buckets";

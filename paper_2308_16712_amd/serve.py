@@ -72,10 +72,10 @@ def sector_dimension(sector) -> int:
 
 def _search_bytes(dim: int) -> int:
     """Hash index of the basis build: 16-byte slots, a power of two with load
-    factor at most 1/8 while the table fits 8 GiB, else the lowest of 1/4,
-    1/2, 3/4 that fits 64 GiB (the library's hash_capacity); above that the
-    bucket table (at most 2^22 + 1 four-byte offsets)."""
-    for num, den, limit in ((8, 1, 8 << 30), (4, 1, 64 << 30), (2, 1, 64 << 30), (4, 3, 64 << 30)):
+    factor at most 1/8 while the table fits 8 GiB, else 1/4 within 64 GiB,
+    else 1/2 or 3/4 within 128 GiB (the library's hash_capacity); above that
+    the bucket table (at most 2^22 + 1 four-byte offsets)."""
+    for num, den, limit in ((8, 1, 8 << 30), (4, 1, 64 << 30), (2, 1, 128 << 30), (4, 3, 128 << 30)):
         cap = 1024
         while cap * den < num * dim:
             cap *= 2

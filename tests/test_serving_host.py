@@ -55,15 +55,16 @@ def test_step_policy():
 
 def test_search_bytes_follow_the_hash_tiers():
     """Admission sizes the hash index as the library does: load at most 1/8
-    while the table fits 8 GiB, else the lowest of 1/4, 1/2, 3/4 within
-    64 GiB, else the bucket table."""
+    while the table fits 8 GiB, else 1/4 within 64 GiB, else 1/2 or 3/4
+    within 128 GiB, else the bucket table."""
     gib = 1 << 30
     assert serve._search_bytes(15804956) == (1 << 27) * 16            # 6x6: 2 GiB at load 0.12
     assert serve._search_bytes(63068876) == (1 << 29) * 16            # ring 36: exactly 8 GiB
     assert serve._search_bytes(134217729) == (1 << 30) * 16           # 2^27 + 1: 1/4 tier, 16 GiB
     assert serve._search_bytes(861725794) == (1 << 32) * 16           # 40-spin chain: 64 GiB at 0.2
-    assert serve._search_bytes(3204236779) == (1 << 32) * 16          # 42-spin chain: 3/4 tier
-    assert serve._search_bytes(4 * 10 ** 9) < gib                     # beyond 64 GiB: bucket table
+    assert serve._search_bytes(3204236779) == (1 << 33) * 16          # 42-spin chain: 1/2 tier, 128 GiB
+    assert serve._search_bytes(5 * 10 ** 9) == (1 << 33) * 16         # 3/4 tier, 128 GiB
+    assert serve._search_bytes(7 * 10 ** 9) < gib                     # beyond 128 GiB: bucket table
     for dim in (1, 1000, 10 ** 6, 10 ** 8, 2 * 10 ** 9):
         b = serve._search_bytes(dim)
         if b >= 1024 * 16:
