@@ -1014,7 +1014,12 @@ void solver_step(ls_solver *const *ss, uint32_t n, uint32_t steps, hipStream_t s
         c = std::min(c, s->m - s->k);   // k < m while a solve is not done
     }
     const size_t A = act.size();
-    const bool batched = A >= 2;
+    // the batched after-product kernels (one launch per kernel whatever the
+    // Krylov dimension) also serve a lone small solve, whose step is bound by
+    // launches (4x6 torus 0.38 -> 0.36 ms per step, 24-site ring 0.29 -> 0.26
+    // ms); a large lone solve keeps the single kernels (32-site ring: 3.69 ms
+    // against 4.10 ms batched).  Both give the same bits.
+    const bool batched = A >= 2 || act[0]->n < (1ull << 21);
     std::vector<uint32_t> k0(A);
     for (size_t a = 0; a < A; ++a) k0[a] = act[a]->k;
     // operators' lookup-miss flags (cleared before each batched step's products)
