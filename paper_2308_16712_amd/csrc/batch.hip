@@ -470,7 +470,7 @@ static void batch_prepare(ls_batch *B, hipStream_t st) {
         const ls_operator *op = B->ops[i];
         const int kind = variant_of(op).kind;
         const size_t own = lds_bytes(kind, op->n_diag + op->n_off, op->n_off, op->basis->plan.lx) +
-                           static_lds_bytes(kind);
+                           (kind == kOrbitTorus ? kPairTableBytes : 0);
         const size_t fr = own + 16 <= kMaxLds ? kMaxLds - own - 16 : 0;
         auto it = lds_free.find(op->basis);
         if (it == lds_free.end()) lds_free.emplace(op->basis, fr);

@@ -226,7 +226,7 @@ Variant variant_of(const ls_operator *op) {
     v.cplx = op->is_complex;
     v.chi = op->is_complex ? kChiComplex : gp.chi_mode;
     const bool torus = gp.torus && op->d_cflip != nullptr &&
-                       lds_bytes(kOrbitTorus, op->n_diag + op->n_off, op->n_off, gp.lx) + static_lds_bytes(kOrbitTorus) <= kMaxLds;
+                       lds_bytes(kOrbitTorus, op->n_diag + op->n_off, op->n_off, gp.lx) + kPairTableBytes <= kMaxLds;
     if (!v.word64 && gp.ly == 1 && gp.lx == gp.n_sites) {
         v.kind = kOrbitRing32;
     } else if (v.word64 && gp.ly == 1 && gp.lx == gp.n_sites && gp.n_sites < 64) {

@@ -86,11 +86,11 @@ __device__ __forceinline__ typename Val<CPLX>::T diag_times(double dre, double d
 }
 
 // Element value conj(c_t) (-1)^popcount(r & sign_t) chi(g*) sqrt(stab_j / stab_i)
-// (the term table already holds conj(c_t)); fs = sqrt(stab_j / stab_i).
+// (the term table already holds conj(c_t)).
 template <int CHI, bool CPLX>
-__device__ __forceinline__ typename Val<CPLX>::T element_value(const ls_term_dev &Tm, uint64_t r, double fs,
-                                                               const PlanDev &P, uint32_t code) {
-    const double f = sign_of(r & Tm.sign) * fs;
+__device__ __forceinline__ typename Val<CPLX>::T element_value(const ls_term_dev &Tm, uint64_t r, uint32_t st_j,
+                                                               double st_i, const PlanDev &P, uint32_t code) {
+    const double f = sign_of(r & Tm.sign) * __dsqrt_rn(__ddiv_rn(static_cast<double>(st_j), st_i));
     if constexpr (!CPLX) {
         double coef = f * Tm.re;
         if constexpr (CHI == kChiReal) coef *= P.chi[code].x;
@@ -134,38 +134,17 @@ __host__ __device__ inline size_t lds_bytes(int kind, uint32_t n_terms, uint32_t
 // Static LDS of the torus kernels.
 constexpr size_t kPairTableBytes = kPairTableEntries * sizeof(uint32_t);
 
-// Static LDS of a kernel of this kind: the pair table of the torus search,
-// the stabilizer-ratio table of the others.  The torus kernels divide and
-// take the square root per element instead: there the table gains 0.5% (6x6
-// product), and its 5.6 KB would come out of the LDS the batched launch
-// leaves for a staged bucket table beside the torus tables; in the ring
-// kernels, whose LDS is otherwise idle, it takes 6% off the product.
-constexpr size_t static_lds_bytes(int kind) {
-    return kind == kOrbitTorus ? kPairTableBytes : kStabTableBytes;
-}
-
 struct LdsTables {
     ls_term_dev *terms;
     uint32_t *lut;
     uint64_t *col;
     uint64_t *cflip;   // [slot][n_off]
     uint32_t *bkt;     // staged bucket table (kLookupStaged)
-    uint8_t *scls;     // class of every stabilizer size
-    double *sratio;    // sqrt(d_b / d_a) by classes
 };
 
 template <int KIND, uint32_t LX, int BLOCK>
 __device__ __forceinline__ LdsTables lds_tables(const MatvecJob &a, unsigned char *smem) {
     LdsTables L;
-    if constexpr (KIND != kOrbitTorus) {
-        __shared__ __align__(8) double stab_ratio[kStabClsMax * kStabClsMax];
-        __shared__ __align__(8) uint8_t stab_cls[kStabMapBytes];
-        L.scls = stab_cls;
-        L.sratio = stab_ratio;
-    } else {
-        L.scls = nullptr;
-        L.sratio = nullptr;
-    }
     if constexpr (KIND == kOrbitTorus) {
         __shared__ uint32_t pair_table[kPairTableEntries];
         L.lut = pair_table;
@@ -199,47 +178,6 @@ __device__ __forceinline__ void stage_tables(const MatvecJob &a, const LdsTables
     }
     if (a.search.mode == kLookupStaged)
         for (uint32_t q = threadIdx.x; q < a.search.n_bkt; q += BLOCK) L.bkt[q] = a.search.buckets[q];
-    if (KIND != kOrbitTorus && a.plan.n_stab_cls) {
-        const uint32_t *cw = reinterpret_cast<const uint32_t *>(a.plan.stab_cls);
-        uint32_t *lw = reinterpret_cast<uint32_t *>(L.scls);
-        for (uint32_t q = threadIdx.x; q < kStabMapBytes / 4; q += BLOCK) lw[q] = cw[q];
-        for (uint32_t q = threadIdx.x; q < a.plan.n_stab_cls * a.plan.n_stab_cls; q += BLOCK)
-            L.sratio[q] = a.plan.stab_ratio[q];
-    }
-}
-
-// The row's part of the element normalisation: its stabilizer size, and the
-// offset of its class's row of the ratio table (torus kernels: the size).
-template <int KIND>
-struct RowStab {
-    uint32_t st;
-    uint32_t base;
-};
-template <>
-struct RowStab<kOrbitTorus> {
-    double st;
-};
-
-template <int KIND>
-__device__ __forceinline__ RowStab<KIND> row_stab(const PlanDev &P, const LdsTables &L, uint32_t st) {
-    if constexpr (KIND == kOrbitTorus) {
-        return RowStab<KIND>{static_cast<double>(st)};
-    } else {
-        return RowStab<KIND>{st, P.n_stab_cls ? static_cast<uint32_t>(L.scls[st]) * P.n_stab_cls : 0u};
-    }
-}
-
-// sqrt(stab_j / stab_i), correctly rounded: read from the ratio table when
-// the kernel and the group have one, else divided and rooted (the same bits).
-template <int KIND>
-__device__ __forceinline__ double stab_factor(const PlanDev &P, const LdsTables &L, const RowStab<KIND> &R,
-                                              uint32_t st_j) {
-    if constexpr (KIND == kOrbitTorus) {
-        return __dsqrt_rn(__ddiv_rn(static_cast<double>(st_j), R.st));
-    } else {
-        if (P.n_stab_cls) return L.sratio[R.base + L.scls[st_j]];
-        return __dsqrt_rn(__ddiv_rn(static_cast<double>(st_j), static_cast<double>(R.st)));
-    }
 }
 
 // Sum of the diagonal terms acting on r: dre + i dim_.
@@ -337,14 +275,14 @@ __device__ __forceinline__ void run_rows_ahead(const MatvecJob &a, const LdsTabl
     if (count == 0 || row >= a.dim) return;
 
     uint64_t r = 0;
-    RowStab<KIND> rs{};
+    double st_i = 1.0;
     T acc[NR];
     uint32_t t = a.n_diag;
     W pr[kTorusCosetSlots] = {};   // unused by these searches
 
     auto begin_row = [&]() {
         r = a.search.reps[row];
-        rs = row_stab<KIND>(a.plan, L, a.stab[row]);
+        st_i = static_cast<double>(a.stab[row]);
         double dre, dim_;
         diag_sum<CPLX>(sterm, a.n_diag, r, dre, dim_);
 #pragma unroll
@@ -406,7 +344,7 @@ __device__ __forceinline__ void run_rows_ahead(const MatvecJob &a, const LdsTabl
                 j = lookup_stab<STAGED>(a, L, p_rep, st_j);
             }
             if (j >= 0) {
-                const T c = element_value<CHI, CPLX>(sterm[p_t], r, stab_factor(a.plan, L, rs, st_j), a.plan, p_code);
+                const T c = element_value<CHI, CPLX>(sterm[p_t], r, st_j, st_i, a.plan, p_code);
 #pragma unroll
                 for (int q = 0; q < NR; ++q) accumulate(acc[q], c, x[j * a.ld + a.col + q]);
             } else {
@@ -459,14 +397,14 @@ __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L,
     if (count == 0 || row >= a.dim) return;
 
     uint64_t r = 0;
-    RowStab<KIND> rs{};
+    double st_i = 1.0;
     T acc[NR];
     uint32_t t = a.n_diag;
     W pr[kTorusCosetSlots] = {};   // p(r) for every coset (torus search)
 
     auto begin_row = [&]() {
         r = a.search.reps[row];
-        rs = row_stab<KIND>(a.plan, L, a.stab[row]);
+        st_i = static_cast<double>(a.stab[row]);
         double dre, dim_;
         diag_sum<CPLX>(sterm, a.n_diag, r, dre, dim_);
 #pragma unroll
@@ -497,7 +435,7 @@ __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L,
             lookup_miss<W, KIND, CHI>(a, rep);
             continue;
         }
-        const T c = element_value<CHI, CPLX>(Tm, r, stab_factor(a.plan, L, rs, st_j), a.plan, code);
+        const T c = element_value<CHI, CPLX>(Tm, r, st_j, st_i, a.plan, code);
 #pragma unroll
         for (int q = 0; q < NR; ++q) accumulate(acc[q], c, x[j * a.ld + a.col + q]);
     }
@@ -538,12 +476,12 @@ __device__ __forceinline__ void run_rows_group(const MatvecJob &a, const LdsTabl
         const bool live = row < a.dim;
         if (!__any(live)) break;
         uint64_t r = 0;
-        RowStab<KIND> rs{};
+        double st_i = 1.0;
         V acc{};
         W pr[kTorusCosetSlots] = {};
         if (live) {
             r = a.search.reps[row];
-            rs = row_stab<KIND>(a.plan, L, a.stab[row]);
+            st_i = static_cast<double>(a.stab[row]);
             double dre, dim_;
             diag_sum<CPLX>(sterm, a.n_diag, r, dre, dim_);
             acc = diag_times<CPLX>(dre, dim_, x[row * a.ld + a.col]);
@@ -574,7 +512,7 @@ __device__ __forceinline__ void run_rows_group(const MatvecJob &a, const LdsTabl
                 uint32_t st_j = 0;
                 const int64_t j = lookup_index_stab(a.search, static_cast<uint64_t>(rep), a.stab, st_j);
                 if (j >= 0) {
-                    c = element_value<CHI, CPLX>(sterm[t], r, stab_factor(a.plan, L, rs, st_j), a.plan, code);
+                    c = element_value<CHI, CPLX>(sterm[t], r, st_j, st_i, a.plan, code);
                     xv = x[static_cast<uint64_t>(j) * a.ld + a.col];
                     present = true;
                 } else {
@@ -620,7 +558,7 @@ __device__ __forceinline__ void push_rows(const MatvecJob &a, const LdsTables &L
     uint64_t row = row0;
     for (uint32_t k = 0; k < count && row < a.dim; ++k, row += step) {
         const uint64_t r = a.search.reps[row];
-        const RowStab<KIND> rs = row_stab<KIND>(a.plan, L, a.stab[row]);
+        const double st_i = static_cast<double>(a.stab[row]);
         T xi[NR];
 #pragma unroll
         for (int q = 0; q < NR; ++q) xi[q] = x[row * a.ld + a.col + q];
@@ -649,7 +587,7 @@ __device__ __forceinline__ void push_rows(const MatvecJob &a, const LdsTables &L
                 lookup_miss<W, KIND, CHI>(a, rep);
                 continue;
             }
-            const T v = element_value<CHI, CPLX>(Tm, r, stab_factor(a.plan, L, rs, st_j), a.plan, code);
+            const T v = element_value<CHI, CPLX>(Tm, r, st_j, st_i, a.plan, code);
 #pragma unroll
             for (int q = 0; q < NR; ++q) scatter_add(&y[static_cast<uint64_t>(j) * a.ld + a.col + q], v, xi[q]);
         }
