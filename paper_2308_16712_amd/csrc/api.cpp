@@ -113,6 +113,7 @@ void free_basis(ls_basis *b) {
     ls::dev_free(b->d_chi);
     ls::dev_free(b->d_chi_one);
     ls::dev_free(b->d_pair_lut);
+    ls::dev_free(b->d_stab_tab);
     delete b;
 }
 

@@ -539,6 +539,32 @@ void fill_plan_dev(const GroupPlan &gp, PlanDev &pd) {
     pd.col0 = gp.col0;
     pd.pair_lut = nullptr;
     for (int a = 0; a < 8; ++a) pd.col_ge[a] = gp.col_ge[a];
+    pd.n_stab_cls = 0;
+    pd.stab_cls = nullptr;
+    pd.stab_ratio = nullptr;
+}
+
+// Stabilizer-ratio table of a group: the class of every divisor of |G|
+// (0xFF for the other sizes) followed, at offset kStabMapBytes, by the
+// correctly rounded sqrt(d_b / d_a) over pairs of divisors (IEEE division
+// and square root, the bits the kernels' own division and square root give).
+// Empty when |G| or its number of divisors is above the table's limits.
+std::vector<unsigned char> stab_table(uint32_t ng, uint32_t &n_cls) {
+    n_cls = 0;
+    if (ng > kStabMapMax) return {};
+    std::vector<uint32_t> div;
+    for (uint32_t d = 1; d <= ng; ++d)
+        if (ng % d == 0) div.push_back(d);
+    if (div.size() > kStabClsMax) return {};
+    const uint32_t nd = static_cast<uint32_t>(div.size());
+    std::vector<unsigned char> t(kStabMapBytes + static_cast<size_t>(nd) * nd * sizeof(double), 0xFF);
+    for (uint32_t c = 0; c < nd; ++c) t[div[c]] = static_cast<unsigned char>(c);
+    double *r = reinterpret_cast<double *>(t.data() + kStabMapBytes);
+    for (uint32_t a = 0; a < nd; ++a)
+        for (uint32_t c = 0; c < nd; ++c)
+            r[a * nd + c] = std::sqrt(static_cast<double>(div[c]) / static_cast<double>(div[a]));
+    n_cls = nd;
+    return t;
 }
 
 }  // namespace
@@ -566,6 +592,16 @@ void upload_plan(ls_basis *b, hipStream_t st) {
         LS_HIP_CHECK(hipMemcpyAsync(b->d_pair_lut, gp.pair_lut.data(), gp.pair_lut.size() * sizeof(uint32_t),
                                     hipMemcpyHostToDevice, st));
         pd.pair_lut = b->d_pair_lut;
+    }
+    uint32_t n_cls = 0;
+    const std::vector<unsigned char> stab = stab_table(gp.n_elements, n_cls);
+    if (n_cls) {
+        unsigned char *d = dev_alloc_n<unsigned char>(stab.size(), st);
+        b->d_stab_tab = d;
+        LS_HIP_CHECK(hipMemcpyAsync(d, stab.data(), stab.size(), hipMemcpyHostToDevice, st));
+        pd.n_stab_cls = n_cls;
+        pd.stab_cls = d;
+        pd.stab_ratio = reinterpret_cast<const double *>(d + kStabMapBytes);
     }
     // the host tables are released on return: the copies complete first
     LS_HIP_CHECK(hipStreamSynchronize(st));

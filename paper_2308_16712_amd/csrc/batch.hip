@@ -56,8 +56,8 @@ __global__ void __launch_bounds__(batch_block(KIND, CPLX))
         const uint32_t jid = __builtin_amdgcn_readfirstlane(T.job);
         const MatvecJob &a = jobs[jid];
         if (jid != cur) {
-            L = lds_tables<KIND, LX, BLOCK>(a, smem);
-            stage_tables<KIND, LX, BLOCK>(a, L);
+            L = lds_tables<KIND, LX, BLOCK, false>(a, smem);
+            stage_tables<KIND, LX, BLOCK, false>(a, L);
             __syncthreads();
             cur = jid;
         }

@@ -141,7 +141,21 @@ struct PlanDev {
     const uint32_t *chi_one;    // device bitset, by code
     const uint32_t *pair_lut;   // device, torus pruning table (or null)
     uint64_t col_ge[8];
+    // Stabilizer-ratio table (0 classes = none): stab_cls[s] is the class of
+    // the divisor s of |G|, stab_ratio[a * n_stab_cls + b] the correctly
+    // rounded sqrt(d_b / d_a) of classes a and b.
+    uint32_t n_stab_cls, pad_;
+    const uint8_t *stab_cls;    // device [kStabMapBytes]
+    const double *stab_ratio;   // device [n_stab_cls][n_stab_cls]
 };
+
+// Stabilizer sizes divide |G|, so the normalisation sqrt(stab_j / stab_i) of
+// an element takes one of a few values: groups of at most kStabMapMax
+// elements with at most kStabClsMax divisors get the table above, which the
+// kernels that use it stage in LDS.
+constexpr uint32_t kStabClsMax = 24;
+constexpr uint32_t kStabMapMax = 1024;
+constexpr size_t kStabMapBytes = kStabMapMax + 8;
 
 // kLookupStaged: the bucket search with its bucket table staged in LDS by
 // every workgroup (a layout the batched launch may pick; never built by a
@@ -203,6 +217,7 @@ struct ls_basis {
     double2 *d_chi = nullptr;
     uint32_t *d_chi_one = nullptr;
     uint32_t *d_pair_lut = nullptr;
+    void *d_stab_tab = nullptr;
     ls::PlanDev plan_dev{};
     ls::SearchDev search_dev{};
 };

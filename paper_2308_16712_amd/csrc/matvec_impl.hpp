@@ -86,11 +86,11 @@ __device__ __forceinline__ typename Val<CPLX>::T diag_times(double dre, double d
 }
 
 // Element value conj(c_t) (-1)^popcount(r & sign_t) chi(g*) sqrt(stab_j / stab_i)
-// (the term table already holds conj(c_t)).
+// (the term table already holds conj(c_t)); fs = sqrt(stab_j / stab_i).
 template <int CHI, bool CPLX>
-__device__ __forceinline__ typename Val<CPLX>::T element_value(const ls_term_dev &Tm, uint64_t r, uint32_t st_j,
-                                                               double st_i, const PlanDev &P, uint32_t code) {
-    const double f = sign_of(r & Tm.sign) * __dsqrt_rn(__ddiv_rn(static_cast<double>(st_j), st_i));
+__device__ __forceinline__ typename Val<CPLX>::T element_value(const ls_term_dev &Tm, uint64_t r, double fs,
+                                                               const PlanDev &P, uint32_t code) {
+    const double f = sign_of(r & Tm.sign) * fs;
     if constexpr (!CPLX) {
         double coef = f * Tm.re;
         if constexpr (CHI == kChiReal) coef *= P.chi[code].x;
@@ -134,17 +134,37 @@ __host__ __device__ inline size_t lds_bytes(int kind, uint32_t n_terms, uint32_t
 // Static LDS of the torus kernels.
 constexpr size_t kPairTableBytes = kPairTableEntries * sizeof(uint32_t);
 
+// Kernels that read the element normalisation from the stabilizer-ratio
+// table (5.6 KB of static LDS): the single launches of the ring and generic
+// searches, whose LDS is otherwise idle (N=32 ring product 2.04 -> 1.92 ms).
+// The others divide and take the square root per element: in the torus
+// kernels the table gains 0.5% (6x6 product) for LDS a staged bucket table
+// could use, and it costs the persistent batched launch an occupancy step
+// (complex ring columns 94 -> 99 VGPRs, 5 -> 4 waves per SIMD).
+constexpr bool uses_ratio_table(int kind, bool batched) { return kind != kOrbitTorus && !batched; }
+
 struct LdsTables {
     ls_term_dev *terms;
     uint32_t *lut;
     uint64_t *col;
     uint64_t *cflip;   // [slot][n_off]
     uint32_t *bkt;     // staged bucket table (kLookupStaged)
+    uint8_t *scls;     // class of every stabilizer size
+    double *sratio;    // sqrt(d_b / d_a) by classes
 };
 
-template <int KIND, uint32_t LX, int BLOCK>
+template <int KIND, uint32_t LX, int BLOCK, bool TAB = uses_ratio_table(KIND, false)>
 __device__ __forceinline__ LdsTables lds_tables(const MatvecJob &a, unsigned char *smem) {
     LdsTables L;
+    if constexpr (TAB) {
+        __shared__ __align__(8) double stab_ratio[kStabClsMax * kStabClsMax];
+        __shared__ __align__(8) uint8_t stab_cls[kStabMapBytes];
+        L.scls = stab_cls;
+        L.sratio = stab_ratio;
+    } else {
+        L.scls = nullptr;
+        L.sratio = nullptr;
+    }
     if constexpr (KIND == kOrbitTorus) {
         __shared__ uint32_t pair_table[kPairTableEntries];
         L.lut = pair_table;
@@ -163,7 +183,7 @@ __device__ __forceinline__ LdsTables lds_tables(const MatvecJob &a, unsigned cha
 }
 
 // All threads of the workgroup stage the job's tables; caller syncs.
-template <int KIND, uint32_t LX, int BLOCK>
+template <int KIND, uint32_t LX, int BLOCK, bool TAB = uses_ratio_table(KIND, false)>
 __device__ __forceinline__ void stage_tables(const MatvecJob &a, const LdsTables &L) {
     for (uint32_t t = threadIdx.x; t < a.n_terms; t += BLOCK) L.terms[t] = a.terms[t];
     if constexpr (KIND == kOrbitTorus) {
@@ -178,6 +198,48 @@ __device__ __forceinline__ void stage_tables(const MatvecJob &a, const LdsTables
     }
     if (a.search.mode == kLookupStaged)
         for (uint32_t q = threadIdx.x; q < a.search.n_bkt; q += BLOCK) L.bkt[q] = a.search.buckets[q];
+    if (TAB && a.plan.n_stab_cls) {
+        const uint32_t *cw = reinterpret_cast<const uint32_t *>(a.plan.stab_cls);
+        uint32_t *lw = reinterpret_cast<uint32_t *>(L.scls);
+        for (uint32_t q = threadIdx.x; q < kStabMapBytes / 4; q += BLOCK) lw[q] = cw[q];
+        for (uint32_t q = threadIdx.x; q < a.plan.n_stab_cls * a.plan.n_stab_cls; q += BLOCK)
+            L.sratio[q] = a.plan.stab_ratio[q];
+    }
+}
+
+// The row's part of the element normalisation: its stabilizer size, and the
+// offset of its class's row of the ratio table (kernels without the table:
+// the size).
+template <bool TAB>
+struct RowStab {
+    uint32_t st;
+    uint32_t base;
+};
+template <>
+struct RowStab<false> {
+    double st;
+};
+
+template <bool TAB>
+__device__ __forceinline__ RowStab<TAB> row_stab(const PlanDev &P, const LdsTables &L, uint32_t st) {
+    if constexpr (!TAB) {
+        return RowStab<TAB>{static_cast<double>(st)};
+    } else {
+        return RowStab<TAB>{st, P.n_stab_cls ? static_cast<uint32_t>(L.scls[st]) * P.n_stab_cls : 0u};
+    }
+}
+
+// sqrt(stab_j / stab_i), correctly rounded: read from the ratio table when
+// the kernel and the group have one, else divided and rooted (the same bits).
+template <bool TAB>
+__device__ __forceinline__ double stab_factor(const PlanDev &P, const LdsTables &L, const RowStab<TAB> &R,
+                                              uint32_t st_j) {
+    if constexpr (!TAB) {
+        return __dsqrt_rn(__ddiv_rn(static_cast<double>(st_j), R.st));
+    } else {
+        if (P.n_stab_cls) return L.sratio[R.base + L.scls[st_j]];
+        return __dsqrt_rn(__ddiv_rn(static_cast<double>(st_j), static_cast<double>(R.st)));
+    }
 }
 
 // Sum of the diagonal terms acting on r: dre + i dim_.
@@ -275,14 +337,14 @@ __device__ __forceinline__ void run_rows_ahead(const MatvecJob &a, const LdsTabl
     if (count == 0 || row >= a.dim) return;
 
     uint64_t r = 0;
-    double st_i = 1.0;
+    RowStab<uses_ratio_table(KIND, STAGED)> rs{};
     T acc[NR];
     uint32_t t = a.n_diag;
     W pr[kTorusCosetSlots] = {};   // unused by these searches
 
     auto begin_row = [&]() {
         r = a.search.reps[row];
-        st_i = static_cast<double>(a.stab[row]);
+        rs = row_stab<uses_ratio_table(KIND, STAGED)>(a.plan, L, a.stab[row]);
         double dre, dim_;
         diag_sum<CPLX>(sterm, a.n_diag, r, dre, dim_);
 #pragma unroll
@@ -344,7 +406,7 @@ __device__ __forceinline__ void run_rows_ahead(const MatvecJob &a, const LdsTabl
                 j = lookup_stab<STAGED>(a, L, p_rep, st_j);
             }
             if (j >= 0) {
-                const T c = element_value<CHI, CPLX>(sterm[p_t], r, st_j, st_i, a.plan, p_code);
+                const T c = element_value<CHI, CPLX>(sterm[p_t], r, stab_factor(a.plan, L, rs, st_j), a.plan, p_code);
 #pragma unroll
                 for (int q = 0; q < NR; ++q) accumulate(acc[q], c, x[j * a.ld + a.col + q]);
             } else {
@@ -372,8 +434,8 @@ __device__ __forceinline__ void run_rows_ahead(const MatvecJob &a, const LdsTabl
 }
 
 // Rows row0, row0 + step, ... (count of them, below dim) of one job.
-// STAGED: the job's search layout may be a bucket table staged in LDS (the
-// batched launch); the other launches never meet one.
+// STAGED: the batched launch, whose job's search layout may be a bucket table
+// staged in LDS; the other launches never meet one.
 template <typename W, int KIND, int CHI, bool CPLX, int NR, uint32_t LX, uint32_t LY, uint32_t NZ,
           bool STAGED = false>
 __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L, uint64_t row0, uint64_t step,
@@ -397,14 +459,14 @@ __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L,
     if (count == 0 || row >= a.dim) return;
 
     uint64_t r = 0;
-    double st_i = 1.0;
+    RowStab<uses_ratio_table(KIND, STAGED)> rs{};
     T acc[NR];
     uint32_t t = a.n_diag;
     W pr[kTorusCosetSlots] = {};   // p(r) for every coset (torus search)
 
     auto begin_row = [&]() {
         r = a.search.reps[row];
-        st_i = static_cast<double>(a.stab[row]);
+        rs = row_stab<uses_ratio_table(KIND, STAGED)>(a.plan, L, a.stab[row]);
         double dre, dim_;
         diag_sum<CPLX>(sterm, a.n_diag, r, dre, dim_);
 #pragma unroll
@@ -435,7 +497,7 @@ __device__ __forceinline__ void run_rows(const MatvecJob &a, const LdsTables &L,
             lookup_miss<W, KIND, CHI>(a, rep);
             continue;
         }
-        const T c = element_value<CHI, CPLX>(Tm, r, st_j, st_i, a.plan, code);
+        const T c = element_value<CHI, CPLX>(Tm, r, stab_factor(a.plan, L, rs, st_j), a.plan, code);
 #pragma unroll
         for (int q = 0; q < NR; ++q) accumulate(acc[q], c, x[j * a.ld + a.col + q]);
     }
@@ -476,12 +538,12 @@ __device__ __forceinline__ void run_rows_group(const MatvecJob &a, const LdsTabl
         const bool live = row < a.dim;
         if (!__any(live)) break;
         uint64_t r = 0;
-        double st_i = 1.0;
+        RowStab<uses_ratio_table(KIND, false)> rs{};
         V acc{};
         W pr[kTorusCosetSlots] = {};
         if (live) {
             r = a.search.reps[row];
-            st_i = static_cast<double>(a.stab[row]);
+            rs = row_stab<uses_ratio_table(KIND, false)>(a.plan, L, a.stab[row]);
             double dre, dim_;
             diag_sum<CPLX>(sterm, a.n_diag, r, dre, dim_);
             acc = diag_times<CPLX>(dre, dim_, x[row * a.ld + a.col]);
@@ -512,7 +574,7 @@ __device__ __forceinline__ void run_rows_group(const MatvecJob &a, const LdsTabl
                 uint32_t st_j = 0;
                 const int64_t j = lookup_index_stab(a.search, static_cast<uint64_t>(rep), a.stab, st_j);
                 if (j >= 0) {
-                    c = element_value<CHI, CPLX>(sterm[t], r, st_j, st_i, a.plan, code);
+                    c = element_value<CHI, CPLX>(sterm[t], r, stab_factor(a.plan, L, rs, st_j), a.plan, code);
                     xv = x[static_cast<uint64_t>(j) * a.ld + a.col];
                     present = true;
                 } else {
@@ -558,7 +620,7 @@ __device__ __forceinline__ void push_rows(const MatvecJob &a, const LdsTables &L
     uint64_t row = row0;
     for (uint32_t k = 0; k < count && row < a.dim; ++k, row += step) {
         const uint64_t r = a.search.reps[row];
-        const double st_i = static_cast<double>(a.stab[row]);
+        const auto rs = row_stab<uses_ratio_table(KIND, false)>(a.plan, L, a.stab[row]);
         T xi[NR];
 #pragma unroll
         for (int q = 0; q < NR; ++q) xi[q] = x[row * a.ld + a.col + q];
@@ -587,7 +649,7 @@ __device__ __forceinline__ void push_rows(const MatvecJob &a, const LdsTables &L
                 lookup_miss<W, KIND, CHI>(a, rep);
                 continue;
             }
-            const T v = element_value<CHI, CPLX>(Tm, r, st_j, st_i, a.plan, code);
+            const T v = element_value<CHI, CPLX>(Tm, r, stab_factor(a.plan, L, rs, st_j), a.plan, code);
 #pragma unroll
             for (int q = 0; q < NR; ++q) scatter_add(&y[static_cast<uint64_t>(j) * a.ld + a.col + q], v, xi[q]);
         }

@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(block_of(KIND)) k_store(StoreArgs s) {
     const uint64_t row = static_cast<uint64_t>(blockIdx.x) * BLOCK + threadIdx.x;
     if (row >= a.dim) return;
     const uint64_t r = a.search.reps[row];
-    const double st_i = static_cast<double>(a.stab[row]);
+    const auto rs = row_stab<uses_ratio_table(KIND, false)>(a.plan, L, a.stab[row]);
     double dre, dim_;
     diag_sum<CPLX>(L.terms, a.n_diag, r, dre, dim_);
     if constexpr (CPLX) static_cast<double2 *>(s.diag)[row] = make_double2(dre, dim_);
@@ -126,7 +126,7 @@ __global__ void __launch_bounds__(block_of(KIND)) k_store(StoreArgs s) {
             continue;
         }
         s.cols[slot] = static_cast<uint32_t>(j);
-        const T v = element_value<CHI, CPLX>(Tm, r, st_j, st_i, a.plan, code);
+        const T v = element_value<CHI, CPLX>(Tm, r, stab_factor(a.plan, L, rs, st_j), a.plan, code);
         if constexpr (CPLX) {
             static_cast<T *>(s.vals)[slot] = v;
         } else {
