@@ -156,10 +156,12 @@ def test_sector_matrix_equals_projected_full_hamiltonian(case):
     assert np.allclose(Hs, Hs.conj().T, atol=1e-13)
     # the columns of B are orthonormal and in the sector
     assert np.allclose(B.conj().T @ B, np.eye(len(reps)), atol=1e-12)
-    # stabilizer sizes match the norm of P|r>: ||P|r>||^2 = stab/|G|
+    # stabilizer sizes match the norm of P|r>: ||P|r>||^2 = stab/|G|, and
+    # each is the order of a subgroup, so it divides |G| (Lagrange)
     Pm = ref.projector(n, g)
     for r, st in zip(reps, stab):
         assert abs(np.linalg.norm(Pm[:, int(r)]) ** 2 - st / g.size) < 1e-12
+        assert g.size % int(st) == 0
 
 
 @pytest.mark.parametrize("case", _dense_cases()[:12], ids=lambda c: c[0])
