@@ -5,6 +5,7 @@ paper prints (Table 2, the four-spin example of Section 2.1), closed forms,
 invariants, full-space constructions built independently in
 ``physics_ref.py``, or a published generator test vector.
 """
+import math
 from math import comb
 
 import numpy as np
@@ -66,6 +67,20 @@ def test_enumeration_count_matches_character_formula(n):
                 g = lattice.ring_group(n, k, r, z)
                 P = oracle.Problem(_sector(n, n // 2, g, lattice.ring_bonds(n)))
                 assert oracle.count_basis(P) == ref.character_dimension(g, n // 2), (n, k, r, z)
+
+
+@pytest.mark.parametrize("dim,w", [(3, 4), (4, 6), (4, 8), (5, 5)])
+def test_enumeration_count_hypercube(dim, w):
+    """A non-abelian group with many stabilizer sizes: the hypercube's
+    automorphisms (2^dim * dim! elements), trivial and sign characters."""
+    n = 1 << dim
+    for sign in (False, True):
+        g = lattice.hypercube_group(dim, sign)
+        assert g.size == n * math.factorial(dim)
+        P = oracle.Problem(_sector(n, w, g, lattice.hypercube_bonds(dim, 1.0, 0.3)))
+        reps, stab = oracle.enumerate_basis(P)
+        assert len(reps) == ref.character_dimension(g, w), (dim, w, sign)
+        assert all(g.size % int(st) == 0 for st in stab)
 
 
 @pytest.mark.parametrize("lx,ly,w", [(3, 3, 4), (4, 3, 6), (4, 4, 8), (2, 4, 4), (4, 4, 7)])

@@ -179,6 +179,39 @@ def relabel_group(g: Group, new_of_old: Sequence[int]) -> Group:
     return Group(n, perm, g.flip.copy(), g.chi.copy())
 
 
+def hypercube_group(dim: int, sign: bool = False) -> Group:
+    """Automorphisms of the dim-dimensional hypercube graph on 2^dim sites
+    (site = a dim-bit index): XOR translations and permutations of the index
+    bits, 2^dim * dim! elements.  sign: the character is the sign of the bit
+    permutation (trivial on the translations), else 1."""
+    n = 1 << dim
+
+    def bitperm(dest):   # bit b of the index moves to bit dest[b]
+        return [sum(((s >> b) & 1) << dest[b] for b in range(dim)) for s in range(n)]
+
+    gens = [([s ^ (1 << k) for s in range(n)], 0, 1.0) for k in range(dim)]
+    swap = list(range(dim))
+    swap[0], swap[1] = 1, 0
+    gens.append((bitperm(swap), 0, -1.0 if sign else 1.0))
+    cycle = [(b + 1) % dim for b in range(dim)]
+    gens.append((bitperm(cycle), 0, 1.0 if dim % 2 == 1 else (-1.0 if sign else 1.0)))
+    return close_group(n, gens)
+
+
+def hypercube_bonds(dim: int, j1: float = 1.0, j2: float = 0.0) -> List[Tuple[int, int, float]]:
+    """Pairs of sites at Hamming distance 1 (j1) and 2 (j2) of their indices."""
+    n = 1 << dim
+    out = []
+    for a in range(n):
+        for b in range(a + 1, n):
+            d = bin(a ^ b).count("1")
+            if d == 1:
+                out.append((a, b, j1))
+            elif d == 2 and j2 != 0.0:
+                out.append((a, b, j2))
+    return out
+
+
 def ring_bonds(n: int, j1: float = 1.0, j2: float = 0.0) -> List[Tuple[int, int, float]]:
     bonds = [(i, (i + 1) % n, j1) for i in range(n)]
     if j2 != 0.0:
